@@ -1,0 +1,115 @@
+"""Seeded synthetic inputs for the phi-action workloads.
+
+This module only builds inputs: 1D finite-difference operators, coefficient
+draws and random vectors.  It holds none of the method's arithmetic and
+imports nothing from the rest of the package, so both the oracle-based tests
+and the HIP path can take their inputs from it.
+
+Operators (1D, Dirichlet, n interior points, h = 1/(n+1)):
+  * diffusion  T_n = tridiag(-1, 2, -1) / h^2   (FE-P1 with lumped mass gives
+    the same matrix, Section 4, Problem 1)
+  * advection  U_n = tridiag(-1, 1, 0) / h      (first-order upwind, backward
+    difference for a non-negative velocity)
+  * A^d = a_d T_n + b_d U_n
+
+Random draws use ``numpy.random.default_rng(seed)`` in a fixed order:
+a_1..a_d (log-uniform in [0.1, 10]), then b_1..b_d (uniform in [0, 50]),
+then v ~ N(0, 1) of length N, stored row-major with axis 0 slowest.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def fd_laplacian(n: int) -> np.ndarray:
+    """Dirichlet second-difference matrix tridiag(-1, 2, -1)/h^2, h = 1/(n+1)."""
+    h = 1.0 / (n + 1)
+    a = np.zeros((n, n))
+    idx = np.arange(n)
+    a[idx, idx] = 2.0
+    a[idx[1:], idx[:-1]] = -1.0
+    a[idx[:-1], idx[1:]] = -1.0
+    return a / (h * h)
+
+
+def fd_upwind(n: int) -> np.ndarray:
+    """First-order upwind (backward difference) matrix tridiag(-1, 1, 0)/h."""
+    h = 1.0 / (n + 1)
+    a = np.zeros((n, n))
+    idx = np.arange(n)
+    a[idx, idx] = 1.0
+    a[idx[1:], idx[:-1]] = -1.0
+    return a / h
+
+
+def adv_diff_1d(n: int, a: float, b: float) -> np.ndarray:
+    """a * diffusion + b * upwind advection, both on n interior points."""
+    return a * fd_laplacian(n) + b * fd_upwind(n)
+
+
+def draw_coefficients(rng: np.random.Generator, dim: int):
+    """Per-axis (a_d, b_d): a_d log-uniform in [0.1, 10], b_d uniform in [0, 50]."""
+    a = np.exp(rng.uniform(math.log(0.1), math.log(10.0), size=dim))
+    b = rng.uniform(0.0, 50.0, size=dim)
+    return a, b
+
+
+def random_vector(rng: np.random.Generator, N: int) -> np.ndarray:
+    return rng.standard_normal(N)
+
+
+def problem(name: str, seed: int = 0, n: int | None = None, dim: int | None = None,
+            t: float | None = None, p: int | None = None, tol: float | None = None):
+    """Build one named synthetic workload.
+
+    Returns a dict with keys: name, mats (list of n_d x n_d float64 arrays,
+    axis 0 first), t, p, tol, v (float64, length N), coef (list of (a, b)).
+
+    Names:
+      * ``laplace2d`` -- 2D, A^x = A^y = T_32, t = 0.01, p = 3, tol 1e-8
+      * ``advdiff3d`` -- 3D adv-diff, n = 128 by default, t = 1e-3, p = 3,
+        tol 1e-8, coefficients drawn from the seed
+      * ``advdiff``   -- same draw in any dim / n (small parity cases)
+      * ``heat3d_eig``-- 3D Laplacian, n = 2^r - 1, t = 1/8, p = 20,
+        tol 1e-14, v = sin(pi x) sin(pi y) sin(pi z) at the nodes
+    """
+    rng = np.random.default_rng(seed)
+    if name == "laplace2d":
+        n = 32 if n is None else n
+        dim = 2 if dim is None else dim
+        mats = [fd_laplacian(n) for _ in range(dim)]
+        coef = [(1.0, 0.0)] * dim
+        v = random_vector(rng, n ** dim)
+        t = 0.01 if t is None else t
+        p = 3 if p is None else p
+        tol = 1e-8 if tol is None else tol
+    elif name in ("advdiff3d", "advdiff"):
+        n = 128 if n is None else n
+        dim = 3 if dim is None else dim
+        a, b = draw_coefficients(rng, dim)
+        mats = [adv_diff_1d(n, float(a[d]), float(b[d])) for d in range(dim)]
+        coef = [(float(a[d]), float(b[d])) for d in range(dim)]
+        v = random_vector(rng, n ** dim)
+        t = 1e-3 if t is None else t
+        p = 3 if p is None else p
+        tol = 1e-8 if tol is None else tol
+    elif name == "heat3d_eig":
+        n = 15 if n is None else n
+        dim = 3 if dim is None else dim
+        mats = [fd_laplacian(n) for _ in range(dim)]
+        coef = [(1.0, 0.0)] * dim
+        x = np.arange(1, n + 1) / (n + 1)
+        s = np.sin(np.pi * x)
+        v = s
+        for _ in range(dim - 1):
+            v = np.multiply.outer(v, s)
+        v = np.ascontiguousarray(v).reshape(-1)
+        t = 0.125 if t is None else t
+        p = 20 if p is None else p
+        tol = 1e-14 if tol is None else tol
+    else:
+        raise ValueError(f"unknown workload {name!r}")
+    return dict(name=name, mats=mats, t=float(t), p=int(p), tol=float(tol), v=v,
+                coef=coef, n=n, dim=dim, seed=seed)
