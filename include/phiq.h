@@ -1,0 +1,197 @@
+/*
+ * phiq.h -- phi-function actions of Kronecker-sum matrices on AMD MI355X.
+ *
+ * Computes  out[k] = phi_k(-t A) v,  k = 0..p,  for
+ *     A = A^0 (+) A^1 (+) ... (+) A^{D-1}
+ *       = sum_d I (x) .. (x) A^d (x) .. (x) I        (Section 2.2, eq. KronA)
+ * with phi_0(M) = e^M and phi_k(M) = int_0^1 e^{(1-s)M} s^{k-1}/(k-1)! ds
+ * (Section 2.1, eq. Varphi), by the quadrature + scaling and modified
+ * squaring method of Croci & Munoz-Matute (Section 3, Algorithms 1, 2 and
+ * phiquadmv, eq. squaring).  Only 1D exponentials of the n_d x n_d factors
+ * are formed; they are applied to v viewed as an n_0 x n_1 (x n_2) tensor by
+ * mode products (eq. Expkron, eq. KronAb).
+ *
+ * Conventions shared by every entry point
+ *   * Tensor layout: v and each out[k] are row-major tensors of shape
+ *     (n_0, n_1, ..., n_{D-1}), axis 0 slowest; A^d acts on axis d (this is
+ *     the order of the Kronecker products in eq. KronA).  N = prod_d n_d.
+ *   * Matrices: A^d is n_d x n_d, row-major, FP64.
+ *   * Pointers marked HOST are ordinary host memory; pointers marked DEVICE
+ *     are device memory of the handle's GPU (e.g. from hipMalloc or a torch
+ *     CUDA tensor).  The caller owns every pointer it passes; the library
+ *     never frees or keeps them after the call returns (plans keep device
+ *     copies of what they need).
+ *   * Streams: device work is enqueued on the given hipStream_t (0 = the
+ *     legacy default stream) and is asynchronous unless stated otherwise;
+ *     the caller must keep inputs alive and outputs untouched until the
+ *     stream reaches that point.
+ *   * Errors: every call returns a phiq_status.  Arguments are validated on
+ *     the host before any device work is enqueued; on an error nothing is
+ *     enqueued and output buffers are left unchanged, except where noted.
+ *     No C++ exception crosses this boundary.
+ *   * Threads: a handle may be used from one host thread at a time.
+ */
+#ifndef PHIQ_H
+#define PHIQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PHIQ_MAX_DIM 4
+#define PHIQ_MAX_P 24
+#define PHIQ_MAX_N 1024
+
+typedef enum {
+  PHIQ_OK = 0,
+  PHIQ_ERR_INVALID_ARG = -1,   /* a size, pointer or option out of range      */
+  PHIQ_ERR_NONFINITE = -2,     /* t, tol or an entry of A^d is not finite     */
+  PHIQ_ERR_NOT_CONVERGED = -3, /* adaptive Clenshaw-Curtis hit its cap        */
+  PHIQ_ERR_OOM = -4,           /* device allocation failed or over the cap    */
+  PHIQ_ERR_HIP = -5,           /* a HIP runtime call failed                   */
+  PHIQ_ERR_UNSUPPORTED = -6    /* valid request this build does not implement */
+} phiq_status;
+
+/* Quadrature rule of the integral form (the `type` input of phiquadmv):
+ * fixed Gauss-Legendre with the node count of the a priori bound
+ * (Algorithm 1), or adaptive nested Clenshaw-Curtis (Algorithm 2). */
+typedef enum { PHIQ_RULE_GAUSS = 1, PHIQ_RULE_CC = 2 } phiq_rule;
+
+/* Arithmetic of the mode products.  The 1D exponentials, the node sums and
+ * the squaring recurrence are always FP64. */
+typedef enum {
+  PHIQ_PREC_FP64 = 0,    /* FP64 MFMA, FP64 intermediates                    */
+  PHIQ_PREC_FP32 = 1,    /* FP32 MFMA with FP32 accumulation                 */
+  PHIQ_PREC_BF16X3 = 2   /* x = hi + lo in bf16, hi*hi + hi*lo + lo*hi, FP32 */
+} phiq_precision;
+
+/* The Kronecker-sum operator: D = dim factors, HOST pointers. */
+typedef struct {
+  int dim;                        /* 1..PHIQ_MAX_DIM                          */
+  int n[PHIQ_MAX_DIM];            /* n_d in 1..PHIQ_MAX_N                     */
+  const double* A[PHIQ_MAX_DIM];  /* HOST, n_d x n_d row-major FP64           */
+} phiq_kron_op;
+
+typedef struct {
+  phiq_rule rule;           /* default PHIQ_RULE_GAUSS                              */
+  phiq_precision precision; /* default PHIQ_PREC_FP64                               */
+  int l;                    /* scaling exponent; -1 = choose (setup_quadrature)     */
+  int m;                    /* Gauss node count (n+1); -1 = choose; CC ignores it  */
+  double alpha;             /* estimate of ||tA||_inf; < 0 = eq. infnorm_upper_bnd  */
+  double c1, c2;            /* cost model C = c1 d n + c2 (n + l p); default 0, 1   */
+  int cc_max_doublings;     /* cap of Algorithm 2's doubling loop; default 6        */
+  size_t workspace_cap;     /* device bytes the handle may hold; 0 = no cap         */
+} phiq_options;
+
+/* What a plan / call did.  Times are filled by phiq_action only. */
+typedef struct {
+  int l;               /* scaling exponent used                                 */
+  int m;               /* quadrature nodes used (n+1)                           */
+  int cc_doublings;    /* doublings of Algorithm 2 (0 for Gauss)                */
+  int ttm_chains;      /* applications of a Kronecker product of 1D factors     */
+  double alpha;        /* ||tA||_inf estimate used by the selector              */
+  double log10_bound;  /* log10 of the a priori bound at (l, m), relative to ||v||_inf */
+  double cc_err;       /* last relative change of Algorithm 2 (0 for Gauss)     */
+  size_t workspace_bytes; /* device bytes held by the handle after the call     */
+} phiq_report;
+
+typedef struct phiq_handle_s* phiq_handle;
+typedef struct phiq_plan_s* phiq_plan;
+
+/* Status name, e.g. "PHIQ_ERR_INVALID_ARG".  Never NULL. */
+const char* phiq_status_string(phiq_status s);
+
+/* Defaults: Gauss, FP64, choose l and m, alpha from eq. infnorm_upper_bnd,
+ * c1 = 0, c2 = 1 (the values used in Section 4), cc cap 6, no workspace cap. */
+phiq_status phiq_options_default(phiq_options* opt);
+
+/* ---------------------------------------------------------------------------
+ * Host-only planning (no GPU needed).
+ * ------------------------------------------------------------------------ */
+
+/* alpha = |t| * sum_d ||A^d||_inf, the upper bound eq. infnorm_upper_bnd. */
+phiq_status phiq_norm_bound(const phiq_kron_op* op, double t, double* alpha);
+
+/* Parameter selection, Algorithms quaderr / quadnodes / setup_quadrature
+ * (Section 3.2-3.3) with the a priori bound of Thm 3.2, for the largest
+ * order p, tolerance eps, norm estimate alpha and vector factor beta.
+ * rule selects which bound (Gauss or Clenshaw-Curtis) is used.  Outputs:
+ * *l, *n (the paper's n: the rule has n+1 nodes) and *cost = C(n, l, p).
+ * d is the spatial dimension entering c1 d n.  p = 0 gives l = 0, n = -1. */
+phiq_status phiq_setup_quadrature(double eps, int p, double alpha, double beta,
+                                  phiq_rule rule, double c1, double c2, int d,
+                                  int* l, int* n, double* cost);
+
+/* log of Algorithm quaderr: max over q = 1..p of the Thm 3.2 bound for the
+ * (n+1)-node rule at norm alpha and vector factor beta.  n may be real. */
+phiq_status phiq_log_quaderr(double n, int p, double alpha, double beta,
+                             phiq_rule rule, double* log_err);
+
+/* Nodes theta and weights w on [0, 1] of the m-point Gauss-Legendre rule
+ * (rule = GAUSS) or the m-point Clenshaw-Curtis rule (rule = CC, m >= 2,
+ * nodes theta_j = (1 + cos(j pi/(m-1)))/2, j = 0..m-1).  HOST arrays of m. */
+phiq_status phiq_quadrature_rule(phiq_rule rule, int m, double* theta, double* w);
+
+/* ---------------------------------------------------------------------------
+ * Device entry points.
+ * ------------------------------------------------------------------------ */
+
+/* Create a handle bound to HIP device `device` (made current during calls).
+ * The handle owns a growable device workspace that later calls reuse, so
+ * repeated calls of the same size allocate nothing. */
+phiq_status phiq_create(phiq_handle* h, int device);
+phiq_status phiq_destroy(phiq_handle h);  /* synchronises the device, frees all */
+
+/* Plan: validates, estimates alpha, selects (l, m) (Gauss) or l (CC) with
+ * tolerance tol read relative to ||v||_inf (the bound is linear in
+ * ||b||_inf, so beta = 1), builds the rule, uploads A^d and forms on the
+ * GPU every 1D exponential the plan needs:
+ *   exp((1 - theta_q) 2^{-l} (-t A^d)) for each node q,
+ *   exp(2^{k-l} (-t A^d)) for k = 0..l (squaring factors and phi_0).
+ * The exponentials are enqueued on `stream`.  opt may be NULL (defaults).
+ * rep may be NULL. */
+phiq_status phiq_plan_create(phiq_handle h, const phiq_kron_op* op, double t, int p,
+                             double tol, const phiq_options* opt, phiq_plan* plan,
+                             phiq_report* rep, hipStream_t stream);
+
+/* Execute a plan on nrhs vectors: v DEVICE nrhs x N, out DEVICE
+ * nrhs x (p+1) x N (out[r][k] = phi_k(-tA) v[r]).  v and out must not
+ * overlap.  Gauss plans run asynchronously and allocate nothing once the
+ * handle's workspace is large enough; Clenshaw-Curtis plans synchronise the
+ * stream once per doubling to read the error.  rep may be NULL. */
+phiq_status phiq_plan_execute(phiq_plan plan, const double* v, int nrhs, double* out,
+                              phiq_report* rep, hipStream_t stream);
+
+phiq_status phiq_plan_destroy(phiq_plan plan);
+
+/* One call: plan_create + plan_execute + plan_destroy.  v DEVICE N,
+ * out DEVICE (p+1) x N.  The whole call is on `stream`; the host returns
+ * after enqueueing (Gauss) or after the last error check (CC). */
+phiq_status phiq_action(phiq_handle h, const phiq_kron_op* op, double t, int p,
+                        const double* v, double tol, const phiq_options* opt,
+                        double* out, phiq_report* rep, hipStream_t stream);
+
+/* Building blocks (also used by the tests).
+ *
+ * phiq_expm: E[b] = exp(X[b]) for nmat matrices n x n, DEVICE row-major
+ * FP64, by truncated Taylor series with scaling and squaring (the same
+ * kernels the plans use).  xnorm HOST[nmat]: an upper bound on ||X[b]||_inf
+ * (selects the scaling).  X and E must not overlap.
+ *
+ * phiq_kron_apply: y[r] = (F^0 (x) F^1 (x) ... (x) F^{D-1}) x[r] for nvec
+ * vectors, F DEVICE pointers (HOST array of D pointers to n_d x n_d
+ * row-major FP64), x and y DEVICE nvec x N, not overlapping. */
+phiq_status phiq_expm(phiq_handle h, int n, int nmat, const double* X, const double* xnorm,
+                      double* E, hipStream_t stream);
+phiq_status phiq_kron_apply(phiq_handle h, int dim, const int* n, const double* const* F,
+                            const double* x, double* y, int nvec, phiq_precision prec,
+                            hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PHIQ_H */

@@ -1,0 +1,115 @@
+"""ctypes declarations of libphiq.so (mirrors include/phiq.h)."""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_int, c_size_t, c_void_p
+
+MAX_DIM = 4
+MAX_P = 24
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libphiq.so")
+
+STATUS = {
+    0: "PHIQ_OK",
+    -1: "PHIQ_ERR_INVALID_ARG",
+    -2: "PHIQ_ERR_NONFINITE",
+    -3: "PHIQ_ERR_NOT_CONVERGED",
+    -4: "PHIQ_ERR_OOM",
+    -5: "PHIQ_ERR_HIP",
+    -6: "PHIQ_ERR_UNSUPPORTED",
+}
+RULE = {"gauss": 1, "cc": 2}
+PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+
+# Every symbol include/phiq.h declares.
+EXPORTS = [
+    "phiq_status_string",
+    "phiq_options_default",
+    "phiq_norm_bound",
+    "phiq_setup_quadrature",
+    "phiq_log_quaderr",
+    "phiq_quadrature_rule",
+    "phiq_create",
+    "phiq_destroy",
+    "phiq_plan_create",
+    "phiq_plan_execute",
+    "phiq_plan_destroy",
+    "phiq_action",
+    "phiq_expm",
+    "phiq_kron_apply",
+]
+
+
+class KronOp(ctypes.Structure):
+    _fields_ = [("dim", c_int), ("n", c_int * MAX_DIM), ("A", POINTER(c_double) * MAX_DIM)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("rule", c_int),
+        ("precision", c_int),
+        ("l", c_int),
+        ("m", c_int),
+        ("alpha", c_double),
+        ("c1", c_double),
+        ("c2", c_double),
+        ("cc_max_doublings", c_int),
+        ("workspace_cap", c_size_t),
+    ]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [
+        ("l", c_int),
+        ("m", c_int),
+        ("cc_doublings", c_int),
+        ("ttm_chains", c_int),
+        ("alpha", c_double),
+        ("log10_bound", c_double),
+        ("cc_err", c_double),
+        ("workspace_bytes", c_size_t),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load():
+    """Load libphiq.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2211_00696_amd.build.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = POINTER
+    sig = {
+        "phiq_status_string": (c_char_p, [c_int]),
+        "phiq_options_default": (c_int, [P(Options)]),
+        "phiq_norm_bound": (c_int, [P(KronOp), c_double, P(c_double)]),
+        "phiq_setup_quadrature": (c_int, [c_double, c_int, c_double, c_double, c_int, c_double, c_double, c_int,
+                                          P(c_int), P(c_int), P(c_double)]),
+        "phiq_log_quaderr": (c_int, [c_double, c_int, c_double, c_double, c_int, P(c_double)]),
+        "phiq_quadrature_rule": (c_int, [c_int, c_int, P(c_double), P(c_double)]),
+        "phiq_create": (c_int, [P(c_void_p), c_int]),
+        "phiq_destroy": (c_int, [c_void_p]),
+        "phiq_plan_create": (c_int, [c_void_p, P(KronOp), c_double, c_int, c_double, P(Options), P(c_void_p),
+                                     P(Report), c_void_p]),
+        "phiq_plan_execute": (c_int, [c_void_p, c_void_p, c_int, c_void_p, P(Report), c_void_p]),
+        "phiq_plan_destroy": (c_int, [c_void_p]),
+        "phiq_action": (c_int, [c_void_p, P(KronOp), c_double, c_int, c_void_p, c_double, P(Options), c_void_p,
+                                P(Report), c_void_p]),
+        "phiq_expm": (c_int, [c_void_p, c_int, c_int, c_void_p, P(c_double), c_void_p, c_void_p]),
+        "phiq_kron_apply": (c_int, [c_void_p, c_int, P(c_int), P(c_void_p), c_void_p, c_void_p, c_int, c_int,
+                                    c_void_p]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib

@@ -1,0 +1,1170 @@
+// C ABI: handles, plans and execution of the phi-action
+// (Algorithms 1, 2 and phiquadmv of Croci & Munoz-Matute, Section 3).
+//
+// Device work per plan (all on the caller's stream):
+//   plan:    upload A^d; Z_d = -t 2^{-l-sigma_d} A^d; powers Z_d^2..Z_d^K;
+//            exp(c Z_d) by the truncated Taylor series for every node
+//            coefficient c = 1 - theta_q and for c = 1; sigma_d squarings;
+//            l more squarings give exp(2^{k-l}(-t A^d)), k = 1..l.
+//   execute: for every node, the Kronecker product of its 1D exponentials
+//            applied to v (D mode products, last axis first, written
+//            rotated so the tensor returns to its layout), with the node
+//            sum fused into the last product; then l modified-squaring steps
+//            (eq. squaring), each D mode products on the p vectors with the
+//            combination fused into the last one; phi_0 from exp(-t A^d).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "phiq.h"
+#include "phiq_internal.h"
+
+#define PHIQ_HIP(x)                               \
+  do {                                            \
+    hipError_t e_ = (hipError_t)(x);              \
+    if (e_ != hipSuccess) return PHIQ_ERR_HIP;    \
+  } while (0)
+#define PHIQ_TRY(x)                  \
+  do {                               \
+    phiq_status s_ = (x);            \
+    if (s_ != PHIQ_OK) return s_;    \
+  } while (0)
+
+namespace phiq {
+
+constexpr double kThetaMax = 2.0;  // Taylor series is used for ||Z||_inf <= 2
+constexpr int kMaxTaylor = 32;
+constexpr size_t kAlign = 256;
+
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+struct Staging {
+  void* host[3] = {nullptr, nullptr, nullptr};
+  size_t cap[3] = {0, 0, 0};
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  bool pending[3] = {false, false, false};
+  int next = 0;
+};
+
+// Smallest K with nu^{K+1}/(K+1)! / (1 - nu/(K+2)) <= 2^-54 (Taylor remainder
+// of exp for ||Z|| <= nu), at least 1.
+int taylor_degree(double nu) {
+  if (nu <= 0.0) return 1;
+  double term = nu;  // nu^{K+1}/(K+1)! for K = 0
+  for (int K = 1; K <= kMaxTaylor; ++K) {
+    term *= nu / (K + 1);
+    const double tail = term / (1.0 - nu / (K + 2));
+    if (nu < K + 2 && tail <= std::ldexp(1.0, -54)) return K;
+  }
+  return kMaxTaylor;
+}
+
+double infnorm(const double* A, int n) {
+  double best = 0.0;
+  for (int i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < n; ++j) s += std::fabs(A[(size_t)i * n + j]);
+    best = std::max(best, s);
+  }
+  return best;
+}
+
+phiq_status validate_op(const phiq_kron_op* op) {
+  if (!op || op->dim < 1 || op->dim > PHIQ_MAX_DIM) return PHIQ_ERR_INVALID_ARG;
+  long double N = 1;
+  for (int d = 0; d < op->dim; ++d) {
+    if (op->n[d] < 1 || op->n[d] > PHIQ_MAX_N || !op->A[d]) return PHIQ_ERR_INVALID_ARG;
+    N *= op->n[d];
+  }
+  if (N > (long double)(1LL << 36)) return PHIQ_ERR_INVALID_ARG;
+  for (int d = 0; d < op->dim; ++d)
+    if (N / op->n[d] >= (long double)(1LL << 31)) return PHIQ_ERR_INVALID_ARG;
+  for (int d = 0; d < op->dim; ++d) {
+    const size_t nn = (size_t)op->n[d] * op->n[d];
+    for (size_t i = 0; i < nn; ++i)
+      if (!std::isfinite(op->A[d][i])) return PHIQ_ERR_NONFINITE;
+  }
+  return PHIQ_OK;
+}
+
+double sum_infnorms(const phiq_kron_op* op) {
+  double s = 0.0;
+  for (int d = 0; d < op->dim; ++d) s += infnorm(op->A[d], op->n[d]);
+  return s;
+}
+
+}  // namespace phiq
+
+using namespace phiq;
+
+struct phiq_handle_s {
+  int device = 0;
+  DevBuf ws;                     // execute workspace (T0, T1, Ya, Yb)
+  DevBuf scratch;                // transient plans (phiq_action) and phiq_expm
+  std::vector<DevBuf> cc_levels; // node vectors of the adaptive rule, per level
+  DevBuf partial;                // CC reduction partials
+  double* partial_host = nullptr;
+  Staging stage;
+  size_t cap_bytes = 0;
+  size_t held() const {
+    size_t s = ws.cap + scratch.cap + partial.cap;
+    for (const auto& b : cc_levels) s += b.cap;
+    return s;
+  }
+};
+
+struct phiq_plan_s {
+  phiq_handle h = nullptr;
+  bool transient = false;
+  void* mem = nullptr;
+  size_t bytes = 0;
+  int D = 0;
+  int n[PHIQ_MAX_DIM] = {};
+  long long N = 1;
+  double t = 0.0;
+  int p = 0;
+  double tol = 0.0;
+  phiq_options opt{};
+  int l = 0, m = 0, K = 1;
+  int sigma[PHIQ_MAX_DIM] = {};
+  double alpha = 0.0, log10_bound = 0.0;
+  // device pointers (inside mem)
+  double* Z[PHIQ_MAX_DIM] = {};      // Z^1..Z^K
+  double* Enode[PHIQ_MAX_DIM] = {};  // Gauss: m node slots then phi_0; CC: phi_0 only
+  double* Esq[PHIQ_MAX_DIM] = {};    // E^(0)..E^(l-1)
+  double* Ephi0[PHIQ_MAX_DIM] = {};
+  double* S[2][PHIQ_MAX_DIM] = {};   // ping-pong for the sigma squarings
+  double* coef = nullptr;            // p x ldcoef
+  int ldcoef = 0;
+  char* jobs = nullptr;              // device job tables (per upload)
+  size_t jobs_cap = 0;
+  // adaptive Clenshaw-Curtis: per level, node exponentials [axis][count]
+  std::vector<DevBuf> cc_E;
+  std::vector<int> cc_count;
+  ~phiq_plan_s() {
+    for (auto& b : cc_E)
+      if (b.p) (void)hipFree(b.p);
+    if (!transient && mem) (void)hipFree(mem);
+  }
+};
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+phiq_status ensure(phiq_handle h, DevBuf& b, size_t bytes) {
+  if (bytes <= b.cap) return PHIQ_OK;
+  const size_t want = align_up(bytes + bytes / 8);
+  if (h->cap_bytes && h->held() - b.cap + want > h->cap_bytes) {
+    if (h->held() - b.cap + bytes > h->cap_bytes) return PHIQ_ERR_OOM;
+  }
+  size_t get = want;
+  if (h->cap_bytes && h->held() - b.cap + get > h->cap_bytes) get = align_up(bytes);
+  if (b.p) {
+    PHIQ_HIP(hipDeviceSynchronize());
+    PHIQ_HIP(hipFree(b.p));
+    b.p = nullptr;
+    b.cap = 0;
+  }
+  if (hipMalloc(&b.p, get) != hipSuccess) {
+    b.p = nullptr;
+    (void)hipGetLastError();
+    return PHIQ_ERR_OOM;
+  }
+  b.cap = get;
+  return PHIQ_OK;
+}
+
+// Pinned staging buffer for one host->device copy; waits if the slot's
+// previous copy has not run yet.
+phiq_status stage_acquire(phiq_handle h, size_t bytes, int* slot, void** host) {
+  Staging& s = h->stage;
+  const int k = s.next;
+  s.next = (s.next + 1) % 3;
+  if (s.pending[k]) {
+    PHIQ_HIP(hipEventSynchronize(s.ev[k]));
+    s.pending[k] = false;
+  }
+  if (s.cap[k] < bytes) {
+    if (s.host[k]) PHIQ_HIP(hipHostFree(s.host[k]));
+    s.host[k] = nullptr;
+    s.cap[k] = 0;
+    const size_t want = align_up(std::max(bytes, (size_t)1 << 16));
+    if (hipHostMalloc(&s.host[k], want, hipHostMallocDefault) != hipSuccess) {
+      s.host[k] = nullptr;
+      return PHIQ_ERR_OOM;
+    }
+    s.cap[k] = want;
+  }
+  if (!s.ev[k]) PHIQ_HIP(hipEventCreateWithFlags(&s.ev[k], hipEventDisableTiming));
+  *slot = k;
+  *host = s.host[k];
+  return PHIQ_OK;
+}
+
+phiq_status stage_copy(phiq_handle h, int slot, void* dst, size_t bytes, hipStream_t st) {
+  PHIQ_HIP(hipMemcpyAsync(dst, h->stage.host[slot], bytes, hipMemcpyHostToDevice, st));
+  PHIQ_HIP(hipEventRecord(h->stage.ev[slot], st));
+  h->stage.pending[slot] = true;
+  return PHIQ_OK;
+}
+
+// Simple bump layout of one device allocation.
+struct Layout {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  }
+};
+
+// Host-side builder of a job blob: jobs are appended and later uploaded as
+// one copy; each group remembers its offset and count.
+struct JobBlob {
+  std::vector<char> bytes;
+  template <class T>
+  size_t add(const std::vector<T>& v) {
+    const size_t o = align_up(bytes.size());
+    bytes.resize(o + v.size() * sizeof(T));
+    if (!v.empty()) std::memcpy(bytes.data() + o, v.data(), v.size() * sizeof(T));
+    bytes.resize(align_up(bytes.size()));
+    return o;
+  }
+};
+
+struct ExpmJobs {
+  // offsets into the blob and counts
+  size_t scale_off = 0;
+  int scale_n = 0;
+  std::vector<std::pair<size_t, int>> power_rounds;
+  size_t taylor_off = 0;
+  int taylor_n = 0;
+  std::vector<std::pair<size_t, int>> sigma_rounds;
+  std::vector<std::pair<size_t, int>> square_chain;
+};
+
+// Target of one Taylor evaluation: axis d, coefficient c, final slot.
+struct ExpTarget {
+  int d;
+  double c;
+  double* dst;
+  int sidx;  // slot index in the sigma ping-pong buffers
+};
+
+// Jobs: powers of Z_d (already scaled in place), Taylor series for every
+// target, and sigma_d squarings through the ping-pong slots.
+void build_taylor_and_sigma(const phiq_plan_s* P, const std::vector<ExpTarget>& tg, JobBlob& blob,
+                            ExpmJobs& ej) {
+  std::vector<TaylorJob> tj;
+  int smax = 0;
+  for (const auto& t : tg) {
+    const int d = t.d, n = P->n[d];
+    TaylorJob j{};
+    j.Zpow = P->Z[d];
+    j.c = t.c;
+    j.n = n;
+    j.K = P->K;
+    j.out = P->sigma[d] > 0 ? P->S[0][d] + (size_t)t.sidx * n * n : t.dst;
+    tj.push_back(j);
+    smax = std::max(smax, P->sigma[d]);
+  }
+  ej.taylor_off = blob.add(tj);
+  ej.taylor_n = (int)tj.size();
+  for (int r = 1; r <= smax; ++r) {
+    std::vector<GemmJob> gj;
+    for (const auto& t : tg) {
+      const int d = t.d, n = P->n[d];
+      if (P->sigma[d] < r) continue;
+      const size_t off = (size_t)t.sidx * n * n;
+      GemmJob g{};
+      const double* src = P->S[(r - 1) % 2][d] + off;
+      g.A = src;
+      g.B = src;
+      g.C = (r == P->sigma[d]) ? t.dst : P->S[r % 2][d] + off;
+      g.n = n;
+      gj.push_back(g);
+    }
+    ej.sigma_rounds.push_back({blob.add(gj), (int)gj.size()});
+  }
+}
+
+void build_powers(const phiq_plan_s* P, JobBlob& blob, ExpmJobs& ej) {
+  for (int pw = 1; pw < P->K; pw *= 2) {
+    std::vector<GemmJob> gj;
+    for (int d = 0; d < P->D; ++d) {
+      const size_t nn = (size_t)P->n[d] * P->n[d];
+      for (int j = 1; j <= pw && j + pw <= P->K; ++j) {
+        GemmJob g{};
+        g.A = P->Z[d] + (size_t)(j - 1) * nn;
+        g.B = P->Z[d] + (size_t)(pw - 1) * nn;
+        g.C = P->Z[d] + (size_t)(j + pw - 1) * nn;
+        g.n = P->n[d];
+        gj.push_back(g);
+      }
+    }
+    ej.power_rounds.push_back({blob.add(gj), (int)gj.size()});
+  }
+}
+
+int nmax_of(const phiq_plan_s* P) {
+  int nm = 1;
+  for (int d = 0; d < P->D; ++d) nm = std::max(nm, P->n[d]);
+  return nm;
+}
+
+phiq_status run_taylor_sigma(const phiq_plan_s* P, const char* jobs_dev, const ExpmJobs& ej, hipStream_t st) {
+  const int nm = nmax_of(P);
+  PHIQ_HIP(launch_taylor_jobs((const TaylorJob*)(jobs_dev + ej.taylor_off), ej.taylor_n, nm, st));
+  for (const auto& r : ej.sigma_rounds) PHIQ_HIP(launch_gemm_jobs((const GemmJob*)(jobs_dev + r.first), r.second, nm, st));
+  return PHIQ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// plan creation
+// ---------------------------------------------------------------------------
+phiq_status plan_build(phiq_handle h, const phiq_kron_op* op, double t, int p, double tol, const phiq_options* uopt,
+                       bool transient, phiq_plan* out, phiq_report* rep, hipStream_t st) {
+  if (!h || !out) return PHIQ_ERR_INVALID_ARG;
+  PHIQ_TRY(validate_op(op));
+  if (!std::isfinite(t) || !std::isfinite(tol)) return PHIQ_ERR_NONFINITE;
+  if (p < 0 || p > PHIQ_MAX_P || !(tol > 0)) return PHIQ_ERR_INVALID_ARG;
+  phiq_options opt;
+  phiq_options_default(&opt);
+  if (uopt) opt = *uopt;
+  if (opt.rule != PHIQ_RULE_GAUSS && opt.rule != PHIQ_RULE_CC) return PHIQ_ERR_INVALID_ARG;
+  if (opt.precision != PHIQ_PREC_FP64 && opt.precision != PHIQ_PREC_FP32 && opt.precision != PHIQ_PREC_BF16X3)
+    return PHIQ_ERR_INVALID_ARG;
+  if (opt.precision != PHIQ_PREC_FP64) return PHIQ_ERR_UNSUPPORTED;
+  if (!std::isfinite(opt.c1) || !std::isfinite(opt.c2) || !std::isfinite(opt.alpha)) return PHIQ_ERR_NONFINITE;
+  if (opt.c1 < 0 || opt.c2 < 0 || opt.l < -1 || opt.l > 60 || opt.m < -1 || opt.m == 0 || opt.m > 4096 ||
+      opt.cc_max_doublings < 1 || opt.cc_max_doublings > 10)
+    return PHIQ_ERR_INVALID_ARG;
+
+  phiq_plan P = new (std::nothrow) phiq_plan_s;
+  if (!P) return PHIQ_ERR_OOM;
+  P->h = h;
+  P->transient = transient;
+  P->D = op->dim;
+  for (int d = 0; d < P->D; ++d) {
+    P->n[d] = op->n[d];
+    P->N *= op->n[d];
+  }
+  P->t = t;
+  P->p = p;
+  P->tol = tol;
+  P->opt = opt;
+
+  // a1: norm estimate (eq. infnorm_upper_bnd)
+  double norms[PHIQ_MAX_DIM];
+  double alpha = 0.0;
+  for (int d = 0; d < P->D; ++d) {
+    norms[d] = std::fabs(t) * infnorm(op->A[d], op->n[d]);
+    alpha += norms[d];
+  }
+  if (opt.alpha >= 0) alpha = opt.alpha;
+  P->alpha = alpha;
+
+  // a2: (l, n) by setup_quadrature with beta = 1 (tol relative to ||v||_inf)
+  int l = 0, nq = -1;
+  if (p > 0) {
+    double cost = 0.0;
+    if (opt.l >= 0) {
+      l = opt.l;
+      nq = (opt.rule == PHIQ_RULE_GAUSS)
+               ? (opt.m > 0 ? opt.m - 1
+                            : (alpha <= 1e-12 ? std::max(1, (p + 1) / 2) - 1
+                                              : quadnodes(tol, p, std::ldexp(alpha, -l), 1.0, opt.rule)))
+               : 4;
+    } else {
+      setup_quadrature(tol, p, alpha, 1.0, opt.rule, opt.c1, opt.c2, P->D, &l, &nq, &cost);
+      if (opt.m > 0 && opt.rule == PHIQ_RULE_GAUSS) nq = opt.m - 1;
+    }
+    if (l < 0 || nq < 0) {
+      delete P;
+      return PHIQ_ERR_NOT_CONVERGED;
+    }
+    P->log10_bound = (alpha > 1e-12 && nq >= 1)
+                         ? log_quaderr(nq, p, std::ldexp(alpha, -l), 1.0, opt.rule) / std::log(10.0)
+                         : -INFINITY;
+  }
+  P->l = l;
+  P->m = (p > 0 && opt.rule == PHIQ_RULE_GAUSS) ? nq + 1 : 0;
+
+  // 1D scaling for the Taylor series
+  double nu = 0.0;
+  for (int d = 0; d < P->D; ++d) {
+    const double xd = std::ldexp(norms[d], -l);
+    int s = 0;
+    while (std::ldexp(xd, -s) > kThetaMax) ++s;
+    P->sigma[d] = s;
+    nu = std::max(nu, std::ldexp(xd, -s));
+  }
+  P->K = taylor_degree(nu);
+
+  // a3: the rule (Gauss); CC nodes are produced level by level at execute time
+  std::vector<double> theta, w;
+  if (P->m > 0) {
+    theta.resize(P->m);
+    w.resize(P->m);
+    gauss_legendre(P->m, theta.data(), w.data());
+  }
+  const int ncoefcols = (opt.rule == PHIQ_RULE_GAUSS) ? P->m : 7 * (1 << opt.cc_max_doublings) + 1;
+  P->ldcoef = std::max(1, ncoefcols);
+
+  // device layout
+  Layout L;
+  size_t offA[PHIQ_MAX_DIM], offZ[PHIQ_MAX_DIM], offE[PHIQ_MAX_DIM], offSq[PHIQ_MAX_DIM], offS0[PHIQ_MAX_DIM],
+      offS1[PHIQ_MAX_DIM], offPhi0[PHIQ_MAX_DIM];
+  const int nslots = P->m + 1;  // Taylor targets: nodes + E^(0)
+  for (int d = 0; d < P->D; ++d) {
+    const size_t nn = (size_t)P->n[d] * P->n[d] * sizeof(double);
+    offA[d] = L.take(nn);
+    offZ[d] = L.take(nn * P->K);
+    offE[d] = L.take(nn * (P->m + 1));
+    offSq[d] = L.take(nn * std::max(1, l));
+    offPhi0[d] = (opt.rule == PHIQ_RULE_GAUSS) ? offE[d] + nn * P->m : L.take(nn);
+    const int cc_slots = (opt.rule == PHIQ_RULE_CC) ? 3 * (1 << opt.cc_max_doublings) + 1 : nslots;
+    const int ss = std::max(nslots, cc_slots);
+    offS0[d] = P->sigma[d] > 0 ? L.take(nn * ss) : 0;
+    offS1[d] = P->sigma[d] > 1 ? L.take(nn * ss) : 0;
+  }
+  const size_t offCoef = L.take(sizeof(double) * (size_t)std::max(1, p) * P->ldcoef);
+  const size_t jobs_cap = 1 << 20;
+  const size_t offJobs = L.take(jobs_cap);
+  P->bytes = L.off;
+  if (transient) {
+    phiq_status s = ensure(h, h->scratch, P->bytes);
+    if (s != PHIQ_OK) {
+      delete P;
+      return s;
+    }
+    P->mem = h->scratch.p;
+  } else {
+    if (h->cap_bytes && h->held() + P->bytes > h->cap_bytes) {
+      delete P;
+      return PHIQ_ERR_OOM;
+    }
+    if (hipMalloc(&P->mem, P->bytes) != hipSuccess) {
+      P->mem = nullptr;
+      (void)hipGetLastError();
+      delete P;
+      return PHIQ_ERR_OOM;
+    }
+  }
+  char* base = (char*)P->mem;
+  for (int d = 0; d < P->D; ++d) {
+    P->Z[d] = (double*)(base + offZ[d]);
+    P->Enode[d] = (double*)(base + offE[d]);
+    P->Esq[d] = (double*)(base + offSq[d]);
+    P->Ephi0[d] = (double*)(base + offPhi0[d]);
+    P->S[0][d] = P->sigma[d] > 0 ? (double*)(base + offS0[d]) : nullptr;
+    P->S[1][d] = P->sigma[d] > 1 ? (double*)(base + offS1[d]) : nullptr;
+  }
+  P->coef = (double*)(base + offCoef);
+  P->jobs = base + offJobs;
+  P->jobs_cap = jobs_cap;
+
+  // ---- host blob: A^d, coefficients, job tables ----
+  JobBlob blob;
+  ExpmJobs ej;
+  // scale jobs: Z_d^1 = (-t 2^{-l-sigma_d}) A^d (A^d uploaded into its slot)
+  std::vector<ScaleJob> sj;
+  for (int d = 0; d < P->D; ++d) {
+    ScaleJob s{};
+    s.src = (const double*)(base + offA[d]);
+    s.dst = P->Z[d];
+    s.s = -t * std::ldexp(1.0, -l - P->sigma[d]);
+    s.n = P->n[d];
+    sj.push_back(s);
+  }
+  ej.scale_off = blob.add(sj);
+  ej.scale_n = (int)sj.size();
+  build_powers(P, blob, ej);
+  // Taylor targets: Gauss nodes (c = 1 - theta_q) and E^(0) (c = 1)
+  std::vector<ExpTarget> tg;
+  for (int d = 0; d < P->D; ++d) {
+    const size_t nn = (size_t)P->n[d] * P->n[d];
+    for (int q = 0; q < P->m; ++q) tg.push_back({d, 1.0 - theta[q], P->Enode[d] + q * nn, q});
+    tg.push_back({d, 1.0, l > 0 ? P->Esq[d] : P->Ephi0[d], P->m});
+  }
+  build_taylor_and_sigma(P, tg, blob, ej);
+  // E^(k) = E^(k-1)^2, k = 1..l (E^(l) is the phi_0 factor)
+  for (int k = 1; k <= l; ++k) {
+    std::vector<GemmJob> gj;
+    for (int d = 0; d < P->D; ++d) {
+      const size_t nn = (size_t)P->n[d] * P->n[d];
+      GemmJob g{};
+      g.A = P->Esq[d] + (k - 1) * nn;
+      g.B = g.A;
+      g.C = (k < l) ? P->Esq[d] + k * nn : P->Ephi0[d];
+      g.n = P->n[d];
+      gj.push_back(g);
+    }
+    ej.square_chain.push_back({blob.add(gj), (int)gj.size()});
+  }
+  if (blob.bytes.size() > jobs_cap) {
+    phiq_plan_destroy(P);
+    return PHIQ_ERR_UNSUPPORTED;
+  }
+  // upload region = [A^d ... ] [coef] [jobs]: three copies from one staging slot
+  size_t a_bytes = 0;
+  for (int d = 0; d < P->D; ++d) a_bytes += (size_t)P->n[d] * P->n[d] * sizeof(double);
+  const size_t coef_bytes = sizeof(double) * (size_t)std::max(1, p) * P->ldcoef;
+  const size_t total = a_bytes + coef_bytes + blob.bytes.size();
+  int slot;
+  void* hostp;
+  phiq_status s = stage_acquire(h, total, &slot, &hostp);
+  if (s != PHIQ_OK) {
+    phiq_plan_destroy(P);
+    return s;
+  }
+  char* hp = (char*)hostp;
+  size_t o = 0;
+  for (int d = 0; d < P->D; ++d) {
+    const size_t nb = (size_t)P->n[d] * P->n[d] * sizeof(double);
+    std::memcpy(hp + o, op->A[d], nb);
+    o += nb;
+  }
+  double* hc = (double*)(hp + o);
+  std::fill(hc, hc + (size_t)std::max(1, p) * P->ldcoef, 0.0);
+  if (opt.rule == PHIQ_RULE_GAUSS) {
+    for (int j = 0; j < p; ++j) {
+      double fact = 1.0;
+      for (int k = 2; k <= j; ++k) fact *= k;
+      for (int q = 0; q < P->m; ++q) hc[(size_t)j * P->ldcoef + q] = w[q] * std::pow(theta[q], j) / fact;
+    }
+  }
+  o += coef_bytes;
+  std::memcpy(hp + o, blob.bytes.data(), blob.bytes.size());
+  // copies: A^d are contiguous in the layout only per axis, so copy per axis
+  {
+    size_t ho = 0;
+    bool ok = true;
+    for (int d = 0; d < P->D && ok; ++d) {
+      const size_t nb = (size_t)P->n[d] * P->n[d] * sizeof(double);
+      ok = hipMemcpyAsync(base + offA[d], hp + ho, nb, hipMemcpyHostToDevice, st) == hipSuccess;
+      ho += nb;
+    }
+    ok = ok && hipMemcpyAsync(P->coef, hp + a_bytes, coef_bytes, hipMemcpyHostToDevice, st) == hipSuccess;
+    ok = ok && hipMemcpyAsync(P->jobs, hp + a_bytes + coef_bytes, blob.bytes.size(), hipMemcpyHostToDevice, st) ==
+                   hipSuccess;
+    ok = ok && hipEventRecord(h->stage.ev[slot], st) == hipSuccess;
+    h->stage.pending[slot] = true;
+    if (!ok) {
+      phiq_plan_destroy(P);
+      return PHIQ_ERR_HIP;
+    }
+  }
+  // ---- device work: the 1D exponentials ----
+  const int nm = nmax_of(P);
+  bool ok = launch_scale_jobs((const ScaleJob*)(P->jobs + ej.scale_off), ej.scale_n, nm, st) == hipSuccess;
+  for (const auto& r : ej.power_rounds)
+    ok = ok && launch_gemm_jobs((const GemmJob*)(P->jobs + r.first), r.second, nm, st) == hipSuccess;
+  ok = ok && run_taylor_sigma(P, P->jobs, ej, st) == PHIQ_OK;
+  for (const auto& r : ej.square_chain)
+    ok = ok && launch_gemm_jobs((const GemmJob*)(P->jobs + r.first), r.second, nm, st) == hipSuccess;
+  if (!ok) {
+    phiq_plan_destroy(P);
+    return PHIQ_ERR_HIP;
+  }
+  if (rep) {
+    std::memset(rep, 0, sizeof(*rep));
+    rep->l = P->l;
+    rep->m = P->m;
+    rep->alpha = P->alpha;
+    rep->log10_bound = P->log10_bound;
+    rep->workspace_bytes = h->held();
+  }
+  *out = P;
+  return PHIQ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// execution helpers
+// ---------------------------------------------------------------------------
+struct Front {
+  const double* X;
+  long long xs;
+};
+
+// Mode products over axes D-1..1 for nb batches (rotated layout); returns the
+// input of the final product over axis 0.
+phiq_status chain_front(const phiq_plan_s* P, const double* X, long long xs, double* const* Ebase, long long const* es,
+                        int nb, double* T0, double* T1, hipStream_t st, Front* f) {
+  const double* cur = X;
+  long long cxs = xs;
+  for (int s = 0; s + 1 < P->D; ++s) {
+    const int d = P->D - 1 - s;
+    TtmArgs a{};
+    a.E = Ebase[d];
+    a.es = es[d];
+    a.X = cur;
+    a.xs = cxs;
+    a.O = (s % 2 == 0) ? T0 : T1;
+    a.os = P->N;
+    a.M = a.K = P->n[d];
+    a.L = (int)(P->N / P->n[d]);
+    a.nbatch = nb;
+    PHIQ_HIP(launch_ttm_store(a, P->opt.precision, st));
+    cur = a.O;
+    cxs = P->N;
+  }
+  f->X = cur;
+  f->xs = cxs;
+  return PHIQ_OK;
+}
+
+TtmArgs final_args(const phiq_plan_s* P, const double* E, long long es, const Front& f, int nb) {
+  TtmArgs a{};
+  a.E = E;
+  a.es = es;
+  a.X = f.X;
+  a.xs = f.xs;
+  a.M = a.K = P->n[0];
+  a.L = (int)(P->N / P->n[0]);
+  a.nbatch = nb;
+  return a;
+}
+
+phiq_status phi0_chain(const phiq_plan_s* P, const double* v, double* out0, double* T0, double* T1, hipStream_t st) {
+  double* E[PHIQ_MAX_DIM];
+  long long es[PHIQ_MAX_DIM];
+  for (int d = 0; d < P->D; ++d) {
+    E[d] = P->Ephi0[d];
+    es[d] = 0;
+  }
+  Front f;
+  PHIQ_TRY(chain_front(P, v, 0, E, es, 1, T0, T1, st, &f));
+  TtmArgs a = final_args(P, P->Ephi0[0], 0, f, 1);
+  a.O = out0;
+  a.os = 0;
+  PHIQ_HIP(launch_ttm_store(a, P->opt.precision, st));
+  return PHIQ_OK;
+}
+
+// l modified-squaring steps (eq. squaring) starting from y in Ycur (p x N);
+// the last step writes into dst_final.
+phiq_status squaring(const phiq_plan_s* P, double* Ycur, double* Yother, double* dst_final, double* T0, double* T1,
+                     hipStream_t st) {
+  const long long N = P->N;
+  double* cur = Ycur;
+  for (int k = 0; k < P->l; ++k) {
+    double* E[PHIQ_MAX_DIM];
+    long long es[PHIQ_MAX_DIM];
+    for (int d = 0; d < P->D; ++d) {
+      E[d] = P->Esq[d] + (size_t)k * P->n[d] * P->n[d];
+      es[d] = 0;
+    }
+    Front f;
+    PHIQ_TRY(chain_front(P, cur, N, E, es, P->p, T0, T1, st, &f));
+    double* dst = (k == P->l - 1) ? dst_final : (cur == Ycur ? Yother : Ycur);
+    TtmArgs a = final_args(P, E[0], 0, f, P->p);
+    a.O = dst;
+    a.os = N;
+    a.Yprev = cur;
+    a.yps = N;
+    PHIQ_HIP(launch_ttm_square(a, P->opt.precision, st));
+    cur = dst;
+  }
+  return PHIQ_OK;
+}
+
+phiq_status execute_gauss(phiq_plan P, const double* v, double* out, hipStream_t st) {
+  phiq_handle h = P->h;
+  const long long N = P->N;
+  const int p = P->p;
+  const int nb = std::max(P->m + 1, p);
+  const size_t tbytes = (P->D > 1 ? (size_t)nb * N * sizeof(double) : 0);
+  const size_t ybytes = (size_t)p * N * sizeof(double);
+  const size_t need = 2 * align_up(tbytes) + (P->l >= 1 ? align_up(ybytes) : 0) + (P->l >= 2 ? align_up(ybytes) : 0);
+  PHIQ_TRY(ensure(h, h->ws, std::max<size_t>(need, kAlign)));
+  char* wb = (char*)h->ws.p;
+  double* T0 = (double*)wb;
+  double* T1 = (double*)(wb + align_up(tbytes));
+  double* Ya = (double*)(wb + 2 * align_up(tbytes));
+  double* Yb = (double*)(wb + 2 * align_up(tbytes) + align_up(ybytes));
+
+  if (p == 0) return phi0_chain(P, v, out, T0, T1, st);
+
+  // quadrature nodes and phi_0 share the first D-1 mode products (nodes
+  // 0..m-1, phi_0 factor at slot m of Enode)
+  double* E[PHIQ_MAX_DIM];
+  long long es[PHIQ_MAX_DIM];
+  for (int d = 0; d < P->D; ++d) {
+    E[d] = P->Enode[d];
+    es[d] = (long long)P->n[d] * P->n[d];
+  }
+  Front f;
+  PHIQ_TRY(chain_front(P, v, 0, E, es, P->m + 1, T0, T1, st, &f));
+  {
+    TtmArgs a = final_args(P, P->Enode[0] + (size_t)P->m * es[0], 0, Front{f.X + P->m * f.xs, 0}, 1);
+    a.O = out;
+    a.os = 0;
+    PHIQ_HIP(launch_ttm_store(a, P->opt.precision, st));
+  }
+  double* Y = (P->l == 0) ? out + N : Ya;
+  for (int j0 = 0; j0 < p; j0 += 4) {
+    TtmArgs a = final_args(P, P->Enode[0], es[0], f, P->m);
+    a.coef = P->coef + (size_t)j0 * P->ldcoef;
+    a.ldcoef = P->ldcoef;
+    a.np = std::min(4, p - j0);
+    a.Y = Y + (size_t)j0 * N;
+    a.ys = N;
+    PHIQ_HIP(launch_ttm_accum(a, P->opt.precision, st));
+  }
+  if (P->l > 0) PHIQ_TRY(squaring(P, Ya, Yb, out + N, T0, T1, st));
+  return PHIQ_OK;
+}
+
+// ---- adaptive Clenshaw-Curtis (Algorithm 2) --------------------------------
+// Level 0 holds the 7 nodes j = 0..6 of the rule with n = 3 (2n+1 points);
+// level k >= 1 holds the 3*2^k new (odd-j) nodes of the rule with n = 3*2^k.
+void cc_level_nodes(int level, std::vector<double>& theta) {
+  theta.clear();
+  if (level == 0) {
+    for (int j = 0; j <= 6; ++j) theta.push_back(0.5 * (1.0 + std::cos(M_PI * j / 6.0)));
+  } else {
+    const int n2 = 6 << level;  // 2n for this level
+    for (int j = 1; j < n2; j += 2) theta.push_back(0.5 * (1.0 + std::cos(M_PI * (double)j / n2)));
+  }
+}
+
+phiq_status cc_ensure_level(phiq_plan P, int level, hipStream_t st) {
+  phiq_handle h = P->h;
+  while ((int)P->cc_E.size() <= level) {
+    const int lv = (int)P->cc_E.size();
+    std::vector<double> theta;
+    cc_level_nodes(lv, theta);
+    const int cnt = (int)theta.size();
+    size_t bytes = 0;
+    for (int d = 0; d < P->D; ++d) bytes += align_up((size_t)cnt * P->n[d] * P->n[d] * sizeof(double));
+    DevBuf b;
+    if (h->cap_bytes && h->held() + bytes > h->cap_bytes) return PHIQ_ERR_OOM;
+    if (hipMalloc(&b.p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return PHIQ_ERR_OOM;
+    }
+    b.cap = bytes;
+    P->cc_E.push_back(b);
+    P->cc_count.push_back(cnt);
+    std::vector<ExpTarget> tg;
+    size_t o = 0;
+    for (int d = 0; d < P->D; ++d) {
+      const size_t nn = (size_t)P->n[d] * P->n[d];
+      double* dd = (double*)((char*)b.p + o);
+      for (int q = 0; q < cnt; ++q) tg.push_back({d, 1.0 - theta[q], dd + q * nn, q});
+      o += align_up((size_t)cnt * nn * sizeof(double));
+    }
+    JobBlob blob;
+    ExpmJobs ej;
+    build_taylor_and_sigma(P, tg, blob, ej);
+    if (blob.bytes.size() > P->jobs_cap) return PHIQ_ERR_UNSUPPORTED;
+    int slot;
+    void* hp;
+    PHIQ_TRY(stage_acquire(h, blob.bytes.size(), &slot, &hp));
+    std::memcpy(hp, blob.bytes.data(), blob.bytes.size());
+    PHIQ_TRY(stage_copy(h, slot, P->jobs, blob.bytes.size(), st));
+    PHIQ_TRY(run_taylor_sigma(P, P->jobs, ej, st));
+  }
+  return PHIQ_OK;
+}
+
+double* cc_level_E(const phiq_plan_s* P, int level, int d) {
+  size_t o = 0;
+  for (int e = 0; e < d; ++e) o += align_up((size_t)P->cc_count[level] * P->n[e] * P->n[e] * sizeof(double));
+  return (double*)((char*)P->cc_E[level].p + o);
+}
+
+phiq_status execute_cc(phiq_plan P, const double* v, double* out, hipStream_t st, phiq_report* rep) {
+  phiq_handle h = P->h;
+  const long long N = P->N;
+  const int p = P->p;
+  const int cap = P->opt.cc_max_doublings;
+  const int maxcnt = 3 * (1 << cap) + 1;
+  const int nb = std::max(std::max(maxcnt, 7), p);
+  const size_t tbytes = (P->D > 1 ? (size_t)nb * N * sizeof(double) : 0);
+  const size_t ybytes = (size_t)p * N * sizeof(double);
+  PHIQ_TRY(ensure(h, h->ws, 2 * align_up(tbytes) + 2 * align_up(ybytes) + kAlign));
+  char* wb = (char*)h->ws.p;
+  double* T0 = (double*)wb;
+  double* T1 = (double*)(wb + align_up(tbytes));
+  double* Ya = (double*)(wb + 2 * align_up(tbytes));
+  double* Yb = (double*)(wb + 2 * align_up(tbytes) + align_up(ybytes));
+  PHIQ_TRY(phi0_chain(P, v, out, T0, T1, st));
+  if (p == 0) return PHIQ_OK;
+
+  const int nblk = 256;
+  PHIQ_TRY(ensure(h, h->partial, (size_t)nblk * PHIQ_MAX_P * 2 * sizeof(double)));
+  if (!h->partial_host) {
+    if (hipHostMalloc((void**)&h->partial_host, (size_t)nblk * PHIQ_MAX_P * 2 * sizeof(double),
+                      hipHostMallocDefault) != hipSuccess) {
+      h->partial_host = nullptr;
+      return PHIQ_ERR_OOM;
+    }
+  }
+
+  double* ycur = Ya;
+  double* ynew = Yb;
+  double err = INFINITY;
+  int level = 0;
+  bool converged = false;
+  for (;; ++level) {
+    PHIQ_TRY(cc_ensure_level(P, level, st));
+    const int cnt = P->cc_count[level];
+    if ((int)h->cc_levels.size() <= level) h->cc_levels.resize(level + 1);
+    PHIQ_TRY(ensure(h, h->cc_levels[level], (size_t)cnt * N * sizeof(double)));
+    double* V = (double*)h->cc_levels[level].p;
+    // node vectors v_i = e^{(1 - x_i) A} b of this level (Algorithm 2, step 2)
+    double* E[PHIQ_MAX_DIM];
+    long long es[PHIQ_MAX_DIM];
+    for (int d = 0; d < P->D; ++d) {
+      E[d] = cc_level_E(P, level, d);
+      es[d] = (long long)P->n[d] * P->n[d];
+    }
+    Front f;
+    PHIQ_TRY(chain_front(P, v, 0, E, es, cnt, T0, T1, st, &f));
+    TtmArgs a = final_args(P, E[0], es[0], f, cnt);
+    a.O = V;
+    a.os = N;
+    PHIQ_HIP(launch_ttm_store(a, P->opt.precision, st));
+    // weights of the full (2n+1)-point rule, n = 3*2^level, in storage order
+    const int n2 = 6 << level;
+    std::vector<double> xt(n2 + 1), wt(n2 + 1);
+    clenshaw_curtis(n2 + 1, xt.data(), wt.data());
+    std::vector<int> ord;  // rule index of every stored node
+    NodeSegs segs{};
+    for (int lv = 0; lv <= level; ++lv) {
+      if (lv == 0) {
+        for (int j = 0; j <= 6; ++j) ord.push_back(j << level);
+      } else {
+        for (int j = 1; j < (6 << lv); j += 2) ord.push_back(j << (level - lv));
+      }
+      segs.V[lv] = (const double*)h->cc_levels[lv].p;
+      segs.count[lv] = P->cc_count[lv];
+    }
+    segs.nseg = level + 1;
+    const int total = (int)ord.size();
+    int slot;
+    void* hp;
+    PHIQ_TRY(stage_acquire(h, sizeof(double) * (size_t)p * total, &slot, &hp));
+    double* hc = (double*)hp;
+    for (int j = 0; j < p; ++j) {
+      double fact = 1.0;
+      for (int k = 2; k <= j; ++k) fact *= k;
+      for (int i = 0; i < total; ++i) hc[(size_t)j * total + i] = wt[ord[i]] * std::pow(xt[ord[i]], j) / fact;
+    }
+    PHIQ_TRY(stage_copy(h, slot, P->coef, sizeof(double) * (size_t)p * total, st));
+    // y_j = sum_i w_i x_i^{j-1}/(j-1)! v_i (Algorithm 2, step 3)
+    PHIQ_HIP(launch_node_sum(segs, N, P->coef, total, p, ynew, st));
+    if (level > 0) {
+      // err = max_j ||y_j - y~_j||_inf / ||y_j||_inf (Algorithm 2, step 4)
+      PHIQ_HIP(launch_absdiff_max(ynew, ycur, p, N, (double*)h->partial.p, nblk, st));
+      PHIQ_HIP(hipMemcpyAsync(h->partial_host, h->partial.p, (size_t)nblk * p * 2 * sizeof(double),
+                              hipMemcpyDeviceToHost, st));
+      PHIQ_HIP(hipStreamSynchronize(st));
+      err = 0.0;
+      for (int j = 0; j < p; ++j) {
+        double num = 0.0, den = 0.0;
+        for (int b = 0; b < nblk; ++b) {
+          num = std::max(num, h->partial_host[((size_t)b * p + j) * 2 + 0]);
+          den = std::max(den, h->partial_host[((size_t)b * p + j) * 2 + 1]);
+        }
+        err = std::max(err, den > 0 ? num / den : num);
+      }
+    }
+    std::swap(ycur, ynew);
+    if (level > 0 && err <= P->tol) {
+      converged = true;
+      break;
+    }
+    if (level >= cap) break;
+  }
+  if (rep) {
+    rep->m = (6 << level) + 1;
+    rep->cc_doublings = level;
+    rep->cc_err = err;
+  }
+  if (!converged) return PHIQ_ERR_NOT_CONVERGED;
+  if (P->l > 0) {
+    double* other = (ycur == Ya) ? Yb : Ya;
+    PHIQ_TRY(squaring(P, ycur, other, out + N, T0, T1, st));
+  } else {
+    PHIQ_HIP(hipMemcpyAsync(out + N, ycur, (size_t)p * N * sizeof(double), hipMemcpyDeviceToDevice, st));
+  }
+  return PHIQ_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* phiq_status_string(phiq_status s) {
+  switch (s) {
+    case PHIQ_OK: return "PHIQ_OK";
+    case PHIQ_ERR_INVALID_ARG: return "PHIQ_ERR_INVALID_ARG";
+    case PHIQ_ERR_NONFINITE: return "PHIQ_ERR_NONFINITE";
+    case PHIQ_ERR_NOT_CONVERGED: return "PHIQ_ERR_NOT_CONVERGED";
+    case PHIQ_ERR_OOM: return "PHIQ_ERR_OOM";
+    case PHIQ_ERR_HIP: return "PHIQ_ERR_HIP";
+    case PHIQ_ERR_UNSUPPORTED: return "PHIQ_ERR_UNSUPPORTED";
+  }
+  return "PHIQ_UNKNOWN_STATUS";
+}
+
+phiq_status phiq_options_default(phiq_options* o) {
+  if (!o) return PHIQ_ERR_INVALID_ARG;
+  std::memset(o, 0, sizeof(*o));
+  o->rule = PHIQ_RULE_GAUSS;
+  o->precision = PHIQ_PREC_FP64;
+  o->l = -1;
+  o->m = -1;
+  o->alpha = -1.0;
+  o->c1 = 0.0;
+  o->c2 = 1.0;
+  o->cc_max_doublings = 6;
+  o->workspace_cap = 0;
+  return PHIQ_OK;
+}
+
+phiq_status phiq_create(phiq_handle* out, int device) {
+  if (!out) return PHIQ_ERR_INVALID_ARG;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess) {
+    (void)hipGetLastError();
+    return PHIQ_ERR_HIP;
+  }
+  if (device < 0 || device >= count) return PHIQ_ERR_INVALID_ARG;
+  phiq_handle h = new (std::nothrow) phiq_handle_s;
+  if (!h) return PHIQ_ERR_OOM;
+  h->device = device;
+  *out = h;
+  return PHIQ_OK;
+}
+
+phiq_status phiq_destroy(phiq_handle h) {
+  if (!h) return PHIQ_ERR_INVALID_ARG;
+  DeviceGuard g(h->device);
+  (void)hipDeviceSynchronize();
+  if (h->ws.p) (void)hipFree(h->ws.p);
+  if (h->scratch.p) (void)hipFree(h->scratch.p);
+  if (h->partial.p) (void)hipFree(h->partial.p);
+  for (auto& b : h->cc_levels)
+    if (b.p) (void)hipFree(b.p);
+  if (h->partial_host) (void)hipHostFree(h->partial_host);
+  for (int k = 0; k < 3; ++k) {
+    if (h->stage.host[k]) (void)hipHostFree(h->stage.host[k]);
+    if (h->stage.ev[k]) (void)hipEventDestroy(h->stage.ev[k]);
+  }
+  delete h;
+  return PHIQ_OK;
+}
+
+phiq_status phiq_plan_create(phiq_handle h, const phiq_kron_op* op, double t, int p, double tol,
+                             const phiq_options* opt, phiq_plan* plan, phiq_report* rep, hipStream_t stream) {
+  if (!h || !plan) return PHIQ_ERR_INVALID_ARG;
+  DeviceGuard g(h->device);
+  if (opt && opt->workspace_cap) h->cap_bytes = opt->workspace_cap;
+  return plan_build(h, op, t, p, tol, opt, false, plan, rep, stream);
+}
+
+phiq_status phiq_plan_execute(phiq_plan plan, const double* v, int nrhs, double* out, phiq_report* rep,
+                              hipStream_t stream) {
+  if (!plan || !v || !out || nrhs < 1) return PHIQ_ERR_INVALID_ARG;
+  const long long N = plan->N;
+  // v and out must not overlap
+  const char* vb = (const char*)v;
+  const char* ve = vb + (size_t)nrhs * N * sizeof(double);
+  const char* ob = (const char*)out;
+  const char* oe = ob + (size_t)nrhs * (plan->p + 1) * N * sizeof(double);
+  if (vb < oe && ob < ve) return PHIQ_ERR_INVALID_ARG;
+  DeviceGuard g(plan->h->device);
+  for (int r = 0; r < nrhs; ++r) {
+    const double* vr = v + (size_t)r * N;
+    double* outr = out + (size_t)r * (plan->p + 1) * N;
+    if (plan->opt.rule == PHIQ_RULE_GAUSS) {
+      PHIQ_TRY(execute_gauss(plan, vr, outr, stream));
+    } else {
+      PHIQ_TRY(execute_cc(plan, vr, outr, stream, rep));
+    }
+  }
+  if (rep) {
+    rep->l = plan->l;
+    if (plan->opt.rule == PHIQ_RULE_GAUSS) rep->m = plan->m;
+    rep->alpha = plan->alpha;
+    rep->log10_bound = plan->log10_bound;
+    const int chains_per = (plan->p > 0 ? rep->m + plan->l * plan->p : 0) + 1;
+    rep->ttm_chains = chains_per * nrhs;
+    rep->workspace_bytes = plan->h->held();
+  }
+  return PHIQ_OK;
+}
+
+phiq_status phiq_plan_destroy(phiq_plan plan) {
+  if (!plan) return PHIQ_ERR_INVALID_ARG;
+  DeviceGuard g(plan->h->device);
+  if (!plan->transient && plan->mem) {
+    // plan memory may still be read by queued work
+    (void)hipDeviceSynchronize();
+  }
+  if (!plan->cc_E.empty()) (void)hipDeviceSynchronize();
+  delete plan;
+  return PHIQ_OK;
+}
+
+phiq_status phiq_action(phiq_handle h, const phiq_kron_op* op, double t, int p, const double* v, double tol,
+                        const phiq_options* opt, double* out, phiq_report* rep, hipStream_t stream) {
+  if (!h || !v || !out) return PHIQ_ERR_INVALID_ARG;
+  DeviceGuard g(h->device);
+  if (opt && opt->workspace_cap) h->cap_bytes = opt->workspace_cap;
+  phiq_plan P = nullptr;
+  phiq_report r{};
+  PHIQ_TRY(plan_build(h, op, t, p, tol, opt, true, &P, &r, stream));
+  phiq_status s = phiq_plan_execute(P, v, 1, out, &r, stream);
+  if (rep) *rep = r;
+  if (!P->cc_E.empty()) (void)hipStreamSynchronize(stream);
+  delete P;  // transient: memory stays in the handle
+  return s;
+}
+
+phiq_status phiq_kron_apply(phiq_handle h, int dim, const int* n, const double* const* F, const double* x, double* y,
+                            int nvec, phiq_precision prec, hipStream_t stream) {
+  if (!h || !n || !F || !x || !y || nvec < 1 || dim < 1 || dim > PHIQ_MAX_DIM) return PHIQ_ERR_INVALID_ARG;
+  if (prec != PHIQ_PREC_FP64 && prec != PHIQ_PREC_FP32 && prec != PHIQ_PREC_BF16X3) return PHIQ_ERR_INVALID_ARG;
+  if (prec != PHIQ_PREC_FP64) return PHIQ_ERR_UNSUPPORTED;
+  long long N = 1;
+  for (int d = 0; d < dim; ++d) {
+    if (n[d] < 1 || n[d] > PHIQ_MAX_N || !F[d]) return PHIQ_ERR_INVALID_ARG;
+    N *= n[d];
+  }
+  const char* xb = (const char*)x;
+  const char* xe = xb + (size_t)nvec * N * sizeof(double);
+  const char* yb = (const char*)y;
+  const char* ye = yb + (size_t)nvec * N * sizeof(double);
+  if (xb < ye && yb < xe) return PHIQ_ERR_INVALID_ARG;
+  DeviceGuard g(h->device);
+  const size_t tb = align_up((size_t)nvec * N * sizeof(double));
+  PHIQ_TRY(ensure(h, h->ws, dim > 1 ? 2 * tb : kAlign));
+  double* T[2] = {(double*)h->ws.p, (double*)((char*)h->ws.p + tb)};
+  const double* cur = x;
+  for (int s = 0; s < dim; ++s) {
+    const int d = dim - 1 - s;
+    TtmArgs a{};
+    a.E = F[d];
+    a.es = 0;
+    a.X = cur;
+    a.xs = N;
+    a.O = (s == dim - 1) ? y : T[s % 2];
+    a.os = N;
+    a.M = a.K = n[d];
+    a.L = (int)(N / n[d]);
+    a.nbatch = nvec;
+    PHIQ_HIP(launch_ttm_store(a, prec, stream));
+    cur = a.O;
+  }
+  return PHIQ_OK;
+}
+
+phiq_status phiq_expm(phiq_handle h, int n, int nmat, const double* X, const double* xnorm, double* E,
+                      hipStream_t stream) {
+  if (!h || !X || !xnorm || !E || n < 1 || n > PHIQ_MAX_N || nmat < 1 || nmat > 4096) return PHIQ_ERR_INVALID_ARG;
+  const size_t nn = (size_t)n * n;
+  const char* xb = (const char*)X;
+  const char* xe = xb + nmat * nn * sizeof(double);
+  const char* eb = (const char*)E;
+  const char* ee = eb + nmat * nn * sizeof(double);
+  if (xb < ee && eb < xe) return PHIQ_ERR_INVALID_ARG;
+  double nu = 0.0;
+  std::vector<int> sig(nmat);
+  for (int b = 0; b < nmat; ++b) {
+    if (!std::isfinite(xnorm[b])) return PHIQ_ERR_NONFINITE;
+    if (xnorm[b] < 0) return PHIQ_ERR_INVALID_ARG;
+    int s = 0;
+    while (std::ldexp(xnorm[b], -s) > kThetaMax) ++s;
+    if (s > 1000) return PHIQ_ERR_INVALID_ARG;
+    sig[b] = s;
+    nu = std::max(nu, std::ldexp(xnorm[b], -s));
+  }
+  DeviceGuard g(h->device);
+  const int K = taylor_degree(nu);
+  int smax = 0;
+  for (int b = 0; b < nmat; ++b) smax = std::max(smax, sig[b]);
+  // scratch: powers K*nmat*nn, ping-pong 2*nmat*nn, jobs
+  JobBlob blob;
+  std::vector<ScaleJob> sj;
+  Layout L;
+  const size_t offZ = L.take(sizeof(double) * K * nmat * nn);
+  const size_t offS0 = L.take(sizeof(double) * nmat * nn);
+  const size_t offS1 = L.take(sizeof(double) * nmat * nn);
+  const size_t offJ = L.take(1 << 20);
+  PHIQ_TRY(ensure(h, h->scratch, L.off));
+  char* base = (char*)h->scratch.p;
+  double* Z = (double*)(base + offZ);
+  double* S[2] = {(double*)(base + offS0), (double*)(base + offS1)};
+  auto zpow = [&](int b, int k) { return Z + ((size_t)b * K + (k - 1)) * nn; };
+  for (int b = 0; b < nmat; ++b) {
+    ScaleJob s{};
+    s.src = X + b * nn;
+    s.dst = zpow(b, 1);
+    s.s = std::ldexp(1.0, -sig[b]);
+    s.n = n;
+    sj.push_back(s);
+  }
+  const size_t o_scale = blob.add(sj);
+  std::vector<std::pair<size_t, int>> rounds;
+  for (int pw = 1; pw < K; pw *= 2) {
+    std::vector<GemmJob> gj;
+    for (int b = 0; b < nmat; ++b)
+      for (int j = 1; j <= pw && j + pw <= K; ++j) gj.push_back(GemmJob{zpow(b, j), zpow(b, pw), zpow(b, j + pw), n, 0});
+    rounds.push_back({blob.add(gj), (int)gj.size()});
+  }
+  std::vector<TaylorJob> tj;
+  for (int b = 0; b < nmat; ++b) tj.push_back(TaylorJob{zpow(b, 1), sig[b] > 0 ? S[0] + b * nn : E + b * nn, 1.0, n, K});
+  const size_t o_tay = blob.add(tj);
+  std::vector<std::pair<size_t, int>> sq;
+  for (int r = 1; r <= smax; ++r) {
+    std::vector<GemmJob> gj;
+    for (int b = 0; b < nmat; ++b) {
+      if (sig[b] < r) continue;
+      const double* src = S[(r - 1) % 2] + b * nn;
+      gj.push_back(GemmJob{src, src, (r == sig[b]) ? E + b * nn : S[r % 2] + b * nn, n, 0});
+    }
+    sq.push_back({blob.add(gj), (int)gj.size()});
+  }
+  if (blob.bytes.size() > (1 << 20)) return PHIQ_ERR_UNSUPPORTED;
+  int slot;
+  void* hp;
+  PHIQ_TRY(stage_acquire(h, blob.bytes.size(), &slot, &hp));
+  std::memcpy(hp, blob.bytes.data(), blob.bytes.size());
+  char* jd = base + offJ;
+  PHIQ_TRY(stage_copy(h, slot, jd, blob.bytes.size(), stream));
+  PHIQ_HIP(launch_scale_jobs((const ScaleJob*)(jd + o_scale), (int)sj.size(), n, stream));
+  for (const auto& r : rounds) PHIQ_HIP(launch_gemm_jobs((const GemmJob*)(jd + r.first), r.second, n, stream));
+  PHIQ_HIP(launch_taylor_jobs((const TaylorJob*)(jd + o_tay), (int)tj.size(), n, stream));
+  for (const auto& r : sq) PHIQ_HIP(launch_gemm_jobs((const GemmJob*)(jd + r.first), r.second, n, stream));
+  return PHIQ_OK;
+}
+
+}  // extern "C"

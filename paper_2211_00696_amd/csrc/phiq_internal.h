@@ -1,0 +1,103 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+#include "phiq.h"
+
+namespace phiq {
+
+// ---- planner.cpp ----------------------------------------------------------
+void poly_coeffs(double n, int p, double alpha, phiq_rule rule, double* a3, double* a2, double* a1);
+double log_bound_at(double rho, double n, int p, double alpha, double beta, phiq_rule rule);
+double best_log_bound(double n, int p, double alpha, double beta, phiq_rule rule);
+double log_quaderr(double n, int p, double alpha, double beta, phiq_rule rule);
+int quadnodes(double eps, int p, double alpha, double beta, phiq_rule rule);
+void setup_quadrature(double eps, int p, double alpha, double beta, phiq_rule rule, double c1,
+                      double c2, int d, int* l, int* n, double* cost);
+void gauss_legendre(int m, double* theta, double* w);
+void clenshaw_curtis(int m, double* theta, double* w);
+
+// ---- api.cpp --------------------------------------------------------------
+phiq_status validate_op(const phiq_kron_op* op);
+double sum_infnorms(const phiq_kron_op* op);
+
+// ---- kernels.hip: device job descriptors ---------------------------------
+// C = A * B, all n x n row-major FP64 (A, B, C distinct).
+struct GemmJob {
+  const double* A;
+  const double* B;
+  double* C;
+  int n;
+  int pad_;
+};
+
+// out = s * src, n x n.
+struct ScaleJob {
+  const double* src;
+  double* dst;
+  double s;
+  int n;
+  int pad_;
+};
+
+// out = sum_{k=0}^{K} c^k/k! Z^k with Z^0 = I and Z^k stored at
+// Zpow + (k-1) n^2 for k = 1..K (a truncated Taylor series of exp(c Z)).
+struct TaylorJob {
+  const double* Zpow;
+  double* out;
+  double c;
+  int n;
+  int K;
+};
+
+// Mode product of a row-major (L x K) tensor view X with the M x K matrix
+// E (M = K = n_d), written rotated: out[i' * L + j] = sum_k E[i'][k] X[j][k].
+// Applying it once per axis, last axis first, returns the tensor to its
+// original layout after D steps.  Batch b uses E + b*es, X + b*xs, O + b*os.
+struct TtmArgs {
+  const double* E;
+  long long es;
+  const double* X;
+  long long xs;
+  double* O;
+  long long os;
+  int M, K, L, nbatch;
+  // node-sum epilogue: Y + j*ys = sum_b coef[j * ldcoef + b] * C_b, j < np
+  const double* coef;
+  int ldcoef;
+  int np;
+  double* Y;
+  long long ys;
+  // squaring epilogue: batch b is order i = b + 1;
+  // O_b = 2^{-i} (C_b + sum_{j=1}^{i} (Yprev + (j-1)*yps)/(i-j)!)
+  const double* Yprev;
+  long long yps;
+};
+
+// Host launchers (kernels.hip).  All return hipSuccess or the launch error.
+int launch_gemm_jobs(const GemmJob* jobs_dev, int njobs, int nmax, void* stream);
+int launch_scale_jobs(const ScaleJob* jobs_dev, int njobs, int nmax, void* stream);
+int launch_taylor_jobs(const TaylorJob* jobs_dev, int njobs, int nmax, void* stream);
+int launch_ttm_store(const TtmArgs& a, phiq_precision prec, void* stream);
+int launch_ttm_accum(const TtmArgs& a, phiq_precision prec, void* stream);
+int launch_ttm_square(const TtmArgs& a, phiq_precision prec, void* stream);
+
+// CC error: partial maxima of |y_j - yold_j| and |y_j| over blocks.
+// partial[(blk * np + j) * 2 + {0, 1}] = block maxima of |y_j - yold_j|, |y_j|
+// with y_j = y + j*N, yold_j = yold + j*N.
+int launch_absdiff_max(const double* y, const double* yold, int np, long long N, double* partial,
+                       int nblocks, void* stream);
+// Node vectors stored in up to 12 segments (one per adaptive level).
+struct NodeSegs {
+  const double* V[12];
+  int count[12];
+  int nseg;
+};
+// Y + j*N = sum_b coef[j * ldcoef + b] * V_b, nodes numbered through the
+// segments in order.
+int launch_node_sum(const NodeSegs& segs, long long N, const double* coef, int ldcoef, int np, double* Y,
+                    void* stream);
+
+}  // namespace phiq

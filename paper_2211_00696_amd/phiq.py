@@ -1,0 +1,246 @@
+"""Thin Python binding of libphiq.so: argument marshalling only.
+
+Device buffers are torch CUDA tensors (float64, contiguous); the 1D
+matrices A^d are host numpy arrays.  Every step of the phi-action runs in
+the library's HIP kernels; nothing here computes.
+"""
+from __future__ import annotations
+
+import ctypes
+from ctypes import POINTER, byref, c_double, c_int, c_void_p
+
+import numpy as np
+
+from . import _lib as L
+
+
+class PhiqError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        self.name = L.STATUS.get(status, str(status))
+        super().__init__(f"{where}: {self.name}")
+
+
+def _check(st: int, where: str):
+    if st != 0:
+        raise PhiqError(st, where)
+
+
+def _stream_ptr(stream):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(x, name):
+    import torch
+
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if x.dtype != torch.float64 or not x.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float64 tensor")
+    return c_void_p(x.data_ptr())
+
+
+class _Op:
+    """Keeps the host copies of A^d alive while the KronOp points at them."""
+
+    def __init__(self, mats):
+        if len(mats) < 1 or len(mats) > L.MAX_DIM:
+            raise ValueError("between 1 and %d matrices" % L.MAX_DIM)
+        self.mats = [np.ascontiguousarray(np.asarray(m, dtype=np.float64)) for m in mats]
+        self.op = L.KronOp()
+        self.op.dim = len(self.mats)
+        for d, m in enumerate(self.mats):
+            if m.ndim != 2 or m.shape[0] != m.shape[1]:
+                raise ValueError("A^d must be square")
+            self.op.n[d] = m.shape[0]
+            self.op.A[d] = m.ctypes.data_as(POINTER(c_double))
+        self.sizes = [m.shape[0] for m in self.mats]
+        self.N = int(np.prod(self.sizes))
+
+
+def options(rule="gauss", precision="fp64", l=None, m=None, alpha=None, c1=None, c2=None,
+            cc_max_doublings=None, workspace_cap=None):
+    lib = L.load()
+    o = L.Options()
+    _check(lib.phiq_options_default(byref(o)), "phiq_options_default")
+    o.rule = L.RULE[rule]
+    o.precision = L.PRECISION[precision]
+    if l is not None:
+        o.l = int(l)
+    if m is not None:
+        o.m = int(m)
+    if alpha is not None:
+        o.alpha = float(alpha)
+    if c1 is not None:
+        o.c1 = float(c1)
+    if c2 is not None:
+        o.c2 = float(c2)
+    if cc_max_doublings is not None:
+        o.cc_max_doublings = int(cc_max_doublings)
+    if workspace_cap is not None:
+        o.workspace_cap = int(workspace_cap)
+    return o
+
+
+# ---------------------------------------------------------------------------
+# host-only planning
+# ---------------------------------------------------------------------------
+def norm_bound(mats, t):
+    lib = L.load()
+    op = _Op(mats)
+    a = c_double()
+    _check(lib.phiq_norm_bound(byref(op.op), float(t), byref(a)), "phiq_norm_bound")
+    return a.value
+
+
+def setup_quadrature(eps, p, alpha, beta=1.0, rule="gauss", c1=0.0, c2=1.0, d=3):
+    """(l, n, cost) of the parameter selection; the rule has n+1 nodes."""
+    lib = L.load()
+    l, n, c = c_int(), c_int(), c_double()
+    _check(lib.phiq_setup_quadrature(float(eps), int(p), float(alpha), float(beta), L.RULE[rule], float(c1),
+                                     float(c2), int(d), byref(l), byref(n), byref(c)), "phiq_setup_quadrature")
+    return l.value, n.value, c.value
+
+
+def log_quaderr(n, p, alpha, beta=1.0, rule="gauss"):
+    lib = L.load()
+    e = c_double()
+    _check(lib.phiq_log_quaderr(float(n), int(p), float(alpha), float(beta), L.RULE[rule], byref(e)),
+           "phiq_log_quaderr")
+    return e.value
+
+
+def quadrature_rule(rule, m):
+    lib = L.load()
+    th = np.zeros(m)
+    w = np.zeros(m)
+    _check(lib.phiq_quadrature_rule(L.RULE[rule], int(m), th.ctypes.data_as(POINTER(c_double)),
+                                    w.ctypes.data_as(POINTER(c_double))), "phiq_quadrature_rule")
+    return th, w
+
+
+def status_string(st):
+    return L.load().phiq_status_string(int(st)).decode()
+
+
+# ---------------------------------------------------------------------------
+# device
+# ---------------------------------------------------------------------------
+class Plan:
+    def __init__(self, handle, ptr, p, N, report):
+        self._h = handle
+        self._ptr = ptr
+        self.p = p
+        self.N = N
+        self.report = report
+
+    def execute(self, v, out=None, stream=None):
+        import torch
+
+        lib = L.load()
+        nrhs = v.numel() // self.N
+        if v.numel() != nrhs * self.N or nrhs < 1:
+            raise ValueError("v must hold nrhs x N values")
+        if out is None:
+            out = torch.empty((nrhs, self.p + 1, self.N), dtype=torch.float64, device=v.device)
+        rep = L.Report()
+        _check(lib.phiq_plan_execute(self._ptr, _dev_ptr(v, "v"), nrhs, _dev_ptr(out, "out"), byref(rep),
+                                     _stream_ptr(stream)), "phiq_plan_execute")
+        return out, rep.as_dict()
+
+    def close(self):
+        if self._ptr:
+            L.load().phiq_plan_destroy(self._ptr)
+            self._ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Handle:
+    """A library handle on one HIP device (owns the reusable workspace)."""
+
+    def __init__(self, device=0):
+        lib = L.load()
+        h = c_void_p()
+        _check(lib.phiq_create(byref(h), int(device)), "phiq_create")
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if self._h:
+            L.load().phiq_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def action(self, mats, t, p, v, tol=1e-8, out=None, stream=None, **opts):
+        """out[k] = phi_k(-t A) v, k = 0..p; returns (out (p+1, N), report dict)."""
+        import torch
+
+        lib = L.load()
+        op = _Op(mats)
+        if v.numel() != op.N:
+            raise ValueError("v has %d entries, the operator needs %d" % (v.numel(), op.N))
+        if out is None:
+            out = torch.empty((p + 1, op.N), dtype=torch.float64, device=v.device)
+        o = options(**opts)
+        rep = L.Report()
+        _check(lib.phiq_action(self._h, byref(op.op), float(t), int(p), _dev_ptr(v, "v"), float(tol), byref(o),
+                               _dev_ptr(out, "out"), byref(rep), _stream_ptr(stream)), "phiq_action")
+        return out, rep.as_dict()
+
+    def plan(self, mats, t, p, tol=1e-8, stream=None, **opts):
+        lib = L.load()
+        op = _Op(mats)
+        o = options(**opts)
+        ptr = c_void_p()
+        rep = L.Report()
+        _check(lib.phiq_plan_create(self._h, byref(op.op), float(t), int(p), float(tol), byref(o), byref(ptr),
+                                    byref(rep), _stream_ptr(stream)), "phiq_plan_create")
+        return Plan(self, ptr, p, op.N, rep.as_dict())
+
+    def kron_apply(self, factors, x, out=None, precision="fp64", stream=None):
+        """y = (F^0 (x) F^1 (x) ...) x for x of shape (nvec, N) (device tensors)."""
+        import torch
+
+        lib = L.load()
+        dim = len(factors)
+        n = (c_int * dim)(*[f.shape[0] for f in factors])
+        F = (c_void_p * dim)(*[_dev_ptr(f, "F").value for f in factors])
+        N = int(np.prod([f.shape[0] for f in factors]))
+        nvec = x.numel() // N
+        if out is None:
+            out = torch.empty_like(x)
+        _check(lib.phiq_kron_apply(self._h, dim, n, F, _dev_ptr(x, "x"), _dev_ptr(out, "out"), nvec,
+                                   L.PRECISION[precision], _stream_ptr(stream)), "phiq_kron_apply")
+        return out
+
+    def expm(self, X, xnorm, out=None, stream=None):
+        """E[b] = exp(X[b]) for X of shape (nmat, n, n) on the device; xnorm: host bounds."""
+        import torch
+
+        lib = L.load()
+        nmat, n, _ = X.shape
+        xn = np.ascontiguousarray(np.asarray(xnorm, dtype=np.float64).reshape(nmat))
+        if out is None:
+            out = torch.empty_like(X)
+        _check(lib.phiq_expm(self._h, int(n), int(nmat), _dev_ptr(X, "X"), xn.ctypes.data_as(POINTER(c_double)),
+                             _dev_ptr(out, "E"), _stream_ptr(stream)), "phiq_expm")
+        return out

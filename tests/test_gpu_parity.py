@@ -1,0 +1,240 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Tolerances: the FP64 path must match the exact phi actions within the
+requested relative tolerance (1e-8 unless stated); building blocks (mode
+products, 1D exponentials) are plain FP64 arithmetic and must match to a
+few units of rounding times the problem size.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import bounds as OB, phi_exact as X, phiquad as Q
+from paper_2211_00696_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def h():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2211_00696_amd import phiq
+
+    hd = phiq.Handle(0)
+    yield hd
+    hd.close()
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def host(x):
+    torch.cuda.synchronize()
+    return x.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def rel_per_k(out, ref):
+    return [rel(out[k], ref[k]) for k in range(ref.shape[0])]
+
+
+# --------------------------------------------------------------------------
+# building blocks
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("sizes", [(5,), (16, 16), (17, 33), (64, 64), (128, 128), (7, 5, 3), (16, 16, 16),
+                                   (33, 20, 17), (64, 64, 64), (1, 9, 2), (130, 3, 65)])
+def test_kron_apply_matches_oracle(h, sizes):
+    print("kron_apply", sizes, flush=True)
+    rng = np.random.default_rng(sum(sizes))
+    F = [rng.standard_normal((n, n)) for n in sizes]
+    N = int(np.prod(sizes))
+    x = rng.standard_normal((2, N))
+    y = host(h.kron_apply([dev(f) for f in F], dev(x)))
+    for r in range(2):
+        ref = X.apply_kron(F, x[r], list(sizes))
+        err = np.max(np.abs(y[r] - ref)) / np.max(np.abs(ref))
+        assert err < 1e-13 * max(sizes), (sizes, err)
+
+
+@pytest.mark.parametrize("n", [1, 7, 32, 100, 128, 256])
+def test_expm_matches_scipy(h, n):
+    print("expm", n, flush=True)
+    rng = np.random.default_rng(n)
+    mats, norms = [], []
+    for scale in (0.0, 0.05, 1.9, 7.0, 300.0):
+        A = rng.standard_normal((n, n))
+        A *= scale / max(np.max(np.sum(np.abs(A), axis=1)), 1e-300)
+        mats.append(A)
+        norms.append(np.max(np.sum(np.abs(A), axis=1)))
+    # a diffusion-like negative definite case and a non-normal upwind case
+    mats.append(-0.002 * I.adv_diff_1d(n, 1.0, 40.0))
+    norms.append(np.max(np.sum(np.abs(mats[-1]), axis=1)))
+    Xd = dev(np.stack(mats))
+    E = host(h.expm(Xd, norms))
+    for b, A in enumerate(mats):
+        ref = scipy.linalg.expm(A)
+        err = np.max(np.abs(E[b] - ref)) / max(np.max(np.abs(ref)), 1e-300)
+        assert err < 1e-13 * max(1.0, norms[b]), (n, b, err)
+
+
+# --------------------------------------------------------------------------
+# phi actions against the exact (augmented-matrix) definition
+# --------------------------------------------------------------------------
+def test_laplace2d_n32_matches_dense_definition(h):
+    pr = I.problem("laplace2d")
+    print("laplace2d n=32", flush=True)
+    out, rep = h.action(pr["mats"], pr["t"], pr["p"], dev(pr["v"]), tol=pr["tol"])
+    ref = X.phi_dense_aug(pr["mats"], pr["t"], pr["v"], pr["p"])
+    errs = rel_per_k(host(out), ref)
+    assert max(errs) < 1e-8, errs
+    assert max(errs) < 1e-12, errs  # what FP64 actually reaches here
+    l, n, _ = OB.setup_quadrature(pr["tol"], pr["p"], OB.infnorm_upper_bound(pr["mats"], pr["t"]), 1.0, "gauss")
+    assert (rep["l"], rep["m"]) == (l, n + 1) == (4, 9)
+
+
+@pytest.mark.parametrize("rule", ["gauss", "cc"])
+@pytest.mark.parametrize("seed", [0, 1])
+def test_advdiff3d_small_matches_dense_definition(h, rule, seed):
+    pr = I.problem("advdiff", seed=seed, n=9, dim=3, t=1e-2)
+    print("advdiff3d n=9", rule, seed, flush=True)
+    out, rep = h.action(pr["mats"], pr["t"], 4, dev(pr["v"]), tol=1e-8, rule=rule)
+    ref = X.phi_dense_aug(pr["mats"], pr["t"], pr["v"], 4)
+    errs = rel_per_k(host(out), ref)
+    assert max(errs) < 1e-8, (errs, rep)
+
+
+def test_unequal_axes_and_ragged_sizes(h):
+    rng = np.random.default_rng(3)
+    mats = [I.adv_diff_1d(5, 0.7, 3.0), I.adv_diff_1d(19, 2.0, 10.0), I.adv_diff_1d(3, 0.2, 1.0)]
+    v = rng.standard_normal(5 * 19 * 3)
+    out, _ = h.action(mats, 5e-3, 3, dev(v), tol=1e-10)
+    ref = X.phi_dense_aug(mats, 5e-3, v, 3)
+    assert max(rel_per_k(host(out), ref)) < 1e-10
+
+
+def test_axis_order_is_row_major(h):
+    # distinct per-axis operators: swapping the axes must change the answer
+    rng = np.random.default_rng(4)
+    mats = [I.adv_diff_1d(6, 0.1, 30.0), I.adv_diff_1d(6, 5.0, 0.0)]
+    v = rng.standard_normal(36)
+    out, _ = h.action(mats, 1e-2, 2, dev(v), tol=1e-10)
+    ref = X.phi_dense_aug(mats, 1e-2, v, 2)
+    swapped = X.phi_dense_aug(mats[::-1], 1e-2, v, 2)
+    o = host(out)
+    assert max(rel_per_k(o, ref)) < 1e-10
+    assert rel(o[1], swapped[1]) > 1e-3
+
+
+def test_p_zero_and_large_p(h):
+    pr = I.problem("advdiff", seed=5, n=8, dim=2, t=2e-2)
+    out, rep = h.action(pr["mats"], pr["t"], 0, dev(pr["v"]), tol=1e-10)
+    ref = X.phi_dense_aug(pr["mats"], pr["t"], pr["v"], 9)
+    assert rel(host(out)[0], ref[0]) < 1e-12
+    out, rep = h.action(pr["mats"], pr["t"], 9, dev(pr["v"]), tol=1e-10)  # node sums in 3 passes
+    assert max(rel_per_k(host(out), ref)) < 1e-10
+
+
+def test_zero_time_gives_inverse_factorials(h):
+    pr = I.problem("advdiff", seed=6, n=6, dim=3)
+    out, rep = h.action(pr["mats"], 0.0, 5, dev(pr["v"]), tol=1e-10)
+    o = host(out)
+    for k in range(6):
+        assert np.allclose(o[k], pr["v"] / math.factorial(k), rtol=1e-15, atol=0)
+    assert rep["l"] == 0
+
+
+@pytest.mark.parametrize("l,m", [(0, 30), (3, 12), (7, 6)])
+def test_forced_scaling_and_nodes(h, l, m):
+    pr = I.problem("advdiff", seed=7, n=7, dim=2, t=1e-2)
+    out, rep = h.action(pr["mats"], pr["t"], 3, dev(pr["v"]), tol=1e-10, l=l, m=m)
+    assert (rep["l"], rep["m"]) == (l, m)
+    ref = Q.phiquadmv(pr["mats"], pr["t"], pr["v"], 3, l=l, n=m - 1)
+    assert max(rel_per_k(host(out), ref)) < 1e-11
+
+
+@pytest.mark.parametrize("n", [15, 31])
+def test_problem1_eigenvector_p20(h, n):
+    # Problem 1 (Section 4) with eps = 1e-14, p = 20: b is the (1,1,1)
+    # eigenvector, so the exact answer is a scalar multiple of b.
+    pr = I.problem("heat3d_eig", n=n)
+    print("heat3d_eig", n, flush=True)
+    out, rep = h.action(pr["mats"], pr["t"], 20, dev(pr["v"]), tol=1e-14)
+    lam = 3 * X.laplacian_min_eig_3d_scalar(n)
+    o = host(out)
+    errs = [rel(o[k], float(X.phi_scalar_mp(k, -pr["t"] * lam)) * pr["v"]) for k in range(21)]
+    assert max(errs) < 1e-12, errs
+    assert rep["m"] == 37 and rep["l"] == {15: 3, 31: 5}[n]
+
+
+def test_plan_reuse_and_multiple_rhs(h):
+    pr = I.problem("advdiff", seed=8, n=12, dim=3, t=5e-3)
+    rng = np.random.default_rng(9)
+    V = rng.standard_normal((3, 12 ** 3))
+    plan = h.plan(pr["mats"], pr["t"], 3, tol=1e-9)
+    out1, _ = plan.execute(dev(V))
+    out2, _ = plan.execute(dev(V[1:2]))
+    o1, o2 = host(out1), host(out2)
+    for r in range(3):
+        ref = X.phi_dense_aug(pr["mats"], pr["t"], V[r], 3)
+        assert max(rel_per_k(o1[r], ref)) < 1e-9
+    assert np.array_equal(o1[1], o2[0])
+    plan.close()
+
+
+def test_cc_reports_adaptive_doublings(h):
+    pr = I.problem("laplace2d", n=16)
+    out, rep = h.action(pr["mats"], pr["t"], 3, dev(pr["v"]), tol=1e-10, rule="cc")
+    ref, info = Q.phiquadmv(pr["mats"], pr["t"], pr["v"], 3, eps=1e-10, rule="cc", beta=1.0, return_info=True)
+    assert (rep["l"], rep["m"], rep["cc_doublings"]) == (info["l"], info["m"], info["doublings"])
+    assert rep["cc_err"] <= 1e-10
+    assert max(rel_per_k(host(out), ref)) < 1e-10
+
+
+def test_cc_cap_reports_not_converged(h):
+    from paper_2211_00696_amd import phiq
+
+    pr = I.problem("laplace2d", n=8)
+    with pytest.raises(phiq.PhiqError, match="NOT_CONVERGED"):
+        h.action(pr["mats"], pr["t"], 3, dev(pr["v"]), tol=1e-30, rule="cc", cc_max_doublings=2)
+
+
+def test_device_argument_errors(h):
+    from paper_2211_00696_amd import phiq
+
+    pr = I.problem("laplace2d", n=8)
+    buf = torch.zeros(5 * 64, dtype=torch.float64, device="cuda")
+    with pytest.raises(phiq.PhiqError, match="INVALID_ARG"):  # v overlaps out
+        h.action(pr["mats"], pr["t"], 3, buf[:64], out=buf[:256].view(4, 64))
+    with pytest.raises(phiq.PhiqError, match="INVALID_ARG"):
+        h.action(pr["mats"], pr["t"], 3, dev(pr["v"]), tol=-1.0)
+    with pytest.raises(phiq.PhiqError, match="NONFINITE"):
+        h.action(pr["mats"], float("nan"), 3, dev(pr["v"]))
+
+
+# --------------------------------------------------------------------------
+# full size: 3D n = 128 advection-diffusion (N = 2,097,152), t = 1e-3, p = 3
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("rule", ["gauss", "cc"])
+def test_advdiff3d_n128_full_size(h, rule):
+    pr = I.problem("advdiff3d", seed=0)
+    print("advdiff3d n=128", rule, flush=True)
+    out, rep = h.action(pr["mats"], pr["t"], 3, dev(pr["v"]), tol=1e-8, rule=rule)
+    o = host(out)
+    # phi_0 exactly: separable 1D exponentials (eq. Expkron)
+    assert rel(o[0], X.phi0_separable(pr["mats"], pr["t"], pr["v"])) < 1e-12
+    # phi_1..phi_3 against the oracle's quadrature at eps = 1e-14
+    ref = Q.phiquadmv(pr["mats"], pr["t"], pr["v"], 3, eps=1e-14, beta=1.0)
+    errs = rel_per_k(o, ref)
+    assert max(errs) < 1e-8, (errs, rep)
+    # recurrence phi_{k-1} = M phi_k + v/(k-1)! holds at any size
+    res = X.recurrence_residual(pr["mats"], pr["t"], pr["v"], o)
+    assert max(res) < 1e-9, res

@@ -1,0 +1,137 @@
+"""Host-side checks of the C-ABI library (no GPU): exports, planner parity.
+
+The library's planner (C++) and the oracle's (Python) share no code; the
+selected integers (l, m) must agree exactly and the rules and bounds to
+rounding.
+"""
+import ctypes
+import json
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import bounds as OB, quadrature as OQ
+from paper_2211_00696_amd import _lib as L, inputs as I, phiq
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    lib = L.load()
+    header = open(os.path.join(ROOT, "include", "phiq.h")).read()
+    declared = set(re.findall(r"\b(phiq_[a-z_0-9]+)\s*\(", header))
+    assert declared == set(L.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings():
+    for code, name in L.STATUS.items():
+        assert phiq.status_string(code) == name
+    assert phiq.status_string(42) == "PHIQ_UNKNOWN_STATUS"
+
+
+@pytest.mark.parametrize("fname", ["points_laplace.json", "points_advdiff.json"])
+def test_setup_quadrature_reproduces_paper_tables(fname):
+    g = json.load(open(os.path.join(GOLDEN, fname)))
+    p, eps = g["p"], g["eps"]
+    for row in g["rows"]:
+        _, alpha, gm, gc, gl, _cm, _cc, cl = row
+        l, n, C = phiq.setup_quadrature(eps, p, alpha, 1.0, "gauss")
+        assert (l, n + 1, n + 1 + l * p) == (gl, gm, gc)
+        l2, _, _ = phiq.setup_quadrature(eps, p, alpha, 1.0, "cc")
+        assert l2 == cl
+
+
+def test_setup_quadrature_matches_oracle_on_a_grid():
+    rng = np.random.default_rng(0)
+    cases = 0
+    for rule in ("gauss", "cc"):
+        for _ in range(60):
+            alpha = float(np.exp(rng.uniform(np.log(1e-3), np.log(1e5))))
+            p = int(rng.integers(1, 21))
+            eps = float(np.exp(rng.uniform(np.log(1e-14), np.log(1e-4))))
+            beta = float(np.exp(rng.uniform(-2, 2)))
+            c1 = float(rng.choice([0.0, 0.3]))
+            got = phiq.setup_quadrature(eps, p, alpha, beta, rule, c1, 1.0, 3)
+            ref = OB.setup_quadrature(eps, p, alpha, beta, rule, c1, 1.0, 3)
+            assert got[:2] == ref[:2], (rule, alpha, p, eps, beta, got, ref)
+            assert got[2] == pytest.approx(ref[2], rel=1e-12)
+            cases += 1
+    assert cases == 120
+
+
+def test_degenerate_selections():
+    assert phiq.setup_quadrature(1e-8, 5, 0.0)[:2] == (0, 2)  # ceil(5/2) = 3 nodes
+    assert phiq.setup_quadrature(1e-8, 0, 10.0)[:2] == (0, -1)
+    assert phiq.setup_quadrature(1e-8, 3, 0.5)[0] == 0      # ceil(log2 0.5) < 0 is clamped
+
+
+def test_log_quaderr_matches_oracle():
+    for rule in ("gauss", "cc"):
+        for alpha in (0.3, 2.0, 9.0, 48.0):
+            for p in (1, 3, 7, 20):
+                for n in (4, 6.5, 10, 37):
+                    got = phiq.log_quaderr(n, p, alpha, 1.0, rule)
+                    ref = OB.log_quaderr(n, p, alpha, 1.0, rule)
+                    assert got == pytest.approx(ref, rel=1e-10, abs=1e-9)
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 9, 10, 37, 64, 129])
+def test_gauss_rule_matches_oracle(m):
+    # numpy's leggauss weights carry relative errors up to ~2e-11 at m = 129
+    # (see the mpmath pin below), hence the tolerance.
+    th, w = phiq.quadrature_rule("gauss", m)
+    tr, wr = OQ.gauss_legendre(m)
+    assert np.allclose(th, tr, rtol=0, atol=2e-15)
+    assert np.allclose(w, wr, rtol=5e-11, atol=1e-16)
+
+
+@pytest.mark.parametrize("m", [5, 37])
+def test_gauss_rule_against_high_precision(m):
+    import mpmath
+
+    th, w = phiq.quadrature_rule("gauss", m)
+    with mpmath.workdps(40):
+        for i in range(m):
+            x = mpmath.mpf(2 * th[i] - 1)
+            for _ in range(6):
+                pm = mpmath.legendre(m, x)
+                dp = m * (x * pm - mpmath.legendre(m - 1, x)) / (x * x - 1)
+                x = x - pm / dp
+            pm = mpmath.legendre(m, x)
+            dp = m * (x * pm - mpmath.legendre(m - 1, x)) / (x * x - 1)
+            wt = float(1 / ((1 - x * x) * dp * dp))
+            assert abs(th[i] - float((1 + x) / 2)) <= 2.3e-16
+            assert abs(w[i] - wt) <= 5e-14 * wt
+
+
+@pytest.mark.parametrize("m", [2, 3, 5, 7, 13, 25, 49, 97, 193, 385])
+def test_cc_rule_matches_oracle(m):
+    th, w = phiq.quadrature_rule("cc", m)
+    tr, wr = OQ.clenshaw_curtis(m - 1)
+    assert np.allclose(th, tr, rtol=0, atol=2e-15)
+    assert np.allclose(w, wr, rtol=1e-12, atol=1e-16)
+
+
+def test_norm_bound():
+    pr = I.problem("advdiff", seed=3, n=16, dim=3)
+    got = phiq.norm_bound(pr["mats"], pr["t"])
+    assert got == pytest.approx(OB.infnorm_upper_bound(pr["mats"], pr["t"]), rel=1e-14)
+
+
+def test_host_validation_errors():
+    with pytest.raises(phiq.PhiqError, match="INVALID_ARG"):
+        phiq.setup_quadrature(-1.0, 3, 10.0)
+    with pytest.raises(phiq.PhiqError, match="NONFINITE"):
+        phiq.setup_quadrature(1e-8, 3, float("inf"))
+    with pytest.raises(phiq.PhiqError, match="INVALID_ARG"):
+        phiq.quadrature_rule("cc", 1)
+    bad = np.eye(3)
+    bad[1, 1] = np.nan
+    with pytest.raises(phiq.PhiqError, match="NONFINITE"):
+        phiq.norm_bound([bad, np.eye(3)], 1.0)
