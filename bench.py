@@ -1,0 +1,232 @@
+#!/usr/bin/env python3
+"""Benchmark: phi_k(-tA)v, k = 0..3, for a 3D advection-diffusion Kronecker sum.
+
+Workload (default): A = A^0 (+) A^1 (+) A^2, A^d = a_d tridiag(-1,2,-1)/h^2 +
+b_d tridiag(-1,1,0)/h on n = 128 interior points per axis (N = 2,097,152),
+a_d log-uniform in [0.1, 10], b_d uniform in [0, 50] (seed 0), t = 1e-3,
+v ~ N(0, 1), Gauss-Legendre nodes, tolerance 1e-8, FP64.
+
+One step = one full phi-action through the C ABI (phiq_action): norm bound,
+parameter selection, rule, 1D exponentials, quadrature with fused node
+sums, modified squaring, phi_0.  Inputs are resident in HBM before the timed
+region.  Kernel times come from HIP events the library records on its
+launch stream during the timed region.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "φ_k(tA)v grid-pts/s + MFMA util: split-BF16 vs FP64 at rel err 1e-8"
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_source_digest():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels_lowp.hip"):
+        p = os.path.join(ROOT, "paper_2211_00696_amd", "csrc", f)
+        if os.path.exists(p):
+            h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel, digest):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if current."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+        ent = d.get(kernel)
+        if not ent or ent.get("kernel_digest") != digest:
+            return None
+        return float(ent["bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def cpu_baseline(pr, out_gpu):
+    """The oracle's own algorithm (numpy, FP64) on the same input, timed."""
+    from oracle import phiquad
+
+    try:
+        from threadpoolctl import threadpool_info
+
+        threads = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    ref = phiquad.phiquadmv(pr["mats"], pr["t"], pr["v"], pr["p"], eps=pr["tol"], beta=1.0)
+    dt = time.perf_counter() - t0
+    N = pr["v"].size
+    errs = [float(np.max(np.abs(out_gpu[k] - ref[k])) / np.max(np.abs(ref[k]))) for k in range(pr["p"] + 1)]
+    return {
+        "value": N / dt,
+        "unit": "grid-pts/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": "one full phi-action (all N = %d points, phi_0..phi_%d) of the same workload by the oracle's "
+                  "numpy quadrature + modified squaring (FP64, BLAS threads = %d), %.2f s"
+                  % (N, pr["p"], threads, dt),
+        "seconds": dt,
+    }, errs
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--rule", default="gauss", choices=["gauss", "cc"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus %d is not supported "
+                                   "(the phi-action of one problem is not split across GPUs here)" % args.gpus}))
+        sys.exit(2)
+    rank = int(os.environ.get("RANK", "0"))
+
+    import torch
+
+    from paper_2211_00696_amd import inputs, phiq
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    pr = inputs.problem("advdiff3d", seed=args.seed, n=args.n)
+    N = pr["v"].size
+    p = pr["p"]
+    v = torch.from_numpy(pr["v"]).to(dev)
+    out = torch.empty((p + 1, N), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    h = phiq.Handle(0)
+    opts = dict(rule=args.rule, precision=args.precision)
+
+    for _ in range(args.warmup):
+        h.action(pr["mats"], pr["t"], p, v, tol=pr["tol"], out=out, **opts)
+    torch.cuda.synchronize()
+
+    # timed region: K full phi-actions, kernel events recorded live
+    h.profile_start()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    rep = None
+    for _ in range(args.steps):
+        _, rep = h.action(pr["mats"], pr["t"], p, v, tol=pr["tol"], out=out, **opts)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stats = h.profile_stop()
+    ms_per_step = wall * 1e3 / args.steps
+    ms_events = ev0.elapsed_time(ev1) / args.steps
+
+    # same work without the event brackets, and execute-only with a reused plan
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        h.action(pr["mats"], pr["t"], p, v, tol=pr["tol"], out=out, **opts)
+    torch.cuda.synchronize()
+    ms_unprofiled = (time.perf_counter() - t1) * 1e3 / args.steps
+    plan = h.plan(pr["mats"], pr["t"], p, tol=pr["tol"], **opts)
+    plan.execute(v)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.execute(v, out=out.view(1, p + 1, N))
+    torch.cuda.synchronize()
+    ms_execute = (time.perf_counter() - t2) * 1e3 / args.steps
+    plan.close()
+
+    # dominant kernel: the mode product (store epilogue) on FP64 MFMA
+    dom = max(stats.items(), key=lambda kv: kv[1]["ms"])[0]
+    st = stats[dom]
+    avg_ms = st["ms"] / st["launches"]
+    flops_per_launch = st["flops"] / st["launches"]
+    achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.precision]
+    digest = kernel_source_digest()
+    traffic = load_traffic(dom, digest)
+    ttm_total = {k: v for k, v in stats.items() if k.startswith("ttm")}
+    ttm_ms = sum(s["ms"] for s in ttm_total.values())
+    ttm_tflops = sum(s["flops"] for s in ttm_total.values()) / (ttm_ms * 1e-3) / 1e12
+
+    out_host = out.cpu().numpy()
+    result = {
+        "metric": METRIC,
+        "value": N / (ms_per_step * 1e-3),
+        "unit": "grid-pts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}[args.precision],
+        "data": "synthetic",
+        "config": {
+            "workload": "3D advection-diffusion Kronecker sum, n=%d per axis (N=%d), a_d log-U[0.1,10], "
+                        "b_d U[0,50], t=1e-3, phi_0..phi_3, v~N(0,1) seed %d, %s, tol 1e-8, %s mode products"
+                        % (args.n, N, args.seed, "Gauss-Legendre" if args.rule == "gauss" else "adaptive Clenshaw-Curtis",
+                           args.precision.upper()),
+            "n": args.n, "N": N, "p": p, "t": pr["t"], "tol": pr["tol"], "rule": args.rule,
+            "precision": args.precision, "seed": args.seed,
+            "coefficients": pr["coef"],
+        },
+        "roofline": {
+            "kernel": dom,
+            "bound": "mfma",
+            "achieved": achieved,
+            "peak": peak,
+            "unit": "TFLOP/s",
+            "frac": achieved / peak,
+            "traffic": traffic,
+            "avg_launch_ms": avg_ms,
+            "launches": st["launches"],
+            "flops_per_launch": flops_per_launch,
+            "algorithmic_bytes_per_launch": st["bytes"] / st["launches"],
+        },
+        "plan": {"l": rep["l"], "m": rep["m"], "alpha": rep["alpha"], "ttm_chains": rep["ttm_chains"],
+                 "log10_bound": rep["log10_bound"]},
+        "ms_per_step_events": ms_events,
+        "ms_per_step_unprofiled": ms_unprofiled,
+        "ms_per_execute_reused_plan": ms_execute,
+        "all_mode_products_tflops": ttm_tflops,
+        "kernels": {k: {"launches": s["launches"], "ms_per_step": s["ms"] / args.steps,
+                        "tflops": (s["flops"] / (s["ms"] * 1e-3) / 1e12) if s["ms"] > 0 else None,
+                        "gbs": (s["bytes"] / (s["ms"] * 1e-3) / 1e9) if s["ms"] > 0 else None}
+                    for k, s in stats.items()},
+        "kernel_digest": digest,
+    }
+    if not args.no_cpu_baseline and rank == 0:
+        cb, errs = cpu_baseline(pr, out_host)
+        result["cpu_baseline"] = cb
+        result["rel_err_vs_oracle_per_phi_k"] = errs
+    else:
+        result["cpu_baseline"] = None
+    h.close()
+    if rank == 0:
+        print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

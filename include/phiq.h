@@ -191,6 +191,31 @@ phiq_status phiq_kron_apply(phiq_handle h, int dim, const int* n, const double* 
                             const double* x, double* y, int nvec, phiq_precision prec,
                             hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Live kernel timing.
+ *
+ * Between phiq_profile_start and phiq_profile_stop the handle brackets every
+ * kernel it launches with a pair of HIP events on the launch stream.  stop
+ * synchronises the device and returns, per kernel class, the number of
+ * launches, the summed event time and the algorithmic work of those
+ * launches: flops of the contractions (2 n N per mode product of one
+ * N-vector) and the bytes each launch must move at least (every operand
+ * read once, every result written once).  Classes: "ttm_store",
+ * "ttm_accum", "ttm_square", "gemm", "taylor", "scale", "node_sum",
+ * "absdiff".  stats is HOST, room for max_stats entries; *n_stats gets the
+ * number of classes with at least one launch.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  char name[24];
+  int launches;
+  double ms;       /* summed event time of the launches                   */
+  double flops;    /* algorithmic floating-point operations               */
+  double bytes;    /* algorithmic bytes (compulsory reads + writes)       */
+} phiq_kernel_stat;
+
+phiq_status phiq_profile_start(phiq_handle h);
+phiq_status phiq_profile_stop(phiq_handle h, phiq_kernel_stat* stats, int max_stats, int* n_stats);
+
 #ifdef __cplusplus
 }
 #endif

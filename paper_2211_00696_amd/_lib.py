@@ -38,6 +38,8 @@ EXPORTS = [
     "phiq_action",
     "phiq_expm",
     "phiq_kron_apply",
+    "phiq_profile_start",
+    "phiq_profile_stop",
 ]
 
 
@@ -75,6 +77,11 @@ class Report(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("launches", c_int), ("ms", c_double), ("flops", c_double),
+                ("bytes", c_double)]
+
+
 _lib = None
 
 
@@ -106,6 +113,8 @@ def load():
         "phiq_expm": (c_int, [c_void_p, c_int, c_int, c_void_p, P(c_double), c_void_p, c_void_p]),
         "phiq_kron_apply": (c_int, [c_void_p, c_int, P(c_int), P(c_void_p), c_void_p, c_void_p, c_int, c_int,
                                     c_void_p]),
+        "phiq_profile_start": (c_int, [c_void_p]),
+        "phiq_profile_stop": (c_int, [c_void_p, P(KernelStat), c_int, P(c_int)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -106,8 +106,26 @@ double sum_infnorms(const phiq_kron_op* op) {
 
 using namespace phiq;
 
+struct ProfRec {
+  int cls;
+  hipEvent_t e0, e1;
+  double flops, bytes;
+};
+
+struct Profiler {
+  bool on = false;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t next = 0;
+};
+
+static const char* const kProfClass[] = {"ttm_store", "ttm_accum", "ttm_square", "gemm",
+                                         "taylor",    "scale",     "node_sum",   "absdiff"};
+enum ProfClass { K_TTM_STORE = 0, K_TTM_ACCUM, K_TTM_SQUARE, K_GEMM, K_TAYLOR, K_SCALE, K_NODE_SUM, K_ABSDIFF, K_NCLASS };
+
 struct phiq_handle_s {
   int device = 0;
+  Profiler prof;
   DevBuf ws;                     // execute workspace (T0, T1, Ya, Yb)
   DevBuf scratch;                // transient plans (phiq_action) and phiq_expm
   std::vector<DevBuf> cc_levels; // node vectors of the adaptive rule, per level
@@ -170,6 +188,73 @@ struct DeviceGuard {
     if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
   }
 };
+
+hipEvent_t prof_event(phiq_handle h) {
+  Profiler& pr = h->prof;
+  if (pr.next < pr.pool.size()) return pr.pool[pr.next++];
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  pr.pool.push_back(e);
+  pr.next = pr.pool.size();
+  return e;
+}
+
+// Launch through f(); when profiling, bracket it with events on st.
+template <class F>
+phiq_status prof_launch(phiq_handle h, hipStream_t st, int cls, double flops, double bytes, F&& f) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (h->prof.on) {
+    e0 = prof_event(h);
+    e1 = prof_event(h);
+    if (e0) (void)hipEventRecord(e0, st);
+  }
+  if (f() != hipSuccess) return PHIQ_ERR_HIP;
+  if (h->prof.on && e0 && e1) {
+    (void)hipEventRecord(e1, st);
+    h->prof.recs.push_back({cls, e0, e1, flops, bytes});
+  }
+  return PHIQ_OK;
+}
+
+// Algorithmic work of a batched mode product (see TtmArgs).
+void ttm_work(const TtmArgs& a, int cls, double* flops, double* bytes) {
+  const double N = (double)a.L * a.K;
+  *flops = 2.0 * a.M * a.K * (double)a.L * a.nbatch;
+  const double xin = (a.xs == 0 ? 1.0 : (double)a.nbatch) * N;
+  double out = (double)a.nbatch * a.M * a.L;
+  double extra = 0.0;
+  if (cls == K_TTM_ACCUM) out = (double)a.np * a.M * a.L;
+  if (cls == K_TTM_SQUARE) extra = (double)a.nbatch * a.M * a.L;  // the y_j read once
+  *bytes = 8.0 * (xin + out + extra + (double)a.nbatch * a.M * a.K * (a.es == 0 ? 0.0 : 1.0));
+}
+
+phiq_status L_ttm(phiq_handle h, int cls, const TtmArgs& a, phiq_precision prec, hipStream_t st) {
+  double fl, by;
+  ttm_work(a, cls, &fl, &by);
+  return prof_launch(h, st, cls, fl, by, [&] {
+    if (cls == K_TTM_ACCUM) return launch_ttm_accum(a, prec, st);
+    if (cls == K_TTM_SQUARE) return launch_ttm_square(a, prec, st);
+    return launch_ttm_store(a, prec, st);
+  });
+}
+
+phiq_status L_gemm(phiq_handle h, const GemmJob* jobs, int njobs, int nm, hipStream_t st) {
+  const double n = nm;
+  return prof_launch(h, st, K_GEMM, 2.0 * n * n * n * njobs, 24.0 * n * n * njobs,
+                     [&] { return launch_gemm_jobs(jobs, njobs, nm, st); });
+}
+
+phiq_status L_taylor(phiq_handle h, const TaylorJob* jobs, int njobs, int nm, int K, hipStream_t st) {
+  const double n = nm;
+  return prof_launch(h, st, K_TAYLOR, 2.0 * K * n * n * njobs, 8.0 * (K + 1) * n * n * njobs,
+                     [&] { return launch_taylor_jobs(jobs, njobs, nm, st); });
+}
+
+phiq_status L_scale(phiq_handle h, const ScaleJob* jobs, int njobs, int nm, hipStream_t st) {
+  const double n = nm;
+  return prof_launch(h, st, K_SCALE, n * n * njobs, 16.0 * n * n * njobs,
+                     [&] { return launch_scale_jobs(jobs, njobs, nm, st); });
+}
 
 phiq_status ensure(phiq_handle h, DevBuf& b, size_t bytes) {
   if (bytes <= b.cap) return PHIQ_OK;
@@ -334,8 +419,8 @@ int nmax_of(const phiq_plan_s* P) {
 
 phiq_status run_taylor_sigma(const phiq_plan_s* P, const char* jobs_dev, const ExpmJobs& ej, hipStream_t st) {
   const int nm = nmax_of(P);
-  PHIQ_HIP(launch_taylor_jobs((const TaylorJob*)(jobs_dev + ej.taylor_off), ej.taylor_n, nm, st));
-  for (const auto& r : ej.sigma_rounds) PHIQ_HIP(launch_gemm_jobs((const GemmJob*)(jobs_dev + r.first), r.second, nm, st));
+  PHIQ_TRY(L_taylor(P->h, (const TaylorJob*)(jobs_dev + ej.taylor_off), ej.taylor_n, nm, P->K, st));
+  for (const auto& r : ej.sigma_rounds) PHIQ_TRY(L_gemm(P->h, (const GemmJob*)(jobs_dev + r.first), r.second, nm, st));
   return PHIQ_OK;
 }
 
@@ -577,12 +662,12 @@ phiq_status plan_build(phiq_handle h, const phiq_kron_op* op, double t, int p, d
   }
   // ---- device work: the 1D exponentials ----
   const int nm = nmax_of(P);
-  bool ok = launch_scale_jobs((const ScaleJob*)(P->jobs + ej.scale_off), ej.scale_n, nm, st) == hipSuccess;
+  bool ok = L_scale(h, (const ScaleJob*)(P->jobs + ej.scale_off), ej.scale_n, nm, st) == PHIQ_OK;
   for (const auto& r : ej.power_rounds)
-    ok = ok && launch_gemm_jobs((const GemmJob*)(P->jobs + r.first), r.second, nm, st) == hipSuccess;
+    ok = ok && L_gemm(h, (const GemmJob*)(P->jobs + r.first), r.second, nm, st) == PHIQ_OK;
   ok = ok && run_taylor_sigma(P, P->jobs, ej, st) == PHIQ_OK;
   for (const auto& r : ej.square_chain)
-    ok = ok && launch_gemm_jobs((const GemmJob*)(P->jobs + r.first), r.second, nm, st) == hipSuccess;
+    ok = ok && L_gemm(h, (const GemmJob*)(P->jobs + r.first), r.second, nm, st) == PHIQ_OK;
   if (!ok) {
     phiq_plan_destroy(P);
     return PHIQ_ERR_HIP;
@@ -625,7 +710,7 @@ phiq_status chain_front(const phiq_plan_s* P, const double* X, long long xs, dou
     a.M = a.K = P->n[d];
     a.L = (int)(P->N / P->n[d]);
     a.nbatch = nb;
-    PHIQ_HIP(launch_ttm_store(a, P->opt.precision, st));
+    PHIQ_TRY(L_ttm(P->h, K_TTM_STORE, a, P->opt.precision, st));
     cur = a.O;
     cxs = P->N;
   }
@@ -658,7 +743,7 @@ phiq_status phi0_chain(const phiq_plan_s* P, const double* v, double* out0, doub
   TtmArgs a = final_args(P, P->Ephi0[0], 0, f, 1);
   a.O = out0;
   a.os = 0;
-  PHIQ_HIP(launch_ttm_store(a, P->opt.precision, st));
+  PHIQ_TRY(L_ttm(P->h, K_TTM_STORE, a, P->opt.precision, st));
   return PHIQ_OK;
 }
 
@@ -683,7 +768,7 @@ phiq_status squaring(const phiq_plan_s* P, double* Ycur, double* Yother, double*
     a.os = N;
     a.Yprev = cur;
     a.yps = N;
-    PHIQ_HIP(launch_ttm_square(a, P->opt.precision, st));
+    PHIQ_TRY(L_ttm(P->h, K_TTM_SQUARE, a, P->opt.precision, st));
     cur = dst;
   }
   return PHIQ_OK;
@@ -720,7 +805,7 @@ phiq_status execute_gauss(phiq_plan P, const double* v, double* out, hipStream_t
     TtmArgs a = final_args(P, P->Enode[0] + (size_t)P->m * es[0], 0, Front{f.X + P->m * f.xs, 0}, 1);
     a.O = out;
     a.os = 0;
-    PHIQ_HIP(launch_ttm_store(a, P->opt.precision, st));
+    PHIQ_TRY(L_ttm(P->h, K_TTM_STORE, a, P->opt.precision, st));
   }
   double* Y = (P->l == 0) ? out + N : Ya;
   for (int j0 = 0; j0 < p; j0 += 4) {
@@ -730,7 +815,7 @@ phiq_status execute_gauss(phiq_plan P, const double* v, double* out, hipStream_t
     a.np = std::min(4, p - j0);
     a.Y = Y + (size_t)j0 * N;
     a.ys = N;
-    PHIQ_HIP(launch_ttm_accum(a, P->opt.precision, st));
+    PHIQ_TRY(L_ttm(P->h, K_TTM_ACCUM, a, P->opt.precision, st));
   }
   if (P->l > 0) PHIQ_TRY(squaring(P, Ya, Yb, out + N, T0, T1, st));
   return PHIQ_OK;
@@ -846,7 +931,7 @@ phiq_status execute_cc(phiq_plan P, const double* v, double* out, hipStream_t st
     TtmArgs a = final_args(P, E[0], es[0], f, cnt);
     a.O = V;
     a.os = N;
-    PHIQ_HIP(launch_ttm_store(a, P->opt.precision, st));
+    PHIQ_TRY(L_ttm(P->h, K_TTM_STORE, a, P->opt.precision, st));
     // weights of the full (2n+1)-point rule, n = 3*2^level, in storage order
     const int n2 = 6 << level;
     std::vector<double> xt(n2 + 1), wt(n2 + 1);
@@ -875,10 +960,13 @@ phiq_status execute_cc(phiq_plan P, const double* v, double* out, hipStream_t st
     }
     PHIQ_TRY(stage_copy(h, slot, P->coef, sizeof(double) * (size_t)p * total, st));
     // y_j = sum_i w_i x_i^{j-1}/(j-1)! v_i (Algorithm 2, step 3)
-    PHIQ_HIP(launch_node_sum(segs, N, P->coef, total, p, ynew, st));
+    PHIQ_TRY(prof_launch(h, st, K_NODE_SUM, 2.0 * p * total * (double)N, 8.0 * (total + p) * (double)N,
+                         [&] { return launch_node_sum(segs, N, P->coef, total, p, ynew, st); }));
     if (level > 0) {
       // err = max_j ||y_j - y~_j||_inf / ||y_j||_inf (Algorithm 2, step 4)
-      PHIQ_HIP(launch_absdiff_max(ynew, ycur, p, N, (double*)h->partial.p, nblk, st));
+      PHIQ_TRY(prof_launch(h, st, K_ABSDIFF, 2.0 * p * (double)N, 16.0 * p * (double)N, [&] {
+        return launch_absdiff_max(ynew, ycur, p, N, (double*)h->partial.p, nblk, st);
+      }));
       PHIQ_HIP(hipMemcpyAsync(h->partial_host, h->partial.p, (size_t)nblk * p * 2 * sizeof(double),
                               hipMemcpyDeviceToHost, st));
       PHIQ_HIP(hipStreamSynchronize(st));
@@ -974,6 +1062,7 @@ phiq_status phiq_destroy(phiq_handle h) {
   for (auto& b : h->cc_levels)
     if (b.p) (void)hipFree(b.p);
   if (h->partial_host) (void)hipHostFree(h->partial_host);
+  for (auto e : h->prof.pool) (void)hipEventDestroy(e);
   for (int k = 0; k < 3; ++k) {
     if (h->stage.host[k]) (void)hipHostFree(h->stage.host[k]);
     if (h->stage.ev[k]) (void)hipEventDestroy(h->stage.ev[k]);
@@ -1081,7 +1170,7 @@ phiq_status phiq_kron_apply(phiq_handle h, int dim, const int* n, const double* 
     a.M = a.K = n[d];
     a.L = (int)(N / n[d]);
     a.nbatch = nvec;
-    PHIQ_HIP(launch_ttm_store(a, prec, stream));
+    PHIQ_TRY(L_ttm(h, K_TTM_STORE, a, prec, stream));
     cur = a.O;
   }
   return PHIQ_OK;
@@ -1160,10 +1249,46 @@ phiq_status phiq_expm(phiq_handle h, int n, int nmat, const double* X, const dou
   std::memcpy(hp, blob.bytes.data(), blob.bytes.size());
   char* jd = base + offJ;
   PHIQ_TRY(stage_copy(h, slot, jd, blob.bytes.size(), stream));
-  PHIQ_HIP(launch_scale_jobs((const ScaleJob*)(jd + o_scale), (int)sj.size(), n, stream));
-  for (const auto& r : rounds) PHIQ_HIP(launch_gemm_jobs((const GemmJob*)(jd + r.first), r.second, n, stream));
-  PHIQ_HIP(launch_taylor_jobs((const TaylorJob*)(jd + o_tay), (int)tj.size(), n, stream));
-  for (const auto& r : sq) PHIQ_HIP(launch_gemm_jobs((const GemmJob*)(jd + r.first), r.second, n, stream));
+  PHIQ_TRY(L_scale(h, (const ScaleJob*)(jd + o_scale), (int)sj.size(), n, stream));
+  for (const auto& r : rounds) PHIQ_TRY(L_gemm(h, (const GemmJob*)(jd + r.first), r.second, n, stream));
+  PHIQ_TRY(L_taylor(h, (const TaylorJob*)(jd + o_tay), (int)tj.size(), n, K, stream));
+  for (const auto& r : sq) PHIQ_TRY(L_gemm(h, (const GemmJob*)(jd + r.first), r.second, n, stream));
+  return PHIQ_OK;
+}
+
+phiq_status phiq_profile_start(phiq_handle h) {
+  if (!h) return PHIQ_ERR_INVALID_ARG;
+  h->prof.recs.clear();
+  h->prof.next = 0;
+  h->prof.on = true;
+  return PHIQ_OK;
+}
+
+phiq_status phiq_profile_stop(phiq_handle h, phiq_kernel_stat* stats, int max_stats, int* n_stats) {
+  if (!h || (max_stats > 0 && !stats) || max_stats < 0) return PHIQ_ERR_INVALID_ARG;
+  DeviceGuard g(h->device);
+  h->prof.on = false;
+  PHIQ_HIP(hipDeviceSynchronize());
+  phiq_kernel_stat agg[K_NCLASS];
+  std::memset(agg, 0, sizeof(agg));
+  for (int c = 0; c < K_NCLASS; ++c) std::strncpy(agg[c].name, kProfClass[c], sizeof(agg[c].name) - 1);
+  for (const auto& r : h->prof.recs) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.e0, r.e1) != hipSuccess) return PHIQ_ERR_HIP;
+    agg[r.cls].launches += 1;
+    agg[r.cls].ms += ms;
+    agg[r.cls].flops += r.flops;
+    agg[r.cls].bytes += r.bytes;
+  }
+  h->prof.recs.clear();
+  h->prof.next = 0;
+  int k = 0;
+  for (int c = 0; c < K_NCLASS; ++c)
+    if (agg[c].launches > 0) {
+      if (k < max_stats) stats[k] = agg[c];
+      ++k;
+    }
+  if (n_stats) *n_stats = std::min(k, max_stats);
   return PHIQ_OK;
 }
 

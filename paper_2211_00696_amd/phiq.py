@@ -190,6 +190,18 @@ class Handle:
         except Exception:
             pass
 
+    def profile_start(self):
+        """Bracket every later kernel launch with HIP events (see phiq_profile_start)."""
+        _check(L.load().phiq_profile_start(self._h), "phiq_profile_start")
+
+    def profile_stop(self):
+        """Synchronise and return {kernel class: dict(launches, ms, flops, bytes)}."""
+        arr = (L.KernelStat * 16)()
+        n = c_int()
+        _check(L.load().phiq_profile_stop(self._h, arr, 16, byref(n)), "phiq_profile_stop")
+        return {arr[i].name.decode(): dict(launches=arr[i].launches, ms=arr[i].ms, flops=arr[i].flops,
+                                           bytes=arr[i].bytes) for i in range(n.value)}
+
     def action(self, mats, t, p, v, tol=1e-8, out=None, stream=None, **opts):
         """out[k] = phi_k(-t A) v, k = 0..p; returns (out (p+1, N), report dict)."""
         import torch
