@@ -225,7 +225,9 @@ void ttm_work(const TtmArgs& a, int cls, double* flops, double* bytes) {
   double extra = 0.0;
   if (cls == K_TTM_ACCUM) out = (double)a.np * a.M * a.L;
   if (cls == K_TTM_SQUARE) extra = (double)a.nbatch * a.M * a.L;  // the y_j read once
-  *bytes = 8.0 * (xin + out + extra + (double)a.nbatch * a.M * a.K * (a.es == 0 ? 0.0 : 1.0));
+  const double xb = a.x_f32 ? 4.0 : 8.0;
+  const double ob = (a.o_f32 && cls == K_TTM_STORE) ? 4.0 : 8.0;
+  *bytes = xb * xin + ob * out + 8.0 * (extra + (double)a.nbatch * a.M * a.K * (a.es == 0 ? 0.0 : 1.0));
 }
 
 phiq_status L_ttm(phiq_handle h, int cls, const TtmArgs& a, phiq_precision prec, hipStream_t st) {
@@ -362,16 +364,24 @@ void build_taylor_and_sigma(const phiq_plan_s* P, const std::vector<ExpTarget>& 
                             ExpmJobs& ej) {
   std::vector<TaylorJob> tj;
   int smax = 0;
-  for (const auto& t : tg) {
-    const int d = t.d, n = P->n[d];
+  for (int d = 0; d < P->D; ++d) {
+    const int n = P->n[d];
     TaylorJob j{};
-    j.Zpow = P->Z[d];
-    j.c = t.c;
-    j.n = n;
-    j.K = P->K;
-    j.out = P->sigma[d] > 0 ? P->S[0][d] + (size_t)t.sidx * n * n : t.dst;
-    tj.push_back(j);
-    smax = std::max(smax, P->sigma[d]);
+    for (const auto& t : tg) {
+      if (t.d != d) continue;
+      if (j.nt == kTaylorTargets) {
+        tj.push_back(j);
+        j = TaylorJob{};
+      }
+      j.Zpow = P->Z[d];
+      j.n = n;
+      j.K = P->K;
+      j.c[j.nt] = t.c;
+      j.dst[j.nt] = P->sigma[d] > 0 ? P->S[0][d] + (size_t)t.sidx * n * n : t.dst;
+      ++j.nt;
+      smax = std::max(smax, P->sigma[d]);
+    }
+    if (j.nt > 0) tj.push_back(j);
   }
   ej.taylor_off = blob.add(tj);
   ej.taylor_n = (int)tj.size();
@@ -439,7 +449,6 @@ phiq_status plan_build(phiq_handle h, const phiq_kron_op* op, double t, int p, d
   if (opt.rule != PHIQ_RULE_GAUSS && opt.rule != PHIQ_RULE_CC) return PHIQ_ERR_INVALID_ARG;
   if (opt.precision != PHIQ_PREC_FP64 && opt.precision != PHIQ_PREC_FP32 && opt.precision != PHIQ_PREC_BF16X3)
     return PHIQ_ERR_INVALID_ARG;
-  if (opt.precision != PHIQ_PREC_FP64) return PHIQ_ERR_UNSUPPORTED;
   if (!std::isfinite(opt.c1) || !std::isfinite(opt.c2) || !std::isfinite(opt.alpha)) return PHIQ_ERR_NONFINITE;
   if (opt.c1 < 0 || opt.c2 < 0 || opt.l < -1 || opt.l > 60 || opt.m < -1 || opt.m == 0 || opt.m > 4096 ||
       opt.cc_max_doublings < 1 || opt.cc_max_doublings > 10)
@@ -517,13 +526,19 @@ phiq_status plan_build(phiq_handle h, const phiq_kron_op* op, double t, int p, d
   P->ldcoef = std::max(1, ncoefcols);
 
   // device layout
+  // The upload region [A^0 .. A^{D-1} | coef | jobs] comes first so that
+  // one host->device copy fills it.
   Layout L;
   size_t offA[PHIQ_MAX_DIM], offZ[PHIQ_MAX_DIM], offE[PHIQ_MAX_DIM], offSq[PHIQ_MAX_DIM], offS0[PHIQ_MAX_DIM],
       offS1[PHIQ_MAX_DIM], offPhi0[PHIQ_MAX_DIM];
+  for (int d = 0; d < P->D; ++d) offA[d] = L.take((size_t)P->n[d] * P->n[d] * sizeof(double));
+  const size_t coef_bytes = sizeof(double) * (size_t)std::max(1, p) * P->ldcoef;
+  const size_t offCoef = L.take(coef_bytes);
+  const size_t jobs_cap = 1 << 20;
+  const size_t offJobs = L.take(jobs_cap);
   const int nslots = P->m + 1;  // Taylor targets: nodes + E^(0)
   for (int d = 0; d < P->D; ++d) {
     const size_t nn = (size_t)P->n[d] * P->n[d] * sizeof(double);
-    offA[d] = L.take(nn);
     offZ[d] = L.take(nn * P->K);
     offE[d] = L.take(nn * (P->m + 1));
     offSq[d] = L.take(nn * std::max(1, l));
@@ -533,9 +548,6 @@ phiq_status plan_build(phiq_handle h, const phiq_kron_op* op, double t, int p, d
     offS0[d] = P->sigma[d] > 0 ? L.take(nn * ss) : 0;
     offS1[d] = P->sigma[d] > 1 ? L.take(nn * ss) : 0;
   }
-  const size_t offCoef = L.take(sizeof(double) * (size_t)std::max(1, p) * P->ldcoef);
-  const size_t jobs_cap = 1 << 20;
-  const size_t offJobs = L.take(jobs_cap);
   P->bytes = L.off;
   if (transient) {
     phiq_status s = ensure(h, h->scratch, P->bytes);
@@ -611,11 +623,8 @@ phiq_status plan_build(phiq_handle h, const phiq_kron_op* op, double t, int p, d
     phiq_plan_destroy(P);
     return PHIQ_ERR_UNSUPPORTED;
   }
-  // upload region = [A^d ... ] [coef] [jobs]: three copies from one staging slot
-  size_t a_bytes = 0;
-  for (int d = 0; d < P->D; ++d) a_bytes += (size_t)P->n[d] * P->n[d] * sizeof(double);
-  const size_t coef_bytes = sizeof(double) * (size_t)std::max(1, p) * P->ldcoef;
-  const size_t total = a_bytes + coef_bytes + blob.bytes.size();
+  // one copy: [A^d ...][coef][jobs] mirrored in the staging buffer
+  const size_t total = offJobs + blob.bytes.size();
   int slot;
   void* hostp;
   phiq_status s = stage_acquire(h, total, &slot, &hostp);
@@ -624,13 +633,9 @@ phiq_status plan_build(phiq_handle h, const phiq_kron_op* op, double t, int p, d
     return s;
   }
   char* hp = (char*)hostp;
-  size_t o = 0;
-  for (int d = 0; d < P->D; ++d) {
-    const size_t nb = (size_t)P->n[d] * P->n[d] * sizeof(double);
-    std::memcpy(hp + o, op->A[d], nb);
-    o += nb;
-  }
-  double* hc = (double*)(hp + o);
+  for (int d = 0; d < P->D; ++d)
+    std::memcpy(hp + offA[d], op->A[d], (size_t)P->n[d] * P->n[d] * sizeof(double));
+  double* hc = (double*)(hp + offCoef);
   std::fill(hc, hc + (size_t)std::max(1, p) * P->ldcoef, 0.0);
   if (opt.rule == PHIQ_RULE_GAUSS) {
     for (int j = 0; j < p; ++j) {
@@ -639,26 +644,10 @@ phiq_status plan_build(phiq_handle h, const phiq_kron_op* op, double t, int p, d
       for (int q = 0; q < P->m; ++q) hc[(size_t)j * P->ldcoef + q] = w[q] * std::pow(theta[q], j) / fact;
     }
   }
-  o += coef_bytes;
-  std::memcpy(hp + o, blob.bytes.data(), blob.bytes.size());
-  // copies: A^d are contiguous in the layout only per axis, so copy per axis
-  {
-    size_t ho = 0;
-    bool ok = true;
-    for (int d = 0; d < P->D && ok; ++d) {
-      const size_t nb = (size_t)P->n[d] * P->n[d] * sizeof(double);
-      ok = hipMemcpyAsync(base + offA[d], hp + ho, nb, hipMemcpyHostToDevice, st) == hipSuccess;
-      ho += nb;
-    }
-    ok = ok && hipMemcpyAsync(P->coef, hp + a_bytes, coef_bytes, hipMemcpyHostToDevice, st) == hipSuccess;
-    ok = ok && hipMemcpyAsync(P->jobs, hp + a_bytes + coef_bytes, blob.bytes.size(), hipMemcpyHostToDevice, st) ==
-                   hipSuccess;
-    ok = ok && hipEventRecord(h->stage.ev[slot], st) == hipSuccess;
-    h->stage.pending[slot] = true;
-    if (!ok) {
-      phiq_plan_destroy(P);
-      return PHIQ_ERR_HIP;
-    }
+  std::memcpy(hp + offJobs, blob.bytes.data(), blob.bytes.size());
+  if (stage_copy(h, slot, base, total, st) != PHIQ_OK) {
+    phiq_plan_destroy(P);
+    return PHIQ_ERR_HIP;
   }
   // ---- device work: the 1D exponentials ----
   const int nm = nmax_of(P);
@@ -688,16 +677,25 @@ phiq_status plan_build(phiq_handle h, const phiq_kron_op* op, double t, int p, d
 // execution helpers
 // ---------------------------------------------------------------------------
 struct Front {
-  const double* X;
+  const void* X;
   long long xs;
+  int f32;  // X holds FP32 values
 };
 
+inline bool lowp(const phiq_plan_s* P) { return P->opt.precision != PHIQ_PREC_FP64; }
+inline size_t tensor_elem(const phiq_plan_s* P) { return lowp(P) ? sizeof(float) : sizeof(double); }
+inline const void* elem_offset(const void* X, long long elems, int f32) {
+  return (const char*)X + elems * (f32 ? (long long)sizeof(float) : (long long)sizeof(double));
+}
+
 // Mode products over axes D-1..1 for nb batches (rotated layout); returns the
-// input of the final product over axis 0.
+// input of the final product over axis 0.  X is FP64; the intermediates T0
+// and T1 are FP32 when a lower precision is selected.
 phiq_status chain_front(const phiq_plan_s* P, const double* X, long long xs, double* const* Ebase, long long const* es,
-                        int nb, double* T0, double* T1, hipStream_t st, Front* f) {
-  const double* cur = X;
+                        int nb, void* T0, void* T1, hipStream_t st, Front* f) {
+  const void* cur = X;
   long long cxs = xs;
+  int cur_f32 = 0;
   for (int s = 0; s + 1 < P->D; ++s) {
     const int d = P->D - 1 - s;
     TtmArgs a{};
@@ -705,17 +703,21 @@ phiq_status chain_front(const phiq_plan_s* P, const double* X, long long xs, dou
     a.es = es[d];
     a.X = cur;
     a.xs = cxs;
+    a.x_f32 = cur_f32;
     a.O = (s % 2 == 0) ? T0 : T1;
     a.os = P->N;
+    a.o_f32 = lowp(P) ? 1 : 0;
     a.M = a.K = P->n[d];
     a.L = (int)(P->N / P->n[d]);
     a.nbatch = nb;
     PHIQ_TRY(L_ttm(P->h, K_TTM_STORE, a, P->opt.precision, st));
     cur = a.O;
     cxs = P->N;
+    cur_f32 = a.o_f32;
   }
   f->X = cur;
   f->xs = cxs;
+  f->f32 = cur_f32;
   return PHIQ_OK;
 }
 
@@ -725,13 +727,15 @@ TtmArgs final_args(const phiq_plan_s* P, const double* E, long long es, const Fr
   a.es = es;
   a.X = f.X;
   a.xs = f.xs;
+  a.x_f32 = f.f32;
+  a.o_f32 = 0;
   a.M = a.K = P->n[0];
   a.L = (int)(P->N / P->n[0]);
   a.nbatch = nb;
   return a;
 }
 
-phiq_status phi0_chain(const phiq_plan_s* P, const double* v, double* out0, double* T0, double* T1, hipStream_t st) {
+phiq_status phi0_chain(const phiq_plan_s* P, const double* v, double* out0, void* T0, void* T1, hipStream_t st) {
   double* E[PHIQ_MAX_DIM];
   long long es[PHIQ_MAX_DIM];
   for (int d = 0; d < P->D; ++d) {
@@ -749,7 +753,7 @@ phiq_status phi0_chain(const phiq_plan_s* P, const double* v, double* out0, doub
 
 // l modified-squaring steps (eq. squaring) starting from y in Ycur (p x N);
 // the last step writes into dst_final.
-phiq_status squaring(const phiq_plan_s* P, double* Ycur, double* Yother, double* dst_final, double* T0, double* T1,
+phiq_status squaring(const phiq_plan_s* P, double* Ycur, double* Yother, double* dst_final, void* T0, void* T1,
                      hipStream_t st) {
   const long long N = P->N;
   double* cur = Ycur;
@@ -779,13 +783,13 @@ phiq_status execute_gauss(phiq_plan P, const double* v, double* out, hipStream_t
   const long long N = P->N;
   const int p = P->p;
   const int nb = std::max(P->m + 1, p);
-  const size_t tbytes = (P->D > 1 ? (size_t)nb * N * sizeof(double) : 0);
+  const size_t tbytes = (P->D > 1 ? (size_t)nb * N * tensor_elem(P) : 0);
   const size_t ybytes = (size_t)p * N * sizeof(double);
   const size_t need = 2 * align_up(tbytes) + (P->l >= 1 ? align_up(ybytes) : 0) + (P->l >= 2 ? align_up(ybytes) : 0);
   PHIQ_TRY(ensure(h, h->ws, std::max<size_t>(need, kAlign)));
   char* wb = (char*)h->ws.p;
-  double* T0 = (double*)wb;
-  double* T1 = (double*)(wb + align_up(tbytes));
+  void* T0 = wb;
+  void* T1 = wb + align_up(tbytes);
   double* Ya = (double*)(wb + 2 * align_up(tbytes));
   double* Yb = (double*)(wb + 2 * align_up(tbytes) + align_up(ybytes));
 
@@ -802,7 +806,7 @@ phiq_status execute_gauss(phiq_plan P, const double* v, double* out, hipStream_t
   Front f;
   PHIQ_TRY(chain_front(P, v, 0, E, es, P->m + 1, T0, T1, st, &f));
   {
-    TtmArgs a = final_args(P, P->Enode[0] + (size_t)P->m * es[0], 0, Front{f.X + P->m * f.xs, 0}, 1);
+    TtmArgs a = final_args(P, P->Enode[0] + (size_t)P->m * es[0], 0, Front{elem_offset(f.X, P->m * f.xs, f.f32), 0, f.f32}, 1);
     a.O = out;
     a.os = 0;
     PHIQ_TRY(L_ttm(P->h, K_TTM_STORE, a, P->opt.precision, st));
@@ -880,6 +884,16 @@ double* cc_level_E(const phiq_plan_s* P, int level, int d) {
   return (double*)((char*)P->cc_E[level].p + o);
 }
 
+// Stopping tolerance of Algorithm 2.  With lower-precision mode products the
+// successive approximations differ by their rounding noise, so the test is
+// floored at a level that noise stays under (2^-18 for FP32 products,
+// 2^-12 for split bf16).
+double cc_tolerance(const phiq_plan_s* P) {
+  if (P->opt.precision == PHIQ_PREC_FP32) return std::max(P->tol, std::ldexp(1.0, -18));
+  if (P->opt.precision == PHIQ_PREC_BF16X3) return std::max(P->tol, std::ldexp(1.0, -12));
+  return P->tol;
+}
+
 phiq_status execute_cc(phiq_plan P, const double* v, double* out, hipStream_t st, phiq_report* rep) {
   phiq_handle h = P->h;
   const long long N = P->N;
@@ -887,12 +901,12 @@ phiq_status execute_cc(phiq_plan P, const double* v, double* out, hipStream_t st
   const int cap = P->opt.cc_max_doublings;
   const int maxcnt = 3 * (1 << cap) + 1;
   const int nb = std::max(std::max(maxcnt, 7), p);
-  const size_t tbytes = (P->D > 1 ? (size_t)nb * N * sizeof(double) : 0);
+  const size_t tbytes = (P->D > 1 ? (size_t)nb * N * tensor_elem(P) : 0);
   const size_t ybytes = (size_t)p * N * sizeof(double);
   PHIQ_TRY(ensure(h, h->ws, 2 * align_up(tbytes) + 2 * align_up(ybytes) + kAlign));
   char* wb = (char*)h->ws.p;
-  double* T0 = (double*)wb;
-  double* T1 = (double*)(wb + align_up(tbytes));
+  void* T0 = wb;
+  void* T1 = wb + align_up(tbytes);
   double* Ya = (double*)(wb + 2 * align_up(tbytes));
   double* Yb = (double*)(wb + 2 * align_up(tbytes) + align_up(ybytes));
   PHIQ_TRY(phi0_chain(P, v, out, T0, T1, st));
@@ -981,7 +995,7 @@ phiq_status execute_cc(phiq_plan P, const double* v, double* out, hipStream_t st
       }
     }
     std::swap(ycur, ynew);
-    if (level > 0 && err <= P->tol) {
+    if (level > 0 && err <= cc_tolerance(P)) {
       converged = true;
       break;
     }
@@ -1142,7 +1156,6 @@ phiq_status phiq_kron_apply(phiq_handle h, int dim, const int* n, const double* 
                             int nvec, phiq_precision prec, hipStream_t stream) {
   if (!h || !n || !F || !x || !y || nvec < 1 || dim < 1 || dim > PHIQ_MAX_DIM) return PHIQ_ERR_INVALID_ARG;
   if (prec != PHIQ_PREC_FP64 && prec != PHIQ_PREC_FP32 && prec != PHIQ_PREC_BF16X3) return PHIQ_ERR_INVALID_ARG;
-  if (prec != PHIQ_PREC_FP64) return PHIQ_ERR_UNSUPPORTED;
   long long N = 1;
   for (int d = 0; d < dim; ++d) {
     if (n[d] < 1 || n[d] > PHIQ_MAX_N || !F[d]) return PHIQ_ERR_INVALID_ARG;
@@ -1154,10 +1167,12 @@ phiq_status phiq_kron_apply(phiq_handle h, int dim, const int* n, const double* 
   const char* ye = yb + (size_t)nvec * N * sizeof(double);
   if (xb < ye && yb < xe) return PHIQ_ERR_INVALID_ARG;
   DeviceGuard g(h->device);
-  const size_t tb = align_up((size_t)nvec * N * sizeof(double));
+  const int lp = prec != PHIQ_PREC_FP64;
+  const size_t tb = align_up((size_t)nvec * N * (lp ? sizeof(float) : sizeof(double)));
   PHIQ_TRY(ensure(h, h->ws, dim > 1 ? 2 * tb : kAlign));
-  double* T[2] = {(double*)h->ws.p, (double*)((char*)h->ws.p + tb)};
-  const double* cur = x;
+  void* T[2] = {h->ws.p, (char*)h->ws.p + tb};
+  const void* cur = x;
+  int cur_f32 = 0;
   for (int s = 0; s < dim; ++s) {
     const int d = dim - 1 - s;
     TtmArgs a{};
@@ -1165,13 +1180,16 @@ phiq_status phiq_kron_apply(phiq_handle h, int dim, const int* n, const double* 
     a.es = 0;
     a.X = cur;
     a.xs = N;
-    a.O = (s == dim - 1) ? y : T[s % 2];
+    a.x_f32 = cur_f32;
+    a.O = (s == dim - 1) ? (void*)y : T[s % 2];
+    a.o_f32 = (s == dim - 1) ? 0 : lp;
     a.os = N;
     a.M = a.K = n[d];
     a.L = (int)(N / n[d]);
     a.nbatch = nvec;
     PHIQ_TRY(L_ttm(h, K_TTM_STORE, a, prec, stream));
     cur = a.O;
+    cur_f32 = a.o_f32;
   }
   return PHIQ_OK;
 }
@@ -1230,7 +1248,16 @@ phiq_status phiq_expm(phiq_handle h, int n, int nmat, const double* X, const dou
     rounds.push_back({blob.add(gj), (int)gj.size()});
   }
   std::vector<TaylorJob> tj;
-  for (int b = 0; b < nmat; ++b) tj.push_back(TaylorJob{zpow(b, 1), sig[b] > 0 ? S[0] + b * nn : E + b * nn, 1.0, n, K});
+  for (int b = 0; b < nmat; ++b) {
+    TaylorJob j{};
+    j.Zpow = zpow(b, 1);
+    j.dst[0] = sig[b] > 0 ? S[0] + b * nn : E + b * nn;
+    j.c[0] = 1.0;
+    j.n = n;
+    j.K = K;
+    j.nt = 1;
+    tj.push_back(j);
+  }
   const size_t o_tay = blob.add(tj);
   std::vector<std::pair<size_t, int>> sq;
   for (int r = 1; r <= smax; ++r) {

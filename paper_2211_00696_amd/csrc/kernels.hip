@@ -31,6 +31,7 @@ struct Tile {
 using Tile64 = Tile<64, 64, 16, 2, 2>;
 using Tile128 = Tile<128, 64, 16, 2, 2>;
 using Tile256 = Tile<256, 64, 16, 4, 1>;
+using Tile32 = Tile<32, 32, 16, 1, 1>;
 
 // ---------------------------------------------------------------------------
 // Staging: rows [r0, r0+ROWS) x k-chunk [k0, k0+BK) of a row-major matrix with
@@ -179,8 +180,8 @@ __global__ __launch_bounds__(C::NT) void ttm_store_kernel(TtmArgs a) {
   const int b = blockIdx.y;
   d4 acc[C::TM][C::TN];
   zero_acc<C>(acc);
-  tile_nt<C>(a.E + b * a.es, a.X + b * a.xs, a.M, a.K, a.L, m0, n0, As, Bs, acc);
-  double* O = a.O + b * a.os;
+  tile_nt<C>(a.E + b * a.es, (const double*)a.X + b * a.xs, a.M, a.K, a.L, m0, n0, As, Bs, acc);
+  double* O = (double*)a.O + b * a.os;
 #pragma unroll
   for (int i = 0; i < C::TM; ++i)
 #pragma unroll
@@ -208,7 +209,7 @@ __global__ __launch_bounds__(C::NT) void ttm_accum_kernel(TtmArgs a) {
   for (int b = 0; b < a.nbatch; ++b) {
     d4 acc[C::TM][C::TN];
     zero_acc<C>(acc);
-    tile_nt<C>(a.E + b * a.es, a.X + b * a.xs, a.M, a.K, a.L, m0, n0, As, Bs, acc);
+    tile_nt<C>(a.E + b * a.es, (const double*)a.X + b * a.xs, a.M, a.K, a.L, m0, n0, As, Bs, acc);
 #pragma unroll
     for (int q = 0; q < PMAX; ++q) {
       if (q < a.np) {
@@ -250,10 +251,10 @@ __global__ __launch_bounds__(C::NT) void ttm_square_kernel(TtmArgs a) {
   const int b = blockIdx.y;
   d4 acc[C::TM][C::TN];
   zero_acc<C>(acc);
-  tile_nt<C>(a.E + b * a.es, a.X + b * a.xs, a.M, a.K, a.L, m0, n0, As, Bs, acc);
+  tile_nt<C>(a.E + b * a.es, (const double*)a.X + b * a.xs, a.M, a.K, a.L, m0, n0, As, Bs, acc);
   const int order = b + 1;
   const double scale = ldexp(1.0, -order);
-  double* O = a.O + b * a.os;
+  double* O = (double*)a.O + b * a.os;
 #pragma unroll
   for (int i = 0; i < C::TM; ++i)
 #pragma unroll
@@ -309,20 +310,27 @@ __global__ void scale_jobs_kernel(const ScaleJob* __restrict__ jobs) {
     jb.dst[i] = jb.s * jb.src[i];
 }
 
-// out = sum_{k=0}^{K} c^k/k! Z^k, Z^0 = I.  Terms are added from the highest
-// power down (smallest terms first).
-__global__ void taylor_jobs_kernel(const TaylorJob* __restrict__ jobs) {
-  const TaylorJob jb = jobs[blockIdx.y];
-  const long long nn = (long long)jb.n * jb.n;
-  double coef[33];
-  coef[0] = 1.0;
-  for (int k = 1; k <= jb.K; ++k) coef[k] = coef[k - 1] * jb.c / (double)k;
+// dst[t] = I + sum_{k=1}^{K} c_t^k/k! Z^k by Horner's rule in c_t:
+//   c (Z + c/2 (Z^2 + c/3 (Z^3 + ...))),
+// with the K powers of one element held in registers for all targets.
+__global__ __launch_bounds__(256) void taylor_jobs_kernel(const TaylorJob* __restrict__ jobs) {
+  const TaylorJob& jb = jobs[blockIdx.y];
+  const int n = jb.n, K = jb.K, nt = jb.nt;
+  const long long nn = (long long)n * n;
+  const double* __restrict__ Z = jb.Zpow;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nn; i += (long long)gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int k = jb.K; k >= 1; --k) s += coef[k] * jb.Zpow[(long long)(k - 1) * nn + i];
-    const long long r = i / jb.n, c = i % jb.n;
-    if (r == c) s += 1.0;
-    jb.out[i] = s;
+    double z[kMaxTaylorDegree];
+#pragma unroll
+    for (int k = 0; k < kMaxTaylorDegree; ++k) z[k] = (k < K) ? Z[k * nn + i] : 0.0;
+    const double diag = (i / n == i % n) ? 1.0 : 0.0;
+    for (int t = 0; t < nt; ++t) {
+      const double c = jb.c[t];
+      double s = 0.0;
+#pragma unroll
+      for (int k = kMaxTaylorDegree - 1; k >= 0; --k)
+        if (k < K) s = z[k] + s * (c * (1.0 / (double)(k + 2)));
+      jb.dst[t][i] = diag + c * s;
+    }
   }
 }
 
@@ -387,9 +395,16 @@ inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
 
 int launch_gemm_jobs(const GemmJob* jobs, int njobs, int nmax, void* stream) {
   if (njobs <= 0) return hipSuccess;
-  using C = Tile64;
-  dim3 grid(cdiv(nmax, C::BM), cdiv(nmax, C::BN), njobs);
-  hipLaunchKernelGGL(gemm_jobs_kernel<C>, grid, dim3(C::NT), 0, (hipStream_t)stream, jobs);
+  // few large-tile blocks would leave most CUs idle: use one-wave 32x32 tiles
+  if ((long long)njobs * cdiv(nmax, 64) * cdiv(nmax, 64) < 512) {
+    using C = Tile32;
+    dim3 grid(cdiv(nmax, C::BM), cdiv(nmax, C::BN), njobs);
+    hipLaunchKernelGGL(gemm_jobs_kernel<C>, grid, dim3(C::NT), 0, (hipStream_t)stream, jobs);
+  } else {
+    using C = Tile64;
+    dim3 grid(cdiv(nmax, C::BM), cdiv(nmax, C::BN), njobs);
+    hipLaunchKernelGGL(gemm_jobs_kernel<C>, grid, dim3(C::NT), 0, (hipStream_t)stream, jobs);
+  }
   return hipGetLastError();
 }
 
@@ -415,7 +430,7 @@ dim3 ttm_grid(const TtmArgs& a, int nb) {
 }  // namespace
 
 int launch_ttm_store(const TtmArgs& a, phiq_precision prec, void* stream) {
-  if (prec != PHIQ_PREC_FP64) return hipErrorInvalidValue;
+  if (prec != PHIQ_PREC_FP64) return launch_ttm_store_lowp(a, prec, stream);
   if (a.M > 64) {
     hipLaunchKernelGGL(ttm_store_kernel<Tile128>, ttm_grid<Tile128>(a, a.nbatch), dim3(Tile128::NT), 0,
                        (hipStream_t)stream, a);
@@ -427,14 +442,15 @@ int launch_ttm_store(const TtmArgs& a, phiq_precision prec, void* stream) {
 }
 
 int launch_ttm_accum(const TtmArgs& a, phiq_precision prec, void* stream) {
-  if (prec != PHIQ_PREC_FP64 || a.np > 4 || a.np < 1) return hipErrorInvalidValue;
+  if (a.np > 4 || a.np < 1) return hipErrorInvalidValue;
+  if (prec != PHIQ_PREC_FP64) return launch_ttm_accum_lowp(a, prec, stream);
   using C = Tile64;
   hipLaunchKernelGGL((ttm_accum_kernel<C, 4>), ttm_grid<C>(a, 1), dim3(C::NT), 0, (hipStream_t)stream, a);
   return hipGetLastError();
 }
 
 int launch_ttm_square(const TtmArgs& a, phiq_precision prec, void* stream) {
-  if (prec != PHIQ_PREC_FP64) return hipErrorInvalidValue;
+  if (prec != PHIQ_PREC_FP64) return launch_ttm_square_lowp(a, prec, stream);
   if (a.M > 64) {
     hipLaunchKernelGGL(ttm_square_kernel<Tile128>, ttm_grid<Tile128>(a, a.nbatch), dim3(Tile128::NT), 0,
                        (hipStream_t)stream, a);

@@ -42,27 +42,35 @@ struct ScaleJob {
   int pad_;
 };
 
-// out = sum_{k=0}^{K} c^k/k! Z^k with Z^0 = I and Z^k stored at
-// Zpow + (k-1) n^2 for k = 1..K (a truncated Taylor series of exp(c Z)).
+// dst[t] = sum_{k=0}^{K} c[t]^k/k! Z^k, t < nt, with Z^0 = I and Z^k stored at
+// Zpow + (k-1) n^2 for k = 1..K (truncated Taylor series of exp(c Z)); the
+// powers are read once per element for all nt coefficients.
+constexpr int kTaylorTargets = 16;
+constexpr int kMaxTaylorDegree = 32;
 struct TaylorJob {
   const double* Zpow;
-  double* out;
-  double c;
+  double* dst[kTaylorTargets];
+  double c[kTaylorTargets];
   int n;
   int K;
+  int nt;
 };
 
 // Mode product of a row-major (L x K) tensor view X with the M x K matrix
 // E (M = K = n_d), written rotated: out[i' * L + j] = sum_k E[i'][k] X[j][k].
 // Applying it once per axis, last axis first, returns the tensor to its
 // original layout after D steps.  Batch b uses E + b*es, X + b*xs, O + b*os.
+// X and O are FP64 for the FP64 path; with a lower precision the
+// intermediate tensors between mode products are FP32 (x_f32 / o_f32 say
+// which side is FP32; strides are in elements).
 struct TtmArgs {
   const double* E;
   long long es;
-  const double* X;
+  const void* X;
   long long xs;
-  double* O;
+  void* O;
   long long os;
+  int x_f32, o_f32;
   int M, K, L, nbatch;
   // node-sum epilogue: Y + j*ys = sum_b coef[j * ldcoef + b] * C_b, j < np
   const double* coef;
@@ -83,6 +91,10 @@ int launch_taylor_jobs(const TaylorJob* jobs_dev, int njobs, int nmax, void* str
 int launch_ttm_store(const TtmArgs& a, phiq_precision prec, void* stream);
 int launch_ttm_accum(const TtmArgs& a, phiq_precision prec, void* stream);
 int launch_ttm_square(const TtmArgs& a, phiq_precision prec, void* stream);
+// FP32-MFMA and split-bf16 (3-product) versions (kernels_lowp.hip)
+int launch_ttm_store_lowp(const TtmArgs& a, phiq_precision prec, void* stream);
+int launch_ttm_accum_lowp(const TtmArgs& a, phiq_precision prec, void* stream);
+int launch_ttm_square_lowp(const TtmArgs& a, phiq_precision prec, void* stream);
 
 // CC error: partial maxima of |y_j - yold_j| and |y_j| over blocks.
 // partial[(blk * np + j) * 2 + {0, 1}] = block maxima of |y_j - yold_j|, |y_j|
