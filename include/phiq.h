@@ -213,8 +213,29 @@ typedef struct {
   double bytes;    /* algorithmic bytes (compulsory reads + writes)       */
 } phiq_kernel_stat;
 
-phiq_status phiq_profile_start(phiq_handle h);
+/* class_mask: bit c set = bracket launches of class c (order above:
+ * bit 0 ttm_store, 1 ttm_accum, 2 ttm_square, 3 gemm, 4 taylor, 5 scale,
+ * 6 node_sum, 7 absdiff); 0 = all classes.  Each bracket adds a little
+ * time to the stream, so timing only the classes of interest keeps the
+ * rest of the work undisturbed. */
+phiq_status phiq_profile_start(phiq_handle h, unsigned class_mask);
 phiq_status phiq_profile_stop(phiq_handle h, phiq_kernel_stat* stats, int max_stats, int* n_stats);
+
+/* ---------------------------------------------------------------------------
+ * Autotuner.
+ *
+ * Times every tile shape of the FP64 mode-product kernels on the launch
+ * shapes a phi-action with these sizes makes (dim axes of sizes n[d], p
+ * orders, m quadrature nodes: node products with m+1 batches, squaring
+ * products with p batches, the fused node sum and the fused squaring step)
+ * and keeps the fastest shape per launch shape in the handle; later calls
+ * with those shapes use it.  Synchronises the stream.  times may be NULL or
+ * HOST [64][8]: row r = launch shape r in the order above, column c = the
+ * time in ms of tile shape c (rows and columns that do not exist are left
+ * untouched).  The workspace contents are overwritten.
+ * ------------------------------------------------------------------------ */
+phiq_status phiq_autotune(phiq_handle h, int dim, const int* n, int p, int m, double* times,
+                          hipStream_t stream);
 
 #ifdef __cplusplus
 }

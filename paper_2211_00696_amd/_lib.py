@@ -20,6 +20,7 @@ STATUS = {
     -6: "PHIQ_ERR_UNSUPPORTED",
 }
 RULE = {"gauss": 1, "cc": 2}
+PROFILE_CLASSES = ["ttm_store", "ttm_accum", "ttm_square", "gemm", "taylor", "scale", "node_sum", "absdiff"]
 PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 
 # Every symbol include/phiq.h declares.
@@ -40,6 +41,7 @@ EXPORTS = [
     "phiq_kron_apply",
     "phiq_profile_start",
     "phiq_profile_stop",
+    "phiq_autotune",
 ]
 
 
@@ -113,8 +115,9 @@ def load():
         "phiq_expm": (c_int, [c_void_p, c_int, c_int, c_void_p, P(c_double), c_void_p, c_void_p]),
         "phiq_kron_apply": (c_int, [c_void_p, c_int, P(c_int), P(c_void_p), c_void_p, c_void_p, c_int, c_int,
                                     c_void_p]),
-        "phiq_profile_start": (c_int, [c_void_p]),
+        "phiq_profile_start": (c_int, [c_void_p, ctypes.c_uint]),
         "phiq_profile_stop": (c_int, [c_void_p, P(KernelStat), c_int, P(c_int)]),
+        "phiq_autotune": (c_int, [c_void_p, c_int, P(c_int), c_int, c_int, P(c_double), c_void_p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -114,6 +114,7 @@ struct ProfRec {
 
 struct Profiler {
   bool on = false;
+  unsigned mask = ~0u;
   std::vector<ProfRec> recs;
   std::vector<hipEvent_t> pool;
   size_t next = 0;
@@ -123,9 +124,14 @@ static const char* const kProfClass[] = {"ttm_store", "ttm_accum", "ttm_square",
                                          "taylor",    "scale",     "node_sum",   "absdiff"};
 enum ProfClass { K_TTM_STORE = 0, K_TTM_ACCUM, K_TTM_SQUARE, K_GEMM, K_TAYLOR, K_SCALE, K_NODE_SUM, K_ABSDIFF, K_NCLASS };
 
+struct TuneEntry {
+  int kind, M, L, nb, cfg;
+};
+
 struct phiq_handle_s {
   int device = 0;
   Profiler prof;
+  std::vector<TuneEntry> tune;  // fastest tile shape per launch shape (autotuner)
   DevBuf ws;                     // execute workspace (T0, T1, Ya, Yb)
   DevBuf scratch;                // transient plans (phiq_action) and phiq_expm
   std::vector<DevBuf> cc_levels; // node vectors of the adaptive rule, per level
@@ -203,13 +209,14 @@ hipEvent_t prof_event(phiq_handle h) {
 template <class F>
 phiq_status prof_launch(phiq_handle h, hipStream_t st, int cls, double flops, double bytes, F&& f) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (h->prof.on) {
+  const bool rec = h->prof.on && ((h->prof.mask >> cls) & 1u);
+  if (rec) {
     e0 = prof_event(h);
     e1 = prof_event(h);
     if (e0) (void)hipEventRecord(e0, st);
   }
   if (f() != hipSuccess) return PHIQ_ERR_HIP;
-  if (h->prof.on && e0 && e1) {
+  if (rec && e0 && e1) {
     (void)hipEventRecord(e1, st);
     h->prof.recs.push_back({cls, e0, e1, flops, bytes});
   }
@@ -230,14 +237,33 @@ void ttm_work(const TtmArgs& a, int cls, double* flops, double* bytes) {
   *bytes = xb * xin + ob * out + 8.0 * (extra + (double)a.nbatch * a.M * a.K * (a.es == 0 ? 0.0 : 1.0));
 }
 
-phiq_status L_ttm(phiq_handle h, int cls, const TtmArgs& a, phiq_precision prec, hipStream_t st) {
+int tuned_cfg(phiq_handle h, int kind, const TtmArgs& a) {
+  const int nb = (kind == 1) ? 1 : a.nbatch;
+  for (const auto& e : h->tune)
+    if (e.kind == kind && e.M == a.M && e.L == a.L && e.nb == nb) return e.cfg;
+  return -1;
+}
+
+int launch_kind(int kind, const TtmArgs& a, phiq_precision prec, hipStream_t st, int cfg) {
+  if (kind == 1) return launch_ttm_accum(a, prec, st, cfg);
+  if (kind == 2) return launch_ttm_square(a, prec, st, cfg);
+  return launch_ttm_store(a, prec, st, cfg);
+}
+
+int kind_of(int cls) { return cls == K_TTM_ACCUM ? 1 : (cls == K_TTM_SQUARE ? 2 : 0); }
+
+phiq_status L_ttm(phiq_handle h, int cls, const TtmArgs& a0, phiq_precision prec, hipStream_t st) {
   double fl, by;
+  TtmArgs a = a0;
+  double f = 1.0;
+  for (int k = 0; k <= PHIQ_MAX_P; ++k) {
+    a.ifact[k] = 1.0 / f;
+    f *= (k + 1);
+  }
   ttm_work(a, cls, &fl, &by);
-  return prof_launch(h, st, cls, fl, by, [&] {
-    if (cls == K_TTM_ACCUM) return launch_ttm_accum(a, prec, st);
-    if (cls == K_TTM_SQUARE) return launch_ttm_square(a, prec, st);
-    return launch_ttm_store(a, prec, st);
-  });
+  const int kind = kind_of(cls);
+  const int cfg = (prec == PHIQ_PREC_FP64) ? tuned_cfg(h, kind, a) : -1;
+  return prof_launch(h, st, cls, fl, by, [&] { return launch_kind(kind, a, prec, st, cfg); });
 }
 
 phiq_status L_gemm(phiq_handle h, const GemmJob* jobs, int njobs, int nm, hipStream_t st) {
@@ -1283,8 +1309,9 @@ phiq_status phiq_expm(phiq_handle h, int n, int nmat, const double* X, const dou
   return PHIQ_OK;
 }
 
-phiq_status phiq_profile_start(phiq_handle h) {
+phiq_status phiq_profile_start(phiq_handle h, unsigned class_mask) {
   if (!h) return PHIQ_ERR_INVALID_ARG;
+  h->prof.mask = class_mask ? class_mask : ~0u;
   h->prof.recs.clear();
   h->prof.next = 0;
   h->prof.on = true;
@@ -1316,6 +1343,103 @@ phiq_status phiq_profile_stop(phiq_handle h, phiq_kernel_stat* stats, int max_st
       ++k;
     }
   if (n_stats) *n_stats = std::min(k, max_stats);
+  return PHIQ_OK;
+}
+
+phiq_status phiq_autotune(phiq_handle h, int dim, const int* n, int p, int m, double* times, hipStream_t st) {
+  if (!h || !n || dim < 1 || dim > PHIQ_MAX_DIM || p < 0 || p > PHIQ_MAX_P || m < 1 || m > 4096)
+    return PHIQ_ERR_INVALID_ARG;
+  long long N = 1;
+  for (int d = 0; d < dim; ++d) {
+    if (n[d] < 1 || n[d] > PHIQ_MAX_N) return PHIQ_ERR_INVALID_ARG;
+    N *= n[d];
+  }
+  DeviceGuard g(h->device);
+  const int nbmax = std::max(m + 1, std::max(p, 1));
+  const size_t tb = align_up((size_t)nbmax * N * sizeof(double));
+  const size_t eb = align_up((size_t)nbmax * PHIQ_MAX_N * PHIQ_MAX_N / 16 * sizeof(double));
+  size_t emax = 0;
+  for (int d = 0; d < dim; ++d) emax = std::max(emax, (size_t)nbmax * n[d] * n[d] * sizeof(double));
+  const size_t need = 2 * tb + align_up(emax) + align_up((size_t)4 * nbmax * sizeof(double));
+  (void)eb;
+  PHIQ_TRY(ensure(h, h->ws, need));
+  char* wb = (char*)h->ws.p;
+  PHIQ_HIP(hipMemsetAsync(wb, 0, need, st));
+  double* X = (double*)wb;
+  double* O = (double*)(wb + tb);
+  double* E = (double*)(wb + 2 * tb);
+  double* coef = (double*)(wb + 2 * tb + align_up(emax));
+  hipEvent_t e0, e1;
+  PHIQ_HIP(hipEventCreate(&e0));
+  PHIQ_HIP(hipEventCreate(&e1));
+  // the launch shapes of a phi-action: store (nodes + phi_0, and p RHS),
+  // node sum, squaring; every axis in turn is the contracted one
+  struct Shape {
+    int kind, M, L, nb;
+  };
+  std::vector<Shape> shapes;
+  for (int d = 0; d < dim; ++d) {
+    const int L = (int)(N / n[d]);
+    shapes.push_back({0, n[d], L, m + 1});
+    if (p > 0) shapes.push_back({0, n[d], L, p});
+    if (d == 0 && p > 0) {
+      shapes.push_back({1, n[d], L, m});
+      shapes.push_back({2, n[d], L, p});
+    }
+  }
+  int ti = 0;
+  for (const auto& sh : shapes) {
+    TtmArgs a{};
+    a.E = E;
+    a.es = 0;
+    a.X = X;
+    a.xs = N;
+    a.O = O;
+    a.os = N;
+    a.M = a.K = sh.M;
+    a.L = sh.L;
+    a.nbatch = sh.nb;
+    a.coef = coef;
+    a.ldcoef = sh.nb;
+    a.np = std::min(4, std::max(1, p));
+    a.Y = O;
+    a.ys = N;
+    a.Yprev = X;
+    a.yps = N;
+    for (int k = 0; k <= PHIQ_MAX_P; ++k) a.ifact[k] = 1.0;
+    int best = -1;
+    float best_ms = 1e30f;
+    for (int c = 0; c < ttm_num_configs(sh.kind); ++c) {
+      if (launch_kind(sh.kind, a, PHIQ_PREC_FP64, st, c) != hipSuccess) continue;  // warm-up
+      PHIQ_HIP(hipEventRecord(e0, st));
+      const int reps = 3;
+      for (int r = 0; r < reps; ++r)
+        if (launch_kind(sh.kind, a, PHIQ_PREC_FP64, st, c) != hipSuccess) return PHIQ_ERR_HIP;
+      PHIQ_HIP(hipEventRecord(e1, st));
+      PHIQ_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      PHIQ_HIP(hipEventElapsedTime(&ms, e0, e1));
+      ms /= reps;
+      if (times && ti < 64) times[ti * 8 + c] = ms;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = c;
+      }
+    }
+    if (best >= 0) {
+      const int nbk = sh.kind == 1 ? 1 : sh.nb;
+      bool found = false;
+      for (auto& e : h->tune)
+        if (e.kind == sh.kind && e.M == sh.M && e.L == sh.L && e.nb == nbk) {
+          e.cfg = best;
+          found = true;
+        }
+      if (!found) h->tune.push_back({sh.kind, sh.M, sh.L, nbk, best});
+    }
+    ++ti;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   return PHIQ_OK;
 }
 

@@ -30,30 +30,69 @@ struct Tile {
 
 using Tile64 = Tile<64, 64, 16, 2, 2>;
 using Tile128 = Tile<128, 64, 16, 2, 2>;
+using Tile128x128 = Tile<128, 128, 16, 2, 2>;
 using Tile256 = Tile<256, 64, 16, 4, 1>;
+using Tile128k32 = Tile<128, 64, 32, 2, 2>;
+using Tile64x128 = Tile<64, 128, 16, 2, 2>;
+using Tile64k32 = Tile<64, 64, 32, 2, 2>;
 using Tile32 = Tile<32, 32, 16, 1, 1>;
 
 // ---------------------------------------------------------------------------
-// Staging: rows [r0, r0+ROWS) x k-chunk [k0, k0+BK) of a row-major matrix with
-// row length ld (k contiguous), zero outside (rows_valid, k_valid).
+// Staging of rows [r0, r0+ROWS) x k-chunk [k0, k0+BK) of a row-major matrix
+// with row length ld (k contiguous).
+//
+// Loads are branch-free and select nothing: lanes outside (rows_valid,
+// k_valid) read a clamped in-range address, so a load's result is first
+// needed when it is written to LDS one chunk later and the prefetch stays in
+// flight during the MFMA work.  Rows past the end only feed outputs that are
+// never stored; past the end of k the E operand is zeroed at the LDS store
+// (ZK), which makes those products vanish whatever the X operand holds.
+// With VEC (ld and k_valid even, 16-byte aligned base) lanes move pairs.
 // ---------------------------------------------------------------------------
-template <int ROWS, int BK, int NT, int PER>
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+template <int ROWS, int BK, int NT, int PER, bool VEC>
 __device__ __forceinline__ void load_kmajor(const double* __restrict__ g, long long ld, int r0,
                                             int rows_valid, int k0, int k_valid, double (&reg)[PER]) {
+  if constexpr (VEC) {
 #pragma unroll
-  for (int i = 0; i < PER; ++i) {
-    const int e = threadIdx.x + i * NT;
-    const int r = e / BK, kk = e % BK;
-    const int row = r0 + r, k = k0 + kk;
-    reg[i] = (row < rows_valid && k < k_valid) ? g[(long long)row * ld + k] : 0.0;
+    for (int i = 0; i < PER / 2; ++i) {
+      const int e = threadIdx.x + i * NT;
+      const int row = r0 + e / (BK / 2), k = k0 + 2 * (e % (BK / 2));
+      const int rc = row < rows_valid ? row : rows_valid - 1;
+      const int kc = k < k_valid ? k : 0;
+      const d2 v = *(const d2*)(g + (long long)rc * ld + kc);
+      reg[2 * i] = v.x;
+      reg[2 * i + 1] = v.y;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = threadIdx.x + i * NT;
+      const int row = r0 + e / BK, k = k0 + e % BK;
+      const int rc = row < rows_valid ? row : rows_valid - 1;
+      const int kc = k < k_valid ? k : 0;
+      reg[i] = g[(long long)rc * ld + kc];
+    }
   }
 }
-template <int BK, int NT, int PER, int LDK>
-__device__ __forceinline__ void store_kmajor(double* s, const double (&reg)[PER]) {
+template <int BK, int NT, int PER, int LDK, bool VEC, bool ZK>
+__device__ __forceinline__ void store_kmajor(double* s, const double (&reg)[PER], int k0, int k_valid) {
+  if constexpr (VEC) {
 #pragma unroll
-  for (int i = 0; i < PER; ++i) {
-    const int e = threadIdx.x + i * NT;
-    s[(e / BK) * LDK + (e % BK)] = reg[i];
+    for (int i = 0; i < PER / 2; ++i) {
+      const int e = threadIdx.x + i * NT;
+      const int r = e / (BK / 2), kk = 2 * (e % (BK / 2));
+      const bool ok = !ZK || k0 + kk < k_valid;
+      *(d2*)(s + r * LDK + kk) = ok ? (d2){reg[2 * i], reg[2 * i + 1]} : (d2){0.0, 0.0};
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = threadIdx.x + i * NT;
+      const bool ok = !ZK || k0 + e % BK < k_valid;
+      s[(e / BK) * LDK + (e % BK)] = ok ? reg[i] : 0.0;
+    }
   }
 }
 // Rows of B are k (n contiguous in global): element (kk, c) of the chunk is
@@ -66,7 +105,9 @@ __device__ __forceinline__ void load_nmajor(const double* __restrict__ g, long l
     const int e = threadIdx.x + i * NT;
     const int kk = e / COLS, c = e % COLS;
     const int k = k0 + kk, col = c0 + c;
-    reg[i] = (col < cols_valid && k < k_valid) ? g[(long long)k * ld + col] : 0.0;
+    const bool ok = col < cols_valid && k < k_valid;
+    const double v = g[(long long)(ok ? k : 0) * ld + (ok ? col : 0)];
+    reg[i] = ok ? v : 0.0;
   }
 }
 template <int COLS, int NT, int PER, int LDK>
@@ -106,41 +147,20 @@ __device__ __forceinline__ void mma_chunk(const double* As, const double* Bs, d4
   }
 }
 
-// acc += E[m0:m0+BM, :] * X[n0:n0+BN, :]^T  (E: M x K, X: L x K, both k-contiguous)
-template <class C>
-__device__ __forceinline__ void tile_nt(const double* __restrict__ E, const double* __restrict__ X, int M,
-                                        int K, int L, int m0, int n0, double* As, double* Bs,
-                                        d4 (&acc)[C::TM][C::TN]) {
-  double ra[C::A_PER], rb[C::B_PER];
-  load_kmajor<C::BM, C::BK, C::NT, C::A_PER>(E, K, m0, M, 0, K, ra);
-  load_kmajor<C::BN, C::BK, C::NT, C::B_PER>(X, K, n0, L, 0, K, rb);
-  for (int k0 = 0; k0 < K; k0 += C::BK) {
-    __syncthreads();
-    store_kmajor<C::BK, C::NT, C::A_PER, C::LDK>(As, ra);
-    store_kmajor<C::BK, C::NT, C::B_PER, C::LDK>(Bs, rb);
-    __syncthreads();
-    if (k0 + C::BK < K) {
-      load_kmajor<C::BM, C::BK, C::NT, C::A_PER>(E, K, m0, M, k0 + C::BK, K, ra);
-      load_kmajor<C::BN, C::BK, C::NT, C::B_PER>(X, K, n0, L, k0 + C::BK, K, rb);
-    }
-    mma_chunk<C>(As, Bs, acc);
-  }
-}
-
 // acc += A[m0:m0+BM, :] * B[:, n0:n0+BN]  (A: n x n, B: n x n, row-major)
 template <class C>
 __device__ __forceinline__ void tile_nn(const double* __restrict__ A, const double* __restrict__ B, int n,
                                         int m0, int n0, double* As, double* Bs, d4 (&acc)[C::TM][C::TN]) {
   double ra[C::A_PER], rb[C::B_PER];
-  load_kmajor<C::BM, C::BK, C::NT, C::A_PER>(A, n, m0, n, 0, n, ra);
+  load_kmajor<C::BM, C::BK, C::NT, C::A_PER, false>(A, n, m0, n, 0, n, ra);
   load_nmajor<C::BN, C::BK, C::NT, C::B_PER>(B, n, n0, n, 0, n, rb);
   for (int k0 = 0; k0 < n; k0 += C::BK) {
     __syncthreads();
-    store_kmajor<C::BK, C::NT, C::A_PER, C::LDK>(As, ra);
+    store_kmajor<C::BK, C::NT, C::A_PER, C::LDK, false, true>(As, ra, k0, n);
     store_nmajor<C::BN, C::NT, C::B_PER, C::LDK>(Bs, rb);
     __syncthreads();
     if (k0 + C::BK < n) {
-      load_kmajor<C::BM, C::BK, C::NT, C::A_PER>(A, n, m0, n, k0 + C::BK, n, ra);
+      load_kmajor<C::BM, C::BK, C::NT, C::A_PER, false>(A, n, m0, n, k0 + C::BK, n, ra);
       load_nmajor<C::BN, C::BK, C::NT, C::B_PER>(B, n, n0, n, k0 + C::BK, n, rb);
     }
     mma_chunk<C>(As, Bs, acc);
@@ -161,26 +181,79 @@ __device__ __forceinline__ int acc_col(int j) {
 
 // ---------------------------------------------------------------------------
 // Mode products (rotated layout), three epilogues.
-// grid: x = (L tile, M tile) with the M tile fastest, so the blocks that read
-// the same X tile are adjacent; y = batch (store / square) or 1 (node sum)
+//
+// Main loop: register prefetch two chunks ahead and a double-buffered LDS
+// tile, one barrier per K-chunk.  Blocks are mapped to tiles XCD-aware: the
+// hardware deals consecutive block ids round-robin to the 8 XCDs, so block b
+// takes tile (b % 8) * ceil(T/8) + b / 8 and the M-tiles of one column block
+// (which read the same X rows) share an XCD's L2.
 // ---------------------------------------------------------------------------
-template <class C>
-__device__ __forceinline__ void tile_origin(int M, int& m0, int& n0) {
-  const int mtiles = (M + C::BM - 1) / C::BM;
-  m0 = (blockIdx.x % mtiles) * C::BM;
-  n0 = (blockIdx.x / mtiles) * C::BN;
+constexpr int kXcds = 8;
+
+template <class C, bool VEC>
+__device__ __forceinline__ void tile_nt_db(const double* __restrict__ E, const double* __restrict__ X, int M, int K,
+                                           int L, int m0, int n0, double* smem, d4 (&acc)[C::TM][C::TN]) {
+  constexpr int STAGE = (C::BM + C::BN) * C::LDK;
+  double ra[C::A_PER], rb[C::B_PER];
+  const int nch = (K + C::BK - 1) / C::BK;
+  load_kmajor<C::BM, C::BK, C::NT, C::A_PER, VEC>(E, K, m0, M, 0, K, ra);
+  load_kmajor<C::BN, C::BK, C::NT, C::B_PER, VEC>(X, K, n0, L, 0, K, rb);
+  store_kmajor<C::BK, C::NT, C::A_PER, C::LDK, VEC, true>(smem, ra, 0, K);
+  store_kmajor<C::BK, C::NT, C::B_PER, C::LDK, VEC, false>(smem + C::BM * C::LDK, rb, 0, K);
+  if (nch > 1) {
+    load_kmajor<C::BM, C::BK, C::NT, C::A_PER, VEC>(E, K, m0, M, C::BK, K, ra);
+    load_kmajor<C::BN, C::BK, C::NT, C::B_PER, VEC>(X, K, n0, L, C::BK, K, rb);
+  }
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    double* cur = smem + (c & 1) * STAGE;
+    double* nxt = smem + ((c + 1) & 1) * STAGE;
+    if (c + 1 < nch) {
+      // readers of nxt (chunk c-1) passed the barrier at the end of c-1
+      store_kmajor<C::BK, C::NT, C::A_PER, C::LDK, VEC, true>(nxt, ra, (c + 1) * C::BK, K);
+      store_kmajor<C::BK, C::NT, C::B_PER, C::LDK, VEC, false>(nxt + C::BM * C::LDK, rb, (c + 1) * C::BK, K);
+      if (c + 2 < nch) {
+        load_kmajor<C::BM, C::BK, C::NT, C::A_PER, VEC>(E, K, m0, M, (c + 2) * C::BK, K, ra);
+        load_kmajor<C::BN, C::BK, C::NT, C::B_PER, VEC>(X, K, n0, L, (c + 2) * C::BK, K, rb);
+      }
+    }
+    mma_chunk<C>(cur, cur + C::BM * C::LDK, acc);
+    __syncthreads();
+  }
 }
 
 template <class C>
+__host__ __device__ inline long long ttm_tiles(int M, int L, int nb) {
+  return (long long)((M + C::BM - 1) / C::BM) * ((L + C::BN - 1) / C::BN) * nb;
+}
+
+// Tile of this block: returns false for the padding blocks of the last XCD.
+// Tiles are numbered (M tile, batch, column block), M tile fastest.
+template <class C>
+__device__ __forceinline__ bool tile_of_block(int M, int L, int nb, int& m0, int& n0, int& b) {
+  const long long T = ttm_tiles<C>(M, L, nb);
+  const long long per = (T + kXcds - 1) / kXcds;
+  const long long t = (long long)(blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+  if (t >= T) return false;
+  // M tile fastest, then batch, then column block: the blocks that share an
+  // X tile (M tiles; batches when X is shared) or the y_j tiles read by the
+  // squaring epilogue run back to back on one XCD
+  const int mtiles = (M + C::BM - 1) / C::BM;
+  m0 = (int)(t % mtiles) * C::BM;
+  const long long r = t / mtiles;
+  b = (int)(r % nb);
+  n0 = (int)(r / nb) * C::BN;
+  return true;
+}
+
+template <class C, bool VEC>
 __global__ __launch_bounds__(C::NT) void ttm_store_kernel(TtmArgs a) {
-  __shared__ double As[C::BM * C::LDK];
-  __shared__ double Bs[C::BN * C::LDK];
-  int m0, n0;
-  tile_origin<C>(a.M, m0, n0);
-  const int b = blockIdx.y;
+  __shared__ double smem[2 * (C::BM + C::BN) * C::LDK];
+  int m0, n0, b;
+  if (!tile_of_block<C>(a.M, a.L, a.nbatch, m0, n0, b)) return;
   d4 acc[C::TM][C::TN];
   zero_acc<C>(acc);
-  tile_nt<C>(a.E + b * a.es, (const double*)a.X + b * a.xs, a.M, a.K, a.L, m0, n0, As, Bs, acc);
+  tile_nt_db<C, VEC>(a.E + b * a.es, (const double*)a.X + b * a.xs, a.M, a.K, a.L, m0, n0, smem, acc);
   double* O = (double*)a.O + b * a.os;
 #pragma unroll
   for (int i = 0; i < C::TM; ++i)
@@ -196,62 +269,55 @@ __global__ __launch_bounds__(C::NT) void ttm_store_kernel(TtmArgs a) {
 }
 
 // Node sum fused into the last mode product: every block loops over all
-// nodes b and keeps np <= PMAX running sums in registers.
-template <class C, int PMAX>
+// nodes b and keeps the NP running sums in registers.
+template <class C, int NP, bool VEC>
 __global__ __launch_bounds__(C::NT) void ttm_accum_kernel(TtmArgs a) {
-  __shared__ double As[C::BM * C::LDK];
-  __shared__ double Bs[C::BN * C::LDK];
-  int m0, n0;
-  tile_origin<C>(a.M, m0, n0);
-  d4 y[PMAX][C::TM][C::TN];
+  __shared__ double smem[2 * (C::BM + C::BN) * C::LDK];
+  int m0, n0, bb;
+  if (!tile_of_block<C>(a.M, a.L, 1, m0, n0, bb)) return;
+  d4 y[NP][C::TM][C::TN];
 #pragma unroll
-  for (int q = 0; q < PMAX; ++q) zero_acc<C>(y[q]);
+  for (int q = 0; q < NP; ++q) zero_acc<C>(y[q]);
   for (int b = 0; b < a.nbatch; ++b) {
     d4 acc[C::TM][C::TN];
     zero_acc<C>(acc);
-    tile_nt<C>(a.E + b * a.es, (const double*)a.X + b * a.xs, a.M, a.K, a.L, m0, n0, As, Bs, acc);
+    tile_nt_db<C, VEC>(a.E + b * a.es, (const double*)a.X + b * a.xs, a.M, a.K, a.L, m0, n0, smem, acc);
 #pragma unroll
-    for (int q = 0; q < PMAX; ++q) {
-      if (q < a.np) {
-        const double w = a.coef[q * a.ldcoef + b];
-#pragma unroll
-        for (int i = 0; i < C::TM; ++i)
-#pragma unroll
-          for (int j = 0; j < C::TN; ++j) y[q][i][j] += w * acc[i][j];
-      }
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < PMAX; ++q) {
-    if (q < a.np) {
-      double* Y = a.Y + q * a.ys;
+    for (int q = 0; q < NP; ++q) {
+      const double w = a.coef[q * a.ldcoef + b];
 #pragma unroll
       for (int i = 0; i < C::TM; ++i)
 #pragma unroll
-        for (int j = 0; j < C::TN; ++j) {
-          const int col = n0 + acc_col<C>(j);
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int row = m0 + acc_row<C>(i, e);
-            if (row < a.M && col < a.L) Y[(long long)row * a.L + col] = y[q][i][j][e];
-          }
-        }
+        for (int j = 0; j < C::TN; ++j) y[q][i][j] += w * acc[i][j];
     }
+  }
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    double* Y = a.Y + q * a.ys;
+#pragma unroll
+    for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+      for (int j = 0; j < C::TN; ++j) {
+        const int col = n0 + acc_col<C>(j);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int row = m0 + acc_row<C>(i, e);
+          if (row < a.M && col < a.L) Y[(long long)row * a.L + col] = y[q][i][j][e];
+        }
+      }
   }
 }
 
 // Modified squaring fused into the last mode product (eq. squaring):
 // batch b is order i = b+1, out = 2^{-i} (E y_i + sum_{j=1}^{i} y_j/(i-j)!).
-template <class C>
+template <class C, bool VEC>
 __global__ __launch_bounds__(C::NT) void ttm_square_kernel(TtmArgs a) {
-  __shared__ double As[C::BM * C::LDK];
-  __shared__ double Bs[C::BN * C::LDK];
-  int m0, n0;
-  tile_origin<C>(a.M, m0, n0);
-  const int b = blockIdx.y;
+  __shared__ double smem[2 * (C::BM + C::BN) * C::LDK];
+  int m0, n0, b;
+  if (!tile_of_block<C>(a.M, a.L, a.nbatch, m0, n0, b)) return;
   d4 acc[C::TM][C::TN];
   zero_acc<C>(acc);
-  tile_nt<C>(a.E + b * a.es, (const double*)a.X + b * a.xs, a.M, a.K, a.L, m0, n0, As, Bs, acc);
+  tile_nt_db<C, VEC>(a.E + b * a.es, (const double*)a.X + b * a.xs, a.M, a.K, a.L, m0, n0, smem, acc);
   const int order = b + 1;
   const double scale = ldexp(1.0, -order);
   double* O = (double*)a.O + b * a.os;
@@ -266,11 +332,7 @@ __global__ __launch_bounds__(C::NT) void ttm_square_kernel(TtmArgs a) {
         if (row < a.M && col < a.L) {
           const long long idx = (long long)row * a.L + col;
           double s = acc[i][j][e];
-          double inv_fact = 1.0;  // 1/(i-j)! for j = i, i-1, ..., 1
-          for (int jj = order; jj >= 1; --jj) {
-            s += a.Yprev[(jj - 1) * a.yps + idx] * inv_fact;
-            inv_fact /= (double)(order - jj + 1);
-          }
+          for (int jj = 1; jj <= order; ++jj) s += a.Yprev[(jj - 1) * a.yps + idx] * a.ifact[order - jj];
           O[idx] = scale * s;
         }
       }
@@ -425,40 +487,103 @@ int launch_taylor_jobs(const TaylorJob* jobs, int njobs, int nmax, void* stream)
 namespace {
 template <class C>
 dim3 ttm_grid(const TtmArgs& a, int nb) {
-  return dim3((unsigned)cdiv(a.M, C::BM) * (unsigned)cdiv(a.L, C::BN), nb, 1);
+  const long long T = ttm_tiles<C>(a.M, a.L, nb);
+  return dim3((unsigned)(((T + kXcds - 1) / kXcds) * kXcds), 1, 1);
+}
+
+// 16-byte vector loads need even row lengths and 16-byte aligned operands
+bool vec_ok(const TtmArgs& a) {
+  return (a.K % 2 == 0) && (((uintptr_t)a.E | (uintptr_t)a.X) % 16 == 0) && (a.es % 2 == 0) && (a.xs % 2 == 0);
+}
+
+template <class C>
+int store_cfg(const TtmArgs& a, hipStream_t st) {
+  if (vec_ok(a))
+    hipLaunchKernelGGL((ttm_store_kernel<C, true>), ttm_grid<C>(a, a.nbatch), dim3(C::NT), 0, st, a);
+  else
+    hipLaunchKernelGGL((ttm_store_kernel<C, false>), ttm_grid<C>(a, a.nbatch), dim3(C::NT), 0, st, a);
+  return hipGetLastError();
+}
+template <class C>
+int square_cfg(const TtmArgs& a, hipStream_t st) {
+  if (vec_ok(a))
+    hipLaunchKernelGGL((ttm_square_kernel<C, true>), ttm_grid<C>(a, a.nbatch), dim3(C::NT), 0, st, a);
+  else
+    hipLaunchKernelGGL((ttm_square_kernel<C, false>), ttm_grid<C>(a, a.nbatch), dim3(C::NT), 0, st, a);
+  return hipGetLastError();
+}
+template <class C, bool VEC>
+int accum_np(const TtmArgs& a, hipStream_t st) {
+  const dim3 g = ttm_grid<C>(a, 1);
+  switch (a.np) {
+    case 1: hipLaunchKernelGGL((ttm_accum_kernel<C, 1, VEC>), g, dim3(C::NT), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((ttm_accum_kernel<C, 2, VEC>), g, dim3(C::NT), 0, st, a); break;
+    case 3: hipLaunchKernelGGL((ttm_accum_kernel<C, 3, VEC>), g, dim3(C::NT), 0, st, a); break;
+    default: hipLaunchKernelGGL((ttm_accum_kernel<C, 4, VEC>), g, dim3(C::NT), 0, st, a); break;
+  }
+  return hipGetLastError();
+}
+template <class C>
+int accum_cfg(const TtmArgs& a, hipStream_t st) {
+  return vec_ok(a) ? accum_np<C, true>(a, st) : accum_np<C, false>(a, st);
+}
+
+// default tile choice when no tuned entry exists (from sweeps on gfx950 at
+// n = 32, 128, 256: 64 x 128 tiles for the stores, 64 x 64 with 32-deep K
+// chunks for small n and for the node sum, 64 x 64 for the squaring step)
+int default_cfg(int kind, int M) {
+  if (kind == 1) return 3;
+  if (kind == 2) return 0;
+  return M >= 128 ? 5 : 6;
 }
 }  // namespace
 
-int launch_ttm_store(const TtmArgs& a, phiq_precision prec, void* stream) {
+int ttm_num_configs(int kind) { return kind == 1 ? 4 : 7; }
+
+int launch_ttm_store(const TtmArgs& a, phiq_precision prec, void* stream, int cfg) {
   if (prec != PHIQ_PREC_FP64) return launch_ttm_store_lowp(a, prec, stream);
-  if (a.M > 64) {
-    hipLaunchKernelGGL(ttm_store_kernel<Tile128>, ttm_grid<Tile128>(a, a.nbatch), dim3(Tile128::NT), 0,
-                       (hipStream_t)stream, a);
-  } else {
-    hipLaunchKernelGGL(ttm_store_kernel<Tile64>, ttm_grid<Tile64>(a, a.nbatch), dim3(Tile64::NT), 0,
-                       (hipStream_t)stream, a);
+  hipStream_t st = (hipStream_t)stream;
+  if (cfg < 0) cfg = default_cfg(0, a.M);
+  switch (cfg) {
+    case 0: return store_cfg<Tile64>(a, st);
+    case 1: return store_cfg<Tile128>(a, st);
+    case 2: return store_cfg<Tile128x128>(a, st);
+    case 3: return store_cfg<Tile256>(a, st);
+    case 4: return store_cfg<Tile128k32>(a, st);
+    case 5: return store_cfg<Tile64x128>(a, st);
+    case 6: return store_cfg<Tile64k32>(a, st);
   }
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
-int launch_ttm_accum(const TtmArgs& a, phiq_precision prec, void* stream) {
+int launch_ttm_accum(const TtmArgs& a, phiq_precision prec, void* stream, int cfg) {
   if (a.np > 4 || a.np < 1) return hipErrorInvalidValue;
   if (prec != PHIQ_PREC_FP64) return launch_ttm_accum_lowp(a, prec, stream);
-  using C = Tile64;
-  hipLaunchKernelGGL((ttm_accum_kernel<C, 4>), ttm_grid<C>(a, 1), dim3(C::NT), 0, (hipStream_t)stream, a);
-  return hipGetLastError();
+  hipStream_t st = (hipStream_t)stream;
+  if (cfg < 0) cfg = default_cfg(1, a.M);
+  switch (cfg) {
+    case 0: return accum_cfg<Tile64>(a, st);
+    case 1: return accum_cfg<Tile128>(a, st);
+    case 2: return accum_cfg<Tile64x128>(a, st);
+    case 3: return accum_cfg<Tile64k32>(a, st);
+  }
+  return hipErrorInvalidValue;
 }
 
-int launch_ttm_square(const TtmArgs& a, phiq_precision prec, void* stream) {
+int launch_ttm_square(const TtmArgs& a, phiq_precision prec, void* stream, int cfg) {
   if (prec != PHIQ_PREC_FP64) return launch_ttm_square_lowp(a, prec, stream);
-  if (a.M > 64) {
-    hipLaunchKernelGGL(ttm_square_kernel<Tile128>, ttm_grid<Tile128>(a, a.nbatch), dim3(Tile128::NT), 0,
-                       (hipStream_t)stream, a);
-  } else {
-    hipLaunchKernelGGL(ttm_square_kernel<Tile64>, ttm_grid<Tile64>(a, a.nbatch), dim3(Tile64::NT), 0,
-                       (hipStream_t)stream, a);
+  hipStream_t st = (hipStream_t)stream;
+  if (cfg < 0) cfg = default_cfg(2, a.M);
+  switch (cfg) {
+    case 0: return square_cfg<Tile64>(a, st);
+    case 1: return square_cfg<Tile128>(a, st);
+    case 2: return square_cfg<Tile128x128>(a, st);
+    case 3: return square_cfg<Tile256>(a, st);
+    case 4: return square_cfg<Tile128k32>(a, st);
+    case 5: return square_cfg<Tile64x128>(a, st);
+    case 6: return square_cfg<Tile64k32>(a, st);
   }
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 int launch_absdiff_max(const double* y, const double* yold, int np, long long N, double* partial, int nblocks,

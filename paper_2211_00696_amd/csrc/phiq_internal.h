@@ -82,15 +82,19 @@ struct TtmArgs {
   // O_b = 2^{-i} (C_b + sum_{j=1}^{i} (Yprev + (j-1)*yps)/(i-j)!)
   const double* Yprev;
   long long yps;
+  double ifact[PHIQ_MAX_P + 1];  // ifact[k] = 1/k!
 };
 
 // Host launchers (kernels.hip).  All return hipSuccess or the launch error.
 int launch_gemm_jobs(const GemmJob* jobs_dev, int njobs, int nmax, void* stream);
 int launch_scale_jobs(const ScaleJob* jobs_dev, int njobs, int nmax, void* stream);
 int launch_taylor_jobs(const TaylorJob* jobs_dev, int njobs, int nmax, void* stream);
-int launch_ttm_store(const TtmArgs& a, phiq_precision prec, void* stream);
-int launch_ttm_accum(const TtmArgs& a, phiq_precision prec, void* stream);
-int launch_ttm_square(const TtmArgs& a, phiq_precision prec, void* stream);
+// cfg selects the FP64 tile shape (-1: default); kinds 0 = store, 1 = node
+// sum, 2 = squaring; ttm_num_configs(kind) shapes exist per kind.
+int ttm_num_configs(int kind);
+int launch_ttm_store(const TtmArgs& a, phiq_precision prec, void* stream, int cfg);
+int launch_ttm_accum(const TtmArgs& a, phiq_precision prec, void* stream, int cfg);
+int launch_ttm_square(const TtmArgs& a, phiq_precision prec, void* stream, int cfg);
 // FP32-MFMA and split-bf16 (3-product) versions (kernels_lowp.hip)
 int launch_ttm_store_lowp(const TtmArgs& a, phiq_precision prec, void* stream);
 int launch_ttm_accum_lowp(const TtmArgs& a, phiq_precision prec, void* stream);

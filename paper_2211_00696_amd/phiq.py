@@ -190,9 +190,12 @@ class Handle:
         except Exception:
             pass
 
-    def profile_start(self):
-        """Bracket every later kernel launch with HIP events (see phiq_profile_start)."""
-        _check(L.load().phiq_profile_start(self._h), "phiq_profile_start")
+    def profile_start(self, classes=None):
+        """Bracket later kernel launches of the given classes (all if None) with HIP events."""
+        mask = 0
+        for c in classes or []:
+            mask |= 1 << L.PROFILE_CLASSES.index(c)
+        _check(L.load().phiq_profile_start(self._h, mask), "phiq_profile_start")
 
     def profile_stop(self):
         """Synchronise and return {kernel class: dict(launches, ms, flops, bytes)}."""
@@ -201,6 +204,17 @@ class Handle:
         _check(L.load().phiq_profile_stop(self._h, arr, 16, byref(n)), "phiq_profile_stop")
         return {arr[i].name.decode(): dict(launches=arr[i].launches, ms=arr[i].ms, flops=arr[i].flops,
                                            bytes=arr[i].bytes) for i in range(n.value)}
+
+    def autotune(self, sizes, p, m, stream=None):
+        """Time the FP64 mode-product tile shapes for these sizes; returns ms [shape][tile]."""
+        times = np.full(64 * 8, -1.0)
+        n = (c_int * len(sizes))(*sizes)
+        _check(L.load().phiq_autotune(self._h, len(sizes), n, int(p), int(m),
+                                      times.ctypes.data_as(POINTER(c_double)), _stream_ptr(stream)),
+               "phiq_autotune")
+        t = times.reshape(64, 8)
+        rows = [r for r in range(64) if (t[r] >= 0).any()]
+        return t[rows]
 
     def action(self, mats, t, p, v, tol=1e-8, out=None, stream=None, **opts):
         """out[k] = phi_k(-t A) v, k = 0..p; returns (out (p+1, N), report dict)."""
