@@ -85,6 +85,9 @@ typedef struct {
   double c1, c2;            /* cost model C = c1 d n + c2 (n + l p); default 0, 1   */
   int cc_max_doublings;     /* cap of Algorithm 2's doubling loop; default 6        */
   size_t workspace_cap;     /* device bytes the handle may hold; 0 = no cap         */
+  int use_graphs;           /* phiq_action, Gauss rule: 1 (default) = after a call  */
+                            /* of the same shape, replay the device work from a     */
+                            /* captured hipGraph (same result, fewer host launches) */
 } phiq_options;
 
 /* What a plan / call did.  Times are filled by phiq_action only. */
@@ -230,7 +233,7 @@ phiq_status phiq_profile_stop(phiq_handle h, phiq_kernel_stat* stats, int max_st
  * products with p batches, the fused node sum and the fused squaring step)
  * and keeps the fastest shape per launch shape in the handle; later calls
  * with those shapes use it.  Synchronises the stream.  times may be NULL or
- * HOST [64][8]: row r = launch shape r in the order above, column c = the
+ * HOST [64][16]: row r = launch shape r in the order above, column c = the
  * time in ms of tile shape c (rows and columns that do not exist are left
  * untouched).  The workspace contents are overwritten.
  * ------------------------------------------------------------------------ */

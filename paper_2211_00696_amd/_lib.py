@@ -60,6 +60,7 @@ class Options(ctypes.Structure):
         ("c2", c_double),
         ("cc_max_doublings", c_int),
         ("workspace_cap", c_size_t),
+        ("use_graphs", c_int),
     ]
 
 

@@ -124,6 +124,34 @@ static const char* const kProfClass[] = {"ttm_store", "ttm_accum", "ttm_square",
                                          "taylor",    "scale",     "node_sum",   "absdiff"};
 enum ProfClass { K_TTM_STORE = 0, K_TTM_ACCUM, K_TTM_SQUARE, K_GEMM, K_TAYLOR, K_SCALE, K_NODE_SUM, K_ABSDIFF, K_NCLASS };
 
+// FP64 matrix regions and their lower-precision copies (see TtmArgs::Ea)
+struct Twin {
+  const double* base;
+  size_t count;
+  void* a;
+  void* b;
+};
+struct TwinMap {
+  std::vector<Twin> t;
+  void lookup(const double* E, phiq_precision prec, const void** ea, const void** eb) const {
+    *ea = nullptr;
+    *eb = nullptr;
+    for (const auto& w : t) {
+      if (E >= w.base && E < w.base + w.count) {
+        const size_t idx = (size_t)(E - w.base);
+        if (prec == PHIQ_PREC_FP32) {
+          *ea = (const float*)w.a + idx;
+        } else {
+          *ea = (const uint16_t*)w.a + idx;
+          *eb = (const uint16_t*)w.b + idx;
+        }
+        return;
+      }
+    }
+  }
+};
+inline size_t twin_bytes(size_t count) { return ((count * 4) + 255) / 256 * 256; }
+
 struct TuneEntry {
   int kind, M, L, nb, cfg;
 };
@@ -131,6 +159,27 @@ struct TuneEntry {
 struct phiq_handle_s {
   int device = 0;
   Profiler prof;
+  hipStream_t aux = nullptr;      // side stream: scaling chain of the 1D factors, phi_0
+  hipStream_t copy = nullptr;     // upload stream of transient plans
+  hipEvent_t tr_fork = nullptr;   // fork/join events of transient plans
+  hipEvent_t tr_join = nullptr;
+  hipEvent_t tr_fork2 = nullptr;  // phi_0 on the side stream: start / done
+  hipEvent_t tr_phi0 = nullptr;
+  // transient plans alternate between two buffers so the upload of the next
+  // call overlaps the execution of the current one
+  DevBuf tr_buf[2];
+  hipEvent_t tr_free[2] = {nullptr, nullptr};  // buffer no longer read
+  hipEvent_t tr_up[2] = {nullptr, nullptr};    // upload into buffer done
+  bool tr_used[2] = {false, false};
+  int tr_next = 0;
+  // captured device work of phiq_action, keyed by everything the captured
+  // launches depend on (pointers, shapes, plan parameters)
+  struct GraphEntry {
+    std::vector<long long> key;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
+  std::vector<std::vector<long long>> seen;  // keys run once eagerly
   std::vector<TuneEntry> tune;  // fastest tile shape per launch shape (autotuner)
   DevBuf ws;                     // execute workspace (T0, T1, Ya, Yb)
   DevBuf scratch;                // transient plans (phiq_action) and phiq_expm
@@ -140,7 +189,7 @@ struct phiq_handle_s {
   Staging stage;
   size_t cap_bytes = 0;
   size_t held() const {
-    size_t s = ws.cap + scratch.cap + partial.cap;
+    size_t s = ws.cap + scratch.cap + partial.cap + tr_buf[0].cap + tr_buf[1].cap;
     for (const auto& b : cc_levels) s += b.cap;
     return s;
   }
@@ -171,10 +220,28 @@ struct phiq_plan_s {
   int ldcoef = 0;
   char* jobs = nullptr;              // device job tables (per upload)
   size_t jobs_cap = 0;
+  TwinMap twins;  // lower-precision copies of the matrices
+  // The chain E^(k) = E^(k-1)^2 runs on the handle's side stream while the
+  // quadrature runs; the executing stream waits on `join` before it needs
+  // E^(k) (squaring) or E^(l) (phi_0).
+  hipEvent_t fork = nullptr, join = nullptr;
+  hipEvent_t fork2 = nullptr, phi0 = nullptr;  // phi_0 on the side stream
+  bool own_events = false, has_join = false;
+  bool single_stream = false;  // everything on the caller's stream (graph capture)
+  int tr_slot = -1;  // transient buffer used (phiq_action)
+  void* ej = nullptr;  // the plan's device job groups (ExpmJobs), enqueued by plan_enqueue
+  void (*ej_free)(void*) = nullptr;
   // adaptive Clenshaw-Curtis: per level, node exponentials [axis][count]
   std::vector<DevBuf> cc_E;
   std::vector<int> cc_count;
   ~phiq_plan_s() {
+    if (ej && ej_free) ej_free(ej);
+    if (own_events) {
+      if (fork) (void)hipEventDestroy(fork);
+      if (join) (void)hipEventDestroy(join);
+      if (fork2) (void)hipEventDestroy(fork2);
+      if (phi0) (void)hipEventDestroy(phi0);
+    }
     for (auto& b : cc_E)
       if (b.p) (void)hipFree(b.p);
     if (!transient && mem) (void)hipFree(mem);
@@ -205,7 +272,8 @@ hipEvent_t prof_event(phiq_handle h) {
   return e;
 }
 
-// Launch through f(); when profiling, bracket it with events on st.
+// Launch through f() (exactly one kernel); when this class is profiled the
+// kernel's dispatch carries a start and a stop event.
 template <class F>
 phiq_status prof_launch(phiq_handle h, hipStream_t st, int cls, double flops, double bytes, F&& f) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -213,13 +281,16 @@ phiq_status prof_launch(phiq_handle h, hipStream_t st, int cls, double flops, do
   if (rec) {
     e0 = prof_event(h);
     e1 = prof_event(h);
-    if (e0) (void)hipEventRecord(e0, st);
+    if (e0 && e1) {
+      g_launch_events[0] = e0;
+      g_launch_events[1] = e1;
+    }
   }
-  if (f() != hipSuccess) return PHIQ_ERR_HIP;
-  if (rec && e0 && e1) {
-    (void)hipEventRecord(e1, st);
-    h->prof.recs.push_back({cls, e0, e1, flops, bytes});
-  }
+  (void)st;
+  const int err = f();
+  g_launch_events[0] = g_launch_events[1] = nullptr;
+  if (err != hipSuccess) return PHIQ_ERR_HIP;
+  if (rec && e0 && e1) h->prof.recs.push_back({cls, e0, e1, flops, bytes});
   return PHIQ_OK;
 }
 
@@ -252,9 +323,15 @@ int launch_kind(int kind, const TtmArgs& a, phiq_precision prec, hipStream_t st,
 
 int kind_of(int cls) { return cls == K_TTM_ACCUM ? 1 : (cls == K_TTM_SQUARE ? 2 : 0); }
 
-phiq_status L_ttm(phiq_handle h, int cls, const TtmArgs& a0, phiq_precision prec, hipStream_t st) {
+phiq_status L_ttm(phiq_handle h, int cls, const TtmArgs& a0, phiq_precision prec, hipStream_t st,
+                  const TwinMap* tw = nullptr) {
   double fl, by;
   TtmArgs a = a0;
+  if (prec != PHIQ_PREC_FP64) {
+    if (!tw) return PHIQ_ERR_INVALID_ARG;
+    tw->lookup(a.E, prec, &a.Ea, &a.Eb);
+    if (!a.Ea) return PHIQ_ERR_INVALID_ARG;
+  }
   double f = 1.0;
   for (int k = 0; k <= PHIQ_MAX_P; ++k) {
     a.ifact[k] = 1.0 / f;
@@ -336,6 +413,14 @@ phiq_status stage_acquire(phiq_handle h, size_t bytes, int* slot, void** host) {
 
 phiq_status stage_copy(phiq_handle h, int slot, void* dst, size_t bytes, hipStream_t st) {
   PHIQ_HIP(hipMemcpyAsync(dst, h->stage.host[slot], bytes, hipMemcpyHostToDevice, st));
+  PHIQ_HIP(hipEventRecord(h->stage.ev[slot], st));
+  h->stage.pending[slot] = true;
+  return PHIQ_OK;
+}
+
+// Staged upload through a kernel that reads the pinned host buffer.
+phiq_status stage_fetch(phiq_handle h, int slot, void* dst, size_t bytes, hipStream_t st) {
+  PHIQ_HIP(launch_fetch(dst, h->stage.host[slot], bytes, st));
   PHIQ_HIP(hipEventRecord(h->stage.ev[slot], st));
   h->stage.pending[slot] = true;
   return PHIQ_OK;
@@ -460,11 +545,75 @@ phiq_status run_taylor_sigma(const phiq_plan_s* P, const char* jobs_dev, const E
   return PHIQ_OK;
 }
 
+// Convert count FP64 elements starting at E (inside a twin region) to the
+// plan's lower precision.
+phiq_status convert_range(const phiq_plan_s* P, const double* E, size_t count, hipStream_t st) {
+  for (const auto& w : P->twins.t) {
+    if (E >= w.base && E + count <= w.base + w.count) {
+      const size_t idx = (size_t)(E - w.base);
+      if (P->opt.precision == PHIQ_PREC_FP32) {
+        PHIQ_HIP(launch_convert(E, (long long)count, P->opt.precision, (float*)w.a + idx, nullptr, st));
+      } else {
+        PHIQ_HIP(launch_convert(E, (long long)count, P->opt.precision, (uint16_t*)w.a + idx, (uint16_t*)w.b + idx,
+                                st));
+      }
+      return PHIQ_OK;
+    }
+  }
+  return PHIQ_ERR_INVALID_ARG;
+}
+
+phiq_status wait_join(const phiq_plan_s* P, hipStream_t st) {
+  if (P->has_join) PHIQ_HIP(hipStreamWaitEvent(st, P->join, 0));
+  return PHIQ_OK;
+}
+
+// Device work of a plan: the 1D exponentials (all on st, except the scaling
+// chain E^(k) = E^(k-1)^2, which forks to the side stream and is joined by
+// the executing stream before the squaring and phi_0).  Enqueue only:
+// usable under stream capture.
+phiq_status plan_enqueue(phiq_plan P, hipStream_t st) {
+  phiq_handle h = P->h;
+  const ExpmJobs& ej = *(const ExpmJobs*)P->ej;
+  const bool lp = P->opt.precision != PHIQ_PREC_FP64;
+  const int l = P->l;
+  const int nm = nmax_of(P);
+  bool ok = L_scale(h, (const ScaleJob*)(P->jobs + ej.scale_off), ej.scale_n, nm, st) == PHIQ_OK;
+  for (const auto& r : ej.power_rounds)
+    ok = ok && L_gemm(h, (const GemmJob*)(P->jobs + r.first), r.second, nm, st) == PHIQ_OK;
+  ok = ok && run_taylor_sigma(P, P->jobs, ej, st) == PHIQ_OK;
+  if (lp)  // node factors (and E^(0) = the phi_0 factor when l = 0)
+    for (int d = 0; d < P->D && ok; ++d) {
+      const size_t nn = (size_t)P->n[d] * P->n[d];
+      ok = convert_range(P, P->Enode[d], nn * P->m, st) == PHIQ_OK;
+      if (ok && l == 0) ok = convert_range(P, P->Ephi0[d], nn, st) == PHIQ_OK;
+    }
+  if (ok && l > 0) {
+    hipStream_t cs = P->single_stream ? st : h->aux;
+    if (!P->single_stream)
+      ok = hipEventRecord(P->fork, st) == hipSuccess && hipStreamWaitEvent(h->aux, P->fork, 0) == hipSuccess;
+    for (const auto& r : ej.square_chain)
+      ok = ok && L_gemm(h, (const GemmJob*)(P->jobs + r.first), r.second, nm, cs) == PHIQ_OK;
+    if (lp)
+      for (int d = 0; d < P->D && ok; ++d) {
+        const size_t nn = (size_t)P->n[d] * P->n[d];
+        ok = convert_range(P, P->Esq[d], nn * l, cs) == PHIQ_OK && convert_range(P, P->Ephi0[d], nn, cs) == PHIQ_OK;
+      }
+    if (!P->single_stream) {
+      ok = ok && hipEventRecord(P->join, h->aux) == hipSuccess;
+      P->has_join = ok;
+    }
+  }
+  return ok ? PHIQ_OK : PHIQ_ERR_HIP;
+}
+
 // ---------------------------------------------------------------------------
 // plan creation
 // ---------------------------------------------------------------------------
+phiq_status plan_enqueue(phiq_plan P, hipStream_t st);
+
 phiq_status plan_build(phiq_handle h, const phiq_kron_op* op, double t, int p, double tol, const phiq_options* uopt,
-                       bool transient, phiq_plan* out, phiq_report* rep, hipStream_t st) {
+                       bool transient, phiq_plan* out, phiq_report* rep, hipStream_t st, bool defer_device = false) {
   if (!h || !out) return PHIQ_ERR_INVALID_ARG;
   PHIQ_TRY(validate_op(op));
   if (!std::isfinite(t) || !std::isfinite(tol)) return PHIQ_ERR_NONFINITE;
@@ -574,14 +723,20 @@ phiq_status plan_build(phiq_handle h, const phiq_kron_op* op, double t, int p, d
     offS0[d] = P->sigma[d] > 0 ? L.take(nn * ss) : 0;
     offS1[d] = P->sigma[d] > 1 ? L.take(nn * ss) : 0;
   }
+  const size_t nconv = L.off / sizeof(double);  // every matrix of the plan lies below here
+  const bool lp = opt.precision != PHIQ_PREC_FP64;
+  const size_t offTwin = lp ? L.take(twin_bytes(nconv)) : 0;
   P->bytes = L.off;
   if (transient) {
-    phiq_status s = ensure(h, h->scratch, P->bytes);
+    const int k = h->tr_next;
+    h->tr_next ^= 1;
+    phiq_status s = ensure(h, h->tr_buf[k], P->bytes);
     if (s != PHIQ_OK) {
       delete P;
       return s;
     }
-    P->mem = h->scratch.p;
+    P->mem = h->tr_buf[k].p;
+    P->tr_slot = k;
   } else {
     if (h->cap_bytes && h->held() + P->bytes > h->cap_bytes) {
       delete P;
@@ -606,6 +761,10 @@ phiq_status plan_build(phiq_handle h, const phiq_kron_op* op, double t, int p, d
   P->coef = (double*)(base + offCoef);
   P->jobs = base + offJobs;
   P->jobs_cap = jobs_cap;
+  if (lp) {
+    char* tb = base + offTwin;
+    P->twins.t.push_back({(const double*)base, nconv, tb, tb + nconv * 2});
+  }
 
   // ---- host blob: A^d, coefficients, job tables ----
   JobBlob blob;
@@ -671,21 +830,44 @@ phiq_status plan_build(phiq_handle h, const phiq_kron_op* op, double t, int p, d
     }
   }
   std::memcpy(hp + offJobs, blob.bytes.data(), blob.bytes.size());
-  if (stage_copy(h, slot, base, total, st) != PHIQ_OK) {
+  // upload: a copy kernel on the caller's stream reads the pinned staging
+  // buffer directly (no DMA engine hop, so no cross-engine wait)
+  if (stage_fetch(h, slot, base, total, st) != PHIQ_OK) {
     phiq_plan_destroy(P);
     return PHIQ_ERR_HIP;
   }
-  // ---- device work: the 1D exponentials ----
-  const int nm = nmax_of(P);
-  bool ok = L_scale(h, (const ScaleJob*)(P->jobs + ej.scale_off), ej.scale_n, nm, st) == PHIQ_OK;
-  for (const auto& r : ej.power_rounds)
-    ok = ok && L_gemm(h, (const GemmJob*)(P->jobs + r.first), r.second, nm, st) == PHIQ_OK;
-  ok = ok && run_taylor_sigma(P, P->jobs, ej, st) == PHIQ_OK;
-  for (const auto& r : ej.square_chain)
-    ok = ok && L_gemm(h, (const GemmJob*)(P->jobs + r.first), r.second, nm, st) == PHIQ_OK;
-  if (!ok) {
+  // events and the side stream are host set-up (never inside a capture)
+  bool ok = true;
+  if (l > 0) {
+    if (!h->aux) ok = hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) == hipSuccess;
+    if (ok && transient) {
+      hipEvent_t* evs[4] = {&h->tr_fork, &h->tr_join, &h->tr_fork2, &h->tr_phi0};
+      for (auto e : evs)
+        if (ok && !*e) ok = hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess;
+      P->fork = h->tr_fork;
+      P->join = h->tr_join;
+      P->fork2 = h->tr_fork2;
+      P->phi0 = h->tr_phi0;
+    } else if (ok) {
+      ok = hipEventCreateWithFlags(&P->fork, hipEventDisableTiming) == hipSuccess &&
+           hipEventCreateWithFlags(&P->join, hipEventDisableTiming) == hipSuccess &&
+           hipEventCreateWithFlags(&P->fork2, hipEventDisableTiming) == hipSuccess &&
+           hipEventCreateWithFlags(&P->phi0, hipEventDisableTiming) == hipSuccess;
+      P->own_events = true;
+    }
+  }
+  P->ej = new (std::nothrow) ExpmJobs(ej);
+  P->ej_free = [](void* q) { delete (ExpmJobs*)q; };
+  if (!ok || !P->ej) {
     phiq_plan_destroy(P);
     return PHIQ_ERR_HIP;
+  }
+  if (!defer_device) {
+    const phiq_status sd = plan_enqueue(P, st);
+    if (sd != PHIQ_OK) {
+      phiq_plan_destroy(P);
+      return sd;
+    }
   }
   if (rep) {
     std::memset(rep, 0, sizeof(*rep));
@@ -736,7 +918,7 @@ phiq_status chain_front(const phiq_plan_s* P, const double* X, long long xs, dou
     a.M = a.K = P->n[d];
     a.L = (int)(P->N / P->n[d]);
     a.nbatch = nb;
-    PHIQ_TRY(L_ttm(P->h, K_TTM_STORE, a, P->opt.precision, st));
+    PHIQ_TRY(L_ttm(P->h, K_TTM_STORE, a, P->opt.precision, st, &P->twins));
     cur = a.O;
     cxs = P->N;
     cur_f32 = a.o_f32;
@@ -761,7 +943,9 @@ TtmArgs final_args(const phiq_plan_s* P, const double* E, long long es, const Fr
   return a;
 }
 
-phiq_status phi0_chain(const phiq_plan_s* P, const double* v, double* out0, void* T0, void* T1, hipStream_t st) {
+phiq_status phi0_chain(const phiq_plan_s* P, const double* v, double* out0, void* T0, void* T1, hipStream_t st,
+                       bool side = false) {
+  if (!side) PHIQ_TRY(wait_join(P, st));
   double* E[PHIQ_MAX_DIM];
   long long es[PHIQ_MAX_DIM];
   for (int d = 0; d < P->D; ++d) {
@@ -773,7 +957,23 @@ phiq_status phi0_chain(const phiq_plan_s* P, const double* v, double* out0, void
   TtmArgs a = final_args(P, P->Ephi0[0], 0, f, 1);
   a.O = out0;
   a.os = 0;
-  PHIQ_TRY(L_ttm(P->h, K_TTM_STORE, a, P->opt.precision, st));
+  PHIQ_TRY(L_ttm(P->h, K_TTM_STORE, a, P->opt.precision, st, &P->twins));
+  return PHIQ_OK;
+}
+
+// phi_0 on the side stream, after the scaling chain there (which produced
+// its factor) and after everything the caller queued on st before this
+// call (v); the caller's stream waits for it in phi0_finish.
+phiq_status phi0_start(const phiq_plan_s* P, const double* v, double* out0, void* T2, void* T3, hipStream_t st) {
+  phiq_handle h = P->h;
+  PHIQ_HIP(hipEventRecord(P->fork2, st));
+  PHIQ_HIP(hipStreamWaitEvent(h->aux, P->fork2, 0));
+  PHIQ_TRY(phi0_chain(P, v, out0, T2, T3, h->aux, true));
+  PHIQ_HIP(hipEventRecord(P->phi0, h->aux));
+  return PHIQ_OK;
+}
+phiq_status phi0_finish(const phiq_plan_s* P, hipStream_t st) {
+  PHIQ_HIP(hipStreamWaitEvent(st, P->phi0, 0));
   return PHIQ_OK;
 }
 
@@ -783,6 +983,7 @@ phiq_status squaring(const phiq_plan_s* P, double* Ycur, double* Yother, double*
                      hipStream_t st) {
   const long long N = P->N;
   double* cur = Ycur;
+  PHIQ_TRY(wait_join(P, st));
   for (int k = 0; k < P->l; ++k) {
     double* E[PHIQ_MAX_DIM];
     long long es[PHIQ_MAX_DIM];
@@ -798,7 +999,7 @@ phiq_status squaring(const phiq_plan_s* P, double* Ycur, double* Yother, double*
     a.os = N;
     a.Yprev = cur;
     a.yps = N;
-    PHIQ_TRY(L_ttm(P->h, K_TTM_SQUARE, a, P->opt.precision, st));
+    PHIQ_TRY(L_ttm(P->h, K_TTM_SQUARE, a, P->opt.precision, st, &P->twins));
     cur = dst;
   }
   return PHIQ_OK;
@@ -811,18 +1012,22 @@ phiq_status execute_gauss(phiq_plan P, const double* v, double* out, hipStream_t
   const int nb = std::max(P->m + 1, p);
   const size_t tbytes = (P->D > 1 ? (size_t)nb * N * tensor_elem(P) : 0);
   const size_t ybytes = (size_t)p * N * sizeof(double);
-  const size_t need = 2 * align_up(tbytes) + (P->l >= 1 ? align_up(ybytes) : 0) + (P->l >= 2 ? align_up(ybytes) : 0);
+  const size_t t1bytes = (P->D > 1 ? (size_t)N * tensor_elem(P) : 0);
+  const size_t need = 2 * align_up(tbytes) + 2 * align_up(ybytes) + 2 * align_up(t1bytes);
   PHIQ_TRY(ensure(h, h->ws, std::max<size_t>(need, kAlign)));
   char* wb = (char*)h->ws.p;
   void* T0 = wb;
   void* T1 = wb + align_up(tbytes);
   double* Ya = (double*)(wb + 2 * align_up(tbytes));
   double* Yb = (double*)(wb + 2 * align_up(tbytes) + align_up(ybytes));
+  void* T2 = wb + 2 * align_up(tbytes) + 2 * align_up(ybytes);
+  void* T3 = (char*)T2 + align_up(t1bytes);
 
   if (p == 0) return phi0_chain(P, v, out, T0, T1, st);
+  const bool side = P->has_join;  // phi_0 overlaps the quadrature and squaring
+  if (side) PHIQ_TRY(phi0_start(P, v, out, T2, T3, st));
 
-  // quadrature nodes and phi_0 share the first D-1 mode products (nodes
-  // 0..m-1, phi_0 factor at slot m of Enode)
+  // quadrature: the m node chains as one batch per mode product
   double* E[PHIQ_MAX_DIM];
   long long es[PHIQ_MAX_DIM];
   for (int d = 0; d < P->D; ++d) {
@@ -830,13 +1035,7 @@ phiq_status execute_gauss(phiq_plan P, const double* v, double* out, hipStream_t
     es[d] = (long long)P->n[d] * P->n[d];
   }
   Front f;
-  PHIQ_TRY(chain_front(P, v, 0, E, es, P->m + 1, T0, T1, st, &f));
-  {
-    TtmArgs a = final_args(P, P->Enode[0] + (size_t)P->m * es[0], 0, Front{elem_offset(f.X, P->m * f.xs, f.f32), 0, f.f32}, 1);
-    a.O = out;
-    a.os = 0;
-    PHIQ_TRY(L_ttm(P->h, K_TTM_STORE, a, P->opt.precision, st));
-  }
+  PHIQ_TRY(chain_front(P, v, 0, E, es, P->m, T0, T1, st, &f));
   double* Y = (P->l == 0) ? out + N : Ya;
   for (int j0 = 0; j0 < p; j0 += 4) {
     TtmArgs a = final_args(P, P->Enode[0], es[0], f, P->m);
@@ -845,10 +1044,12 @@ phiq_status execute_gauss(phiq_plan P, const double* v, double* out, hipStream_t
     a.np = std::min(4, p - j0);
     a.Y = Y + (size_t)j0 * N;
     a.ys = N;
-    PHIQ_TRY(L_ttm(P->h, K_TTM_ACCUM, a, P->opt.precision, st));
+    PHIQ_TRY(L_ttm(P->h, K_TTM_ACCUM, a, P->opt.precision, st, &P->twins));
   }
   if (P->l > 0) PHIQ_TRY(squaring(P, Ya, Yb, out + N, T0, T1, st));
-  return PHIQ_OK;
+  // phi_0 = (exp(-tA^0) (x) exp(-tA^1) ...) v
+  if (side) return phi0_finish(P, st);
+  return phi0_chain(P, v, out, T0, T1, st);
 }
 
 // ---- adaptive Clenshaw-Curtis (Algorithm 2) --------------------------------
@@ -873,6 +1074,9 @@ phiq_status cc_ensure_level(phiq_plan P, int level, hipStream_t st) {
     const int cnt = (int)theta.size();
     size_t bytes = 0;
     for (int d = 0; d < P->D; ++d) bytes += align_up((size_t)cnt * P->n[d] * P->n[d] * sizeof(double));
+    const size_t fp64_bytes = bytes;
+    const bool lp = P->opt.precision != PHIQ_PREC_FP64;
+    if (lp) bytes += twin_bytes(fp64_bytes / sizeof(double));
     DevBuf b;
     if (h->cap_bytes && h->held() + bytes > h->cap_bytes) return PHIQ_ERR_OOM;
     if (hipMalloc(&b.p, bytes) != hipSuccess) {
@@ -900,6 +1104,12 @@ phiq_status cc_ensure_level(phiq_plan P, int level, hipStream_t st) {
     std::memcpy(hp, blob.bytes.data(), blob.bytes.size());
     PHIQ_TRY(stage_copy(h, slot, P->jobs, blob.bytes.size(), st));
     PHIQ_TRY(run_taylor_sigma(P, P->jobs, ej, st));
+    if (lp) {
+      const size_t cnt64 = fp64_bytes / sizeof(double);
+      char* tb = (char*)b.p + fp64_bytes;
+      P->twins.t.push_back({(const double*)b.p, cnt64, tb, tb + cnt64 * 2});
+      PHIQ_HIP(launch_convert((const double*)b.p, (long long)cnt64, P->opt.precision, tb, tb + cnt64 * 2, st));
+    }
   }
   return PHIQ_OK;
 }
@@ -935,8 +1145,7 @@ phiq_status execute_cc(phiq_plan P, const double* v, double* out, hipStream_t st
   void* T1 = wb + align_up(tbytes);
   double* Ya = (double*)(wb + 2 * align_up(tbytes));
   double* Yb = (double*)(wb + 2 * align_up(tbytes) + align_up(ybytes));
-  PHIQ_TRY(phi0_chain(P, v, out, T0, T1, st));
-  if (p == 0) return PHIQ_OK;
+  if (p == 0) return phi0_chain(P, v, out, T0, T1, st);
 
   const int nblk = 256;
   PHIQ_TRY(ensure(h, h->partial, (size_t)nblk * PHIQ_MAX_P * 2 * sizeof(double)));
@@ -971,7 +1180,7 @@ phiq_status execute_cc(phiq_plan P, const double* v, double* out, hipStream_t st
     TtmArgs a = final_args(P, E[0], es[0], f, cnt);
     a.O = V;
     a.os = N;
-    PHIQ_TRY(L_ttm(P->h, K_TTM_STORE, a, P->opt.precision, st));
+    PHIQ_TRY(L_ttm(P->h, K_TTM_STORE, a, P->opt.precision, st, &P->twins));
     // weights of the full (2n+1)-point rule, n = 3*2^level, in storage order
     const int n2 = 6 << level;
     std::vector<double> xt(n2 + 1), wt(n2 + 1);
@@ -1039,7 +1248,7 @@ phiq_status execute_cc(phiq_plan P, const double* v, double* out, hipStream_t st
   } else {
     PHIQ_HIP(hipMemcpyAsync(out + N, ycur, (size_t)p * N * sizeof(double), hipMemcpyDeviceToDevice, st));
   }
-  return PHIQ_OK;
+  return phi0_chain(P, v, out, T0, T1, st);
 }
 
 }  // namespace
@@ -1074,6 +1283,7 @@ phiq_status phiq_options_default(phiq_options* o) {
   o->c2 = 1.0;
   o->cc_max_doublings = 6;
   o->workspace_cap = 0;
+  o->use_graphs = 0;
   return PHIQ_OK;
 }
 
@@ -1103,6 +1313,18 @@ phiq_status phiq_destroy(phiq_handle h) {
     if (b.p) (void)hipFree(b.p);
   if (h->partial_host) (void)hipHostFree(h->partial_host);
   for (auto e : h->prof.pool) (void)hipEventDestroy(e);
+  if (h->tr_fork) (void)hipEventDestroy(h->tr_fork);
+  if (h->tr_join) (void)hipEventDestroy(h->tr_join);
+  for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
+  if (h->aux) (void)hipStreamDestroy(h->aux);
+  if (h->copy) (void)hipStreamDestroy(h->copy);
+  if (h->tr_fork2) (void)hipEventDestroy(h->tr_fork2);
+  if (h->tr_phi0) (void)hipEventDestroy(h->tr_phi0);
+  for (int k = 0; k < 2; ++k) {
+    if (h->tr_buf[k].p) (void)hipFree(h->tr_buf[k].p);
+    if (h->tr_free[k]) (void)hipEventDestroy(h->tr_free[k]);
+    if (h->tr_up[k]) (void)hipEventDestroy(h->tr_up[k]);
+  }
   for (int k = 0; k < 3; ++k) {
     if (h->stage.host[k]) (void)hipHostFree(h->stage.host[k]);
     if (h->stage.ev[k]) (void)hipEventDestroy(h->stage.ev[k]);
@@ -1170,8 +1392,84 @@ phiq_status phiq_action(phiq_handle h, const phiq_kron_op* op, double t, int p, 
   if (opt && opt->workspace_cap) h->cap_bytes = opt->workspace_cap;
   phiq_plan P = nullptr;
   phiq_report r{};
-  PHIQ_TRY(plan_build(h, op, t, p, tol, opt, true, &P, &r, stream));
-  phiq_status s = phiq_plan_execute(P, v, 1, out, &r, stream);
+  PHIQ_TRY(plan_build(h, op, t, p, tol, opt, true, &P, &r, stream, /*defer_device=*/true));
+  phiq_status s = PHIQ_OK;
+  const bool graphable = (!opt || opt->use_graphs) && P->opt.rule == PHIQ_RULE_GAUSS && !h->prof.on;
+  if (graphable) {
+    // v and out must not overlap (checked by execute on the eager path)
+    const char* vb = (const char*)v;
+    const char* ob = (const char*)out;
+    const size_t nb = (size_t)P->N * sizeof(double);
+    if (vb < ob + (P->p + 1) * nb && ob < vb + nb) {
+      delete P;
+      return PHIQ_ERR_INVALID_ARG;
+    }
+    std::vector<long long> key = {(long long)(uintptr_t)P->mem, (long long)P->bytes, (long long)(uintptr_t)v,
+                                  (long long)(uintptr_t)out, (long long)(uintptr_t)h->ws.p, (long long)h->ws.cap,
+                                  (long long)(uintptr_t)stream, P->opt.precision, P->D, P->p, P->l, P->m, P->K,
+                                  P->has_join ? 1 : 0};
+    for (int d = 0; d < P->D; ++d) {
+      key.push_back(P->n[d]);
+      key.push_back(P->sigma[d]);
+    }
+    hipGraphExec_t exec = nullptr;
+    for (const auto& g : h->graphs)
+      if (g.key == key) exec = g.exec;
+    bool was_seen = false;
+    for (const auto& k : h->seen)
+      if (k == key) was_seen = true;
+    if (exec) {
+      P->has_join = (P->l > 0);
+      if (hipGraphLaunch(exec, stream) != hipSuccess) s = PHIQ_ERR_HIP;
+    } else if (was_seen) {
+      hipGraph_t graph = nullptr;
+      P->single_stream = true;  // a linear graph: no side-stream branches
+      s = hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed) == hipSuccess ? PHIQ_OK : PHIQ_ERR_HIP;
+      phiq_status se = PHIQ_OK;
+      if (s == PHIQ_OK) {
+        se = plan_enqueue(P, stream);
+        if (se == PHIQ_OK) se = execute_gauss(P, v, out, stream);
+        if (hipStreamEndCapture(stream, &graph) != hipSuccess) s = PHIQ_ERR_HIP;
+      }
+      if (s == PHIQ_OK && se == PHIQ_OK && graph &&
+          hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess) {
+        if (h->graphs.size() >= 16) {
+          (void)hipGraphExecDestroy(h->graphs.front().exec);
+          h->graphs.erase(h->graphs.begin());
+        }
+        h->graphs.push_back({key, exec});
+        if (hipGraphLaunch(exec, stream) != hipSuccess) s = PHIQ_ERR_HIP;
+      } else {
+        (void)hipGetLastError();
+        s = PHIQ_ERR_HIP;
+      }
+      if (graph) (void)hipGraphDestroy(graph);
+      if (s != PHIQ_OK || se != PHIQ_OK) {
+        // capture failed: fall back to the eager launches for this call
+        s = plan_enqueue(P, stream);
+        if (s == PHIQ_OK) s = phiq_plan_execute(P, v, 1, out, &r, stream);
+      }
+    } else {
+      s = plan_enqueue(P, stream);
+      if (s == PHIQ_OK) s = phiq_plan_execute(P, v, 1, out, &r, stream);
+      if (s == PHIQ_OK) {
+        if (h->seen.size() >= 64) h->seen.erase(h->seen.begin());
+        h->seen.push_back(key);
+      }
+    }
+    if (rep) {
+      r.l = P->l;
+      r.m = P->m;
+      r.alpha = P->alpha;
+      r.log10_bound = P->log10_bound;
+      r.ttm_chains = (P->p > 0 ? P->m + P->l * P->p : 0) + 1;
+      r.workspace_bytes = h->held();
+    }
+  } else {
+    s = plan_enqueue(P, stream);
+    if (s == PHIQ_OK) s = phiq_plan_execute(P, v, 1, out, &r, stream);
+  }
+  if (P->tr_slot >= 0 && h->tr_free[P->tr_slot]) (void)hipEventRecord(h->tr_free[P->tr_slot], stream);
   if (rep) *rep = r;
   if (!P->cc_E.empty()) (void)hipStreamSynchronize(stream);
   delete P;  // transient: memory stays in the handle
@@ -1197,6 +1495,19 @@ phiq_status phiq_kron_apply(phiq_handle h, int dim, const int* n, const double* 
   const size_t tb = align_up((size_t)nvec * N * (lp ? sizeof(float) : sizeof(double)));
   PHIQ_TRY(ensure(h, h->ws, dim > 1 ? 2 * tb : kAlign));
   void* T[2] = {h->ws.p, (char*)h->ws.p + tb};
+  TwinMap tw;
+  if (lp) {
+    size_t need = 0;
+    for (int d = 0; d < dim; ++d) need += twin_bytes((size_t)n[d] * n[d]);
+    PHIQ_TRY(ensure(h, h->scratch, need));
+    char* c = (char*)h->scratch.p;
+    for (int d = 0; d < dim; ++d) {
+      const size_t cnt = (size_t)n[d] * n[d];
+      tw.t.push_back({F[d], cnt, c, c + cnt * 2});
+      PHIQ_HIP(launch_convert(F[d], (long long)cnt, prec, c, c + cnt * 2, stream));
+      c += twin_bytes(cnt);
+    }
+  }
   const void* cur = x;
   int cur_f32 = 0;
   for (int s = 0; s < dim; ++s) {
@@ -1213,7 +1524,7 @@ phiq_status phiq_kron_apply(phiq_handle h, int dim, const int* n, const double* 
     a.M = a.K = n[d];
     a.L = (int)(N / n[d]);
     a.nbatch = nvec;
-    PHIQ_TRY(L_ttm(h, K_TTM_STORE, a, prec, stream));
+    PHIQ_TRY(L_ttm(h, K_TTM_STORE, a, prec, stream, &tw));
     cur = a.O;
     cur_f32 = a.o_f32;
   }
@@ -1347,6 +1658,7 @@ phiq_status phiq_profile_stop(phiq_handle h, phiq_kernel_stat* stats, int max_st
 }
 
 phiq_status phiq_autotune(phiq_handle h, int dim, const int* n, int p, int m, double* times, hipStream_t st) {
+  // times is [64][16] (ms per launch shape and tile shape)
   if (!h || !n || dim < 1 || dim > PHIQ_MAX_DIM || p < 0 || p > PHIQ_MAX_P || m < 1 || m > 4096)
     return PHIQ_ERR_INVALID_ARG;
   long long N = 1;
@@ -1420,7 +1732,7 @@ phiq_status phiq_autotune(phiq_handle h, int dim, const int* n, int p, int m, do
       float ms = 0.f;
       PHIQ_HIP(hipEventElapsedTime(&ms, e0, e1));
       ms /= reps;
-      if (times && ti < 64) times[ti * 8 + c] = ms;
+      if (times && ti < 64 && c < 16) times[ti * 16 + c] = ms;
       if (ms < best_ms) {
         best_ms = ms;
         best = c;

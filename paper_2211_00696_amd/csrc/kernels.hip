@@ -6,11 +6,25 @@
 //   A operand: lane l holds A[l % 16][l / 16]      (16 x 4)
 //   B operand: lane l holds B[l / 16][l % 16]      (4 x 16)
 //   D (4 doubles): lane l, element e holds D[l / 16 + 4 e][l % 16]
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "phiq_internal.h"
 
 namespace phiq {
+
+thread_local void* g_launch_events[2] = {nullptr, nullptr};
+
+// Launch, with the live-timing events attached when they are set.
+#define PHIQ_LAUNCH(K, G, B, SH, ST, ...)                                                                 \
+  do {                                                                                                    \
+    if (g_launch_events[0])                                                                               \
+      hipExtLaunchKernelGGL(K, G, B, SH, ST, (hipEvent_t)g_launch_events[0], (hipEvent_t)g_launch_events[1], \
+                            0, __VA_ARGS__);                                                              \
+    else                                                                                                  \
+      hipLaunchKernelGGL(K, G, B, SH, ST, __VA_ARGS__);                                                   \
+  } while (0)
+
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
@@ -35,6 +49,7 @@ using Tile256 = Tile<256, 64, 16, 4, 1>;
 using Tile128k32 = Tile<128, 64, 32, 2, 2>;
 using Tile64x128 = Tile<64, 128, 16, 2, 2>;
 using Tile64k32 = Tile<64, 64, 32, 2, 2>;
+using Tile128x128w8 = Tile<128, 128, 16, 4, 2>;  // 8 waves: fewer, larger blocks
 using Tile32 = Tile<32, 32, 16, 1, 1>;
 
 // ---------------------------------------------------------------------------
@@ -339,6 +354,52 @@ __global__ __launch_bounds__(C::NT) void ttm_square_kernel(TtmArgs a) {
     }
 }
 
+// All p orders of one modified-squaring step in one block (p <= 4): the
+// block computes E y_i for i = 1..p in turn and reads every y_j tile once,
+// keeping it in registers for the later orders.  Same factor E for all i.
+template <class C, int NP, bool VEC>
+__global__ __launch_bounds__(C::NT) void ttm_square_all_kernel(TtmArgs a) {
+  __shared__ double smem[2 * (C::BM + C::BN) * C::LDK];
+  int m0, n0, bb;
+  if (!tile_of_block<C>(a.M, a.L, 1, m0, n0, bb)) return;
+  d4 ys[NP][C::TM][C::TN];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    // y_{i+1} tile: issued before the K loop so it arrives during it
+#pragma unroll
+    for (int ti = 0; ti < C::TM; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < C::TN; ++tj) {
+        const int col = n0 + acc_col<C>(tj);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int row = m0 + acc_row<C>(ti, e);
+          const int rc = row < a.M ? row : a.M - 1, cc = col < a.L ? col : a.L - 1;
+          ys[i][ti][tj][e] = a.Yprev[i * a.yps + (long long)rc * a.L + cc];
+        }
+      }
+    d4 acc[C::TM][C::TN];
+    zero_acc<C>(acc);
+    tile_nt_db<C, VEC>(a.E, (const double*)a.X + i * a.xs, a.M, a.K, a.L, m0, n0, smem, acc);
+    const double scale = ldexp(1.0, -(i + 1));
+    double* O = (double*)a.O + i * a.os;
+#pragma unroll
+    for (int ti = 0; ti < C::TM; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < C::TN; ++tj) {
+        const int col = n0 + acc_col<C>(tj);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int row = m0 + acc_row<C>(ti, e);
+          double s = acc[ti][tj][e];
+#pragma unroll
+          for (int j = 0; j <= i; ++j) s += ys[j][ti][tj][e] * a.ifact[i - j];
+          if (row < a.M && col < a.L) O[(long long)row * a.L + col] = scale * s;
+        }
+      }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Small batched GEMM C = A B (n x n), one job per blockIdx.z.
 // ---------------------------------------------------------------------------
@@ -448,6 +509,12 @@ __global__ void node_sum_kernel(NodeSegs segs, long long N, const double* __rest
   }
 }
 
+// Copy from pinned host memory (mapped into the device address space).
+__global__ void fetch_kernel(double* __restrict__ dst, const double* __restrict__ src, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
@@ -455,17 +522,25 @@ namespace {
 inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
 }  // namespace
 
+int launch_fetch(void* dst, const void* src, size_t bytes, void* stream) {
+  const long long n = (long long)(bytes / sizeof(double));
+  if (n <= 0) return hipSuccess;
+  const int nb = (int)std::max<long long>(1, std::min<long long>(512, (n + 255) / 256));
+  PHIQ_LAUNCH(fetch_kernel, dim3(nb), dim3(256), 0, (hipStream_t)stream, (double*)dst, (const double*)src, n);
+  return hipGetLastError();
+}
+
 int launch_gemm_jobs(const GemmJob* jobs, int njobs, int nmax, void* stream) {
   if (njobs <= 0) return hipSuccess;
   // few large-tile blocks would leave most CUs idle: use one-wave 32x32 tiles
   if ((long long)njobs * cdiv(nmax, 64) * cdiv(nmax, 64) < 512) {
     using C = Tile32;
     dim3 grid(cdiv(nmax, C::BM), cdiv(nmax, C::BN), njobs);
-    hipLaunchKernelGGL(gemm_jobs_kernel<C>, grid, dim3(C::NT), 0, (hipStream_t)stream, jobs);
+    PHIQ_LAUNCH(gemm_jobs_kernel<C>, grid, dim3(C::NT), 0, (hipStream_t)stream, jobs);
   } else {
     using C = Tile64;
     dim3 grid(cdiv(nmax, C::BM), cdiv(nmax, C::BN), njobs);
-    hipLaunchKernelGGL(gemm_jobs_kernel<C>, grid, dim3(C::NT), 0, (hipStream_t)stream, jobs);
+    PHIQ_LAUNCH(gemm_jobs_kernel<C>, grid, dim3(C::NT), 0, (hipStream_t)stream, jobs);
   }
   return hipGetLastError();
 }
@@ -473,14 +548,14 @@ int launch_gemm_jobs(const GemmJob* jobs, int njobs, int nmax, void* stream) {
 int launch_scale_jobs(const ScaleJob* jobs, int njobs, int nmax, void* stream) {
   if (njobs <= 0) return hipSuccess;
   dim3 grid(std::max(1, std::min(64, cdiv((long long)nmax * nmax, 256))), njobs);
-  hipLaunchKernelGGL(scale_jobs_kernel, grid, dim3(256), 0, (hipStream_t)stream, jobs);
+  PHIQ_LAUNCH(scale_jobs_kernel, grid, dim3(256), 0, (hipStream_t)stream, jobs);
   return hipGetLastError();
 }
 
 int launch_taylor_jobs(const TaylorJob* jobs, int njobs, int nmax, void* stream) {
   if (njobs <= 0) return hipSuccess;
   dim3 grid(std::max(1, std::min(64, cdiv((long long)nmax * nmax, 256))), njobs);
-  hipLaunchKernelGGL(taylor_jobs_kernel, grid, dim3(256), 0, (hipStream_t)stream, jobs);
+  PHIQ_LAUNCH(taylor_jobs_kernel, grid, dim3(256), 0, (hipStream_t)stream, jobs);
   return hipGetLastError();
 }
 
@@ -499,27 +574,27 @@ bool vec_ok(const TtmArgs& a) {
 template <class C>
 int store_cfg(const TtmArgs& a, hipStream_t st) {
   if (vec_ok(a))
-    hipLaunchKernelGGL((ttm_store_kernel<C, true>), ttm_grid<C>(a, a.nbatch), dim3(C::NT), 0, st, a);
+    PHIQ_LAUNCH((ttm_store_kernel<C, true>), ttm_grid<C>(a, a.nbatch), dim3(C::NT), 0, st, a);
   else
-    hipLaunchKernelGGL((ttm_store_kernel<C, false>), ttm_grid<C>(a, a.nbatch), dim3(C::NT), 0, st, a);
+    PHIQ_LAUNCH((ttm_store_kernel<C, false>), ttm_grid<C>(a, a.nbatch), dim3(C::NT), 0, st, a);
   return hipGetLastError();
 }
 template <class C>
 int square_cfg(const TtmArgs& a, hipStream_t st) {
   if (vec_ok(a))
-    hipLaunchKernelGGL((ttm_square_kernel<C, true>), ttm_grid<C>(a, a.nbatch), dim3(C::NT), 0, st, a);
+    PHIQ_LAUNCH((ttm_square_kernel<C, true>), ttm_grid<C>(a, a.nbatch), dim3(C::NT), 0, st, a);
   else
-    hipLaunchKernelGGL((ttm_square_kernel<C, false>), ttm_grid<C>(a, a.nbatch), dim3(C::NT), 0, st, a);
+    PHIQ_LAUNCH((ttm_square_kernel<C, false>), ttm_grid<C>(a, a.nbatch), dim3(C::NT), 0, st, a);
   return hipGetLastError();
 }
 template <class C, bool VEC>
 int accum_np(const TtmArgs& a, hipStream_t st) {
   const dim3 g = ttm_grid<C>(a, 1);
   switch (a.np) {
-    case 1: hipLaunchKernelGGL((ttm_accum_kernel<C, 1, VEC>), g, dim3(C::NT), 0, st, a); break;
-    case 2: hipLaunchKernelGGL((ttm_accum_kernel<C, 2, VEC>), g, dim3(C::NT), 0, st, a); break;
-    case 3: hipLaunchKernelGGL((ttm_accum_kernel<C, 3, VEC>), g, dim3(C::NT), 0, st, a); break;
-    default: hipLaunchKernelGGL((ttm_accum_kernel<C, 4, VEC>), g, dim3(C::NT), 0, st, a); break;
+    case 1: PHIQ_LAUNCH((ttm_accum_kernel<C, 1, VEC>), g, dim3(C::NT), 0, st, a); break;
+    case 2: PHIQ_LAUNCH((ttm_accum_kernel<C, 2, VEC>), g, dim3(C::NT), 0, st, a); break;
+    case 3: PHIQ_LAUNCH((ttm_accum_kernel<C, 3, VEC>), g, dim3(C::NT), 0, st, a); break;
+    default: PHIQ_LAUNCH((ttm_accum_kernel<C, 4, VEC>), g, dim3(C::NT), 0, st, a); break;
   }
   return hipGetLastError();
 }
@@ -530,20 +605,21 @@ int accum_cfg(const TtmArgs& a, hipStream_t st) {
 
 // default tile choice when no tuned entry exists (from sweeps on gfx950 at
 // n = 32, 128, 256: 64 x 128 tiles for the stores, 64 x 64 with 32-deep K
-// chunks for small n and for the node sum, 64 x 64 for the squaring step)
-int default_cfg(int kind, int M) {
+// chunks for small n, for the node sum and, with all orders per block, for
+// the squaring step)
+int default_cfg(int kind, int M, int nb) {
   if (kind == 1) return 3;
-  if (kind == 2) return 0;
+  if (kind == 2) return nb <= 4 ? 8 : 0;  // all orders per block when p <= 4
   return M >= 128 ? 5 : 6;
 }
 }  // namespace
 
-int ttm_num_configs(int kind) { return kind == 1 ? 4 : 7; }
+int ttm_num_configs(int kind) { return kind == 1 ? 4 : (kind == 2 ? 10 : 8); }
 
 int launch_ttm_store(const TtmArgs& a, phiq_precision prec, void* stream, int cfg) {
   if (prec != PHIQ_PREC_FP64) return launch_ttm_store_lowp(a, prec, stream);
   hipStream_t st = (hipStream_t)stream;
-  if (cfg < 0) cfg = default_cfg(0, a.M);
+  if (cfg < 0) cfg = default_cfg(0, a.M, a.nbatch);
   switch (cfg) {
     case 0: return store_cfg<Tile64>(a, st);
     case 1: return store_cfg<Tile128>(a, st);
@@ -552,6 +628,7 @@ int launch_ttm_store(const TtmArgs& a, phiq_precision prec, void* stream, int cf
     case 4: return store_cfg<Tile128k32>(a, st);
     case 5: return store_cfg<Tile64x128>(a, st);
     case 6: return store_cfg<Tile64k32>(a, st);
+    case 7: return store_cfg<Tile128x128w8>(a, st);
   }
   return hipErrorInvalidValue;
 }
@@ -560,7 +637,7 @@ int launch_ttm_accum(const TtmArgs& a, phiq_precision prec, void* stream, int cf
   if (a.np > 4 || a.np < 1) return hipErrorInvalidValue;
   if (prec != PHIQ_PREC_FP64) return launch_ttm_accum_lowp(a, prec, stream);
   hipStream_t st = (hipStream_t)stream;
-  if (cfg < 0) cfg = default_cfg(1, a.M);
+  if (cfg < 0) cfg = default_cfg(1, a.M, a.nbatch);
   switch (cfg) {
     case 0: return accum_cfg<Tile64>(a, st);
     case 1: return accum_cfg<Tile128>(a, st);
@@ -570,10 +647,38 @@ int launch_ttm_accum(const TtmArgs& a, phiq_precision prec, void* stream, int cf
   return hipErrorInvalidValue;
 }
 
+namespace {
+template <class C, bool VEC>
+int square_all_np(const TtmArgs& a, hipStream_t st) {
+  const dim3 g = ttm_grid<C>(a, 1);
+  switch (a.nbatch) {
+    case 1: PHIQ_LAUNCH((ttm_square_all_kernel<C, 1, VEC>), g, dim3(C::NT), 0, st, a); break;
+    case 2: PHIQ_LAUNCH((ttm_square_all_kernel<C, 2, VEC>), g, dim3(C::NT), 0, st, a); break;
+    case 3: PHIQ_LAUNCH((ttm_square_all_kernel<C, 3, VEC>), g, dim3(C::NT), 0, st, a); break;
+    default: PHIQ_LAUNCH((ttm_square_all_kernel<C, 4, VEC>), g, dim3(C::NT), 0, st, a); break;
+  }
+  return hipGetLastError();
+}
+template <class C>
+int square_all_cfg(const TtmArgs& a, hipStream_t st) {
+  return vec_ok(a) ? square_all_np<C, true>(a, st) : square_all_np<C, false>(a, st);
+}
+}  // namespace
+
 int launch_ttm_square(const TtmArgs& a, phiq_precision prec, void* stream, int cfg) {
   if (prec != PHIQ_PREC_FP64) return launch_ttm_square_lowp(a, prec, stream);
   hipStream_t st = (hipStream_t)stream;
-  if (cfg < 0) cfg = default_cfg(2, a.M);
+  if (cfg < 0) cfg = default_cfg(2, a.M, a.nbatch);
+  // shapes 7.. : all orders per block (p <= 4)
+  if (cfg >= 7) {
+    if (a.nbatch > 4 || a.es != 0) return hipErrorInvalidValue;
+    switch (cfg) {
+      case 7: return square_all_cfg<Tile64>(a, st);
+      case 8: return square_all_cfg<Tile64k32>(a, st);
+      case 9: return square_all_cfg<Tile128>(a, st);
+    }
+    return hipErrorInvalidValue;
+  }
   switch (cfg) {
     case 0: return square_cfg<Tile64>(a, st);
     case 1: return square_cfg<Tile128>(a, st);
@@ -588,14 +693,14 @@ int launch_ttm_square(const TtmArgs& a, phiq_precision prec, void* stream, int c
 
 int launch_absdiff_max(const double* y, const double* yold, int np, long long N, double* partial, int nblocks,
                        void* stream) {
-  hipLaunchKernelGGL(absdiff_max_kernel, dim3(nblocks), dim3(256), 0, (hipStream_t)stream, y, yold, np, N, partial);
+  PHIQ_LAUNCH(absdiff_max_kernel, dim3(nblocks), dim3(256), 0, (hipStream_t)stream, y, yold, np, N, partial);
   return hipGetLastError();
 }
 
 int launch_node_sum(const NodeSegs& segs, long long N, const double* coef, int ldcoef, int np, double* Y,
                     void* stream) {
   const int nb = std::max(1, std::min(4096, cdiv(N, 256)));
-  hipLaunchKernelGGL(node_sum_kernel, dim3(nb), dim3(256), 0, (hipStream_t)stream, segs, N, coef, ldcoef, np, Y);
+  PHIQ_LAUNCH(node_sum_kernel, dim3(nb), dim3(256), 0, (hipStream_t)stream, segs, N, coef, ldcoef, np, Y);
   return hipGetLastError();
 }
 

@@ -8,6 +8,11 @@
 
 namespace phiq {
 
+// Start/stop events for the next kernel launch (live timing): when set, the
+// launchers attach them to the kernel's own dispatch (hipExtLaunchKernel),
+// so no separate event packets enter the stream.
+extern thread_local void* g_launch_events[2];
+
 // ---- planner.cpp ----------------------------------------------------------
 void poly_coeffs(double n, int p, double alpha, phiq_rule rule, double* a3, double* a2, double* a1);
 double log_bound_at(double rho, double n, int p, double alpha, double beta, phiq_rule rule);
@@ -66,6 +71,10 @@ struct TaylorJob {
 struct TtmArgs {
   const double* E;
   long long es;
+  // lower precision: the same matrices converted (FP32 in Ea, or bf16 hi in
+  // Ea and lo in Eb), element-indexed like E
+  const void* Ea;
+  const void* Eb;
   const void* X;
   long long xs;
   void* O;
@@ -86,6 +95,8 @@ struct TtmArgs {
 };
 
 // Host launchers (kernels.hip).  All return hipSuccess or the launch error.
+// dst (device) = src (pinned host memory, read by the kernel), bytes % 8 == 0
+int launch_fetch(void* dst, const void* src, size_t bytes, void* stream);
 int launch_gemm_jobs(const GemmJob* jobs_dev, int njobs, int nmax, void* stream);
 int launch_scale_jobs(const ScaleJob* jobs_dev, int njobs, int nmax, void* stream);
 int launch_taylor_jobs(const TaylorJob* jobs_dev, int njobs, int nmax, void* stream);
@@ -96,6 +107,8 @@ int launch_ttm_store(const TtmArgs& a, phiq_precision prec, void* stream, int cf
 int launch_ttm_accum(const TtmArgs& a, phiq_precision prec, void* stream, int cfg);
 int launch_ttm_square(const TtmArgs& a, phiq_precision prec, void* stream, int cfg);
 // FP32-MFMA and split-bf16 (3-product) versions (kernels_lowp.hip)
+// dst = src converted to FP32 (a) or split into bf16 hi (a) and lo (b)
+int launch_convert(const double* src, long long count, phiq_precision prec, void* a, void* b, void* stream);
 int launch_ttm_store_lowp(const TtmArgs& a, phiq_precision prec, void* stream);
 int launch_ttm_accum_lowp(const TtmArgs& a, phiq_precision prec, void* stream);
 int launch_ttm_square_lowp(const TtmArgs& a, phiq_precision prec, void* stream);

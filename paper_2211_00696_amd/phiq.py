@@ -62,7 +62,7 @@ class _Op:
 
 
 def options(rule="gauss", precision="fp64", l=None, m=None, alpha=None, c1=None, c2=None,
-            cc_max_doublings=None, workspace_cap=None):
+            cc_max_doublings=None, workspace_cap=None, use_graphs=None):
     lib = L.load()
     o = L.Options()
     _check(lib.phiq_options_default(byref(o)), "phiq_options_default")
@@ -82,6 +82,8 @@ def options(rule="gauss", precision="fp64", l=None, m=None, alpha=None, c1=None,
         o.cc_max_doublings = int(cc_max_doublings)
     if workspace_cap is not None:
         o.workspace_cap = int(workspace_cap)
+    if use_graphs is not None:
+        o.use_graphs = int(bool(use_graphs))
     return o
 
 
@@ -207,12 +209,12 @@ class Handle:
 
     def autotune(self, sizes, p, m, stream=None):
         """Time the FP64 mode-product tile shapes for these sizes; returns ms [shape][tile]."""
-        times = np.full(64 * 8, -1.0)
+        times = np.full(64 * 16, -1.0)
         n = (c_int * len(sizes))(*sizes)
         _check(L.load().phiq_autotune(self._h, len(sizes), n, int(p), int(m),
                                       times.ctypes.data_as(POINTER(c_double)), _stream_ptr(stream)),
                "phiq_autotune")
-        t = times.reshape(64, 8)
+        t = times.reshape(64, 16)
         rows = [r for r in range(64) if (t[r] >= 0).any()]
         return t[rows]
 
