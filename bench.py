@@ -36,7 +36,7 @@ HBM_PEAK_GBS = 8000.0
 
 def kernel_source_digest():
     h = hashlib.sha256()
-    for f in ("kernels.hip", "kernels_lowp.hip"):
+    for f in ("kernels.hip", "tile_fp64.h", "kernels_lowp.hip"):
         p = os.path.join(ROOT, "paper_2211_00696_amd", "csrc", f)
         if os.path.exists(p):
             h.update(open(p, "rb").read())
@@ -96,6 +96,9 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="before the steps, negate a buffer of this many MiB into another once (a plain device copy "
+                         "of known size that calibrates hardware byte counters taken over the same run)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -118,6 +121,13 @@ def main():
     stream = torch.cuda.current_stream()
     h = phiq.Handle(0)
     opts = dict(rule=args.rule, precision=args.precision)
+    if args.copy_probe_mib > 0:
+        src = torch.ones(args.copy_probe_mib << 17, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.neg(src, out=dst)  # one elementwise kernel: reads and writes copy_probe_mib MiB
+        torch.cuda.synchronize()
+        del src, dst
 
     # tile shapes for this problem's launch shapes (autotuner, before timing)
     _, rep0 = h.action(pr["mats"], pr["t"], p, v, tol=pr["tol"], out=out, **opts)

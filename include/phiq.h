@@ -85,9 +85,11 @@ typedef struct {
   double c1, c2;            /* cost model C = c1 d n + c2 (n + l p); default 0, 1   */
   int cc_max_doublings;     /* cap of Algorithm 2's doubling loop; default 6        */
   size_t workspace_cap;     /* device bytes the handle may hold; 0 = no cap         */
-  int use_graphs;           /* phiq_action, Gauss rule: 1 (default) = after a call  */
-                            /* of the same shape, replay the device work from a     */
-                            /* captured hipGraph (same result, fewer host launches) */
+  int use_graphs;           /* phiq_action, Gauss rule: 1 = from the third call of  */
+                            /* one shape on, replay the device work from a captured */
+                            /* hipGraph (bitwise the same result).  Default 0: on   */
+                            /* ROCm 7 a replay of the ~45-node graph costs more     */
+                            /* than the eager launches it replaces.                 */
 } phiq_options;
 
 /* What a plan / call did.  Times are filled by phiq_action only. */

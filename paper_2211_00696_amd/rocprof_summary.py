@@ -1,0 +1,146 @@
+"""Summaries of rocprofv3 CSV output for bench.py runs.
+
+  python -m paper_2211_00696_amd.rocprof_summary times   TRACE.csv BENCH.json
+  python -m paper_2211_00696_amd.rocprof_summary traffic FETCH.csv WRITE.csv BENCH.json COPY_MIB
+
+`times` reads a `--kernel-trace` CSV and prints a markdown table per kernel,
+plus the average duration of the dominant class's launches inside bench.py's
+timed region (to compare with the live HIP-event figure in BENCH.json).
+
+`traffic` reads two `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE` counter CSVs of
+the same command, calibrates each counter with the plain device copy that
+`bench.py --copy-probe-mib COPY_MIB` launches (a negation of COPY_MIB MiB into
+another buffer: COPY_MIB MiB read, COPY_MIB MiB written), and prints the HBM
+bytes per launch of the dominant class as JSON for profiles/traffic.json.
+
+bench.py's step sequence after warm-up is: K timed actions, K untimed
+actions, one plan execution, K executions of the reused plan.  Every step
+launches the same kernels, so the timed region's launches of a class are the
+K*L launches that precede the last (2K+1)*L, with L the class's launches per
+step.
+"""
+from __future__ import annotations
+
+import csv
+import json
+import re
+import sys
+from collections import defaultdict
+
+CLASS_RE = {
+    "ttm_store": re.compile(r"(^|::)ttm_(lp_)?store_kernel"),
+    "ttm_accum": re.compile(r"(^|::)ttm_(lp_)?accum_kernel"),
+    "ttm_square": re.compile(r"(^|::)ttm_(lp_)?square(_all)?_kernel"),
+    "gemm": re.compile(r"(^|::)gemm_jobs_kernel"),
+    "taylor": re.compile(r"(^|::)taylor_jobs_kernel"),
+    "scale": re.compile(r"(^|::)scale_jobs_kernel"),
+    "node_sum": re.compile(r"(^|::)node_sum_kernel"),
+    "absdiff": re.compile(r"(^|::)absdiff_max_kernel"),
+}
+COPY_RE = re.compile(r"neg", re.I)
+
+
+def _rows(path):
+    with open(path, newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def _name(r):
+    n = r.get("Kernel_Name") or r.get("Kernel-Name") or r.get("KernelName") or ""
+    return n.strip()
+
+
+def _short(n):
+    n = re.sub(r"^void ", "", n)
+    return n.split("(")[0] if "(" in n and not n.startswith("(") else n
+
+
+def _timed_slice(items, bench):
+    dom = bench["roofline"]["kernel"]
+    K = int(bench["steps"])
+    L = int(bench["kernels_one_step"][dom]["launches"])
+    after = (2 * K + 1) * L
+    if len(items) < after + K * L:
+        raise SystemExit("trace holds %d %s launches, fewer than the %d the bench sequence makes"
+                         % (len(items), dom, after + K * L))
+    return items[len(items) - after - K * L: len(items) - after]
+
+
+def times(trace_csv, bench_json):
+    bench = json.load(open(bench_json))
+    rows = _rows(trace_csv)
+    per = defaultdict(list)
+    disp = []
+    for r in rows:
+        n = _short(_name(r))
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1000.0
+        per[n].append(d)
+        disp.append((int(r["Start_Timestamp"]), n, d))
+    disp.sort()
+    tot = sum(sum(v) for v in per.values())
+    print("| kernel | calls | total us | avg us | min us | max us | % |")
+    print("|---|---|---|---|---|---|---|")
+    for n, v in sorted(per.items(), key=lambda kv: -sum(kv[1])):
+        print("| `%s` | %d | %.1f | %.2f | %.2f | %.2f | %.1f |"
+              % (n[:100], len(v), sum(v), sum(v) / len(v), min(v), max(v), 100 * sum(v) / tot))
+    dom = bench["roofline"]["kernel"]
+    cls = [(n, d) for _, n, d in disp if CLASS_RE[dom].search(n)]
+    sl = _timed_slice(cls, bench)
+    avg = sum(d for _, d in sl) / len(sl)
+    print()
+    print("Timed region, class `%s`: %d launches, average %.2f us (rocprofv3); "
+          "bench.py live HIP events: %.2f us over %d launches."
+          % (dom, len(sl), avg, bench["roofline"]["avg_launch_ms"] * 1e3, bench["roofline"]["launches"]))
+    names = sorted(set(n for n, _ in sl))
+    print("Kernels of the class in the timed region: " + ", ".join("`%s`" % n for n in names))
+
+
+def _counter(path, counter):
+    out = []
+    for r in _rows(path):
+        if r.get("Counter_Name", counter) != counter:
+            continue
+        out.append((int(r.get("Dispatch_Id", r.get("Correlation_Id", 0))), _short(_name(r)),
+                    float(r["Counter_Value"])))
+    # one row per dispatch (values of the same dispatch summed over dimensions)
+    agg = defaultdict(float)
+    nm = {}
+    for i, n, v in out:
+        agg[i] += v
+        nm[i] = n
+    return [(i, nm[i], agg[i]) for i in sorted(agg)]
+
+
+def traffic(fetch_csv, write_csv, bench_json, copy_mib):
+    bench = json.load(open(bench_json))
+    dom = bench["roofline"]["kernel"]
+    copy_kib = float(copy_mib) * 1024.0
+    res = {}
+    for label, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
+        rows = _counter(path, counter)
+        cp = [v for _, n, v in rows if COPY_RE.search(n)]
+        if not cp:
+            raise SystemExit("no copy-probe dispatch in " + path)
+        scale = copy_kib / max(cp)
+        cls = [(n, v) for _, n, v in rows if CLASS_RE[dom].search(n)]
+        sl = _timed_slice(cls, bench)
+        kib = sum(v for _, v in sl) / len(sl)
+        res[label] = {"counter": counter, "copy_probe_kib_measured": max(cp), "copy_probe_kib_expected": copy_kib,
+                      "scale": scale, "kib_per_launch_raw": kib, "bytes_per_launch": kib * scale * 1024.0,
+                      "launches": len(sl)}
+    total = res["fetch"]["bytes_per_launch"] + res["write"]["bytes_per_launch"]
+    alg = bench["roofline"]["algorithmic_bytes_per_launch"]
+    print(json.dumps({dom: {"kernel_digest": bench["kernel_digest"], "bytes_per_launch": total,
+                            "algorithmic_bytes_per_launch": alg, "ratio_to_algorithmic": total / alg,
+                            "fetch": res["fetch"], "write": res["write"],
+                            "workload": bench["config"]["workload"]}}, indent=1))
+
+
+if __name__ == "__main__":
+    if len(sys.argv) >= 4 and sys.argv[1] == "times":
+        times(sys.argv[2], sys.argv[3])
+    elif len(sys.argv) >= 6 and sys.argv[1] == "traffic":
+        traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
+    else:
+        print(__doc__)
+        sys.exit(2)
