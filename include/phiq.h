@@ -180,6 +180,58 @@ phiq_status phiq_action(phiq_handle h, const phiq_kron_op* op, double t, int p,
                         const double* v, double tol, const phiq_options* opt,
                         double* out, phiq_report* rep, hipStream_t stream);
 
+/* One problem of a batch: operator, time, order, tolerance and nrhs vectors
+ * that share them (e.g. the stage vectors of an exponential Runge-Kutta
+ * step).  A[d] HOST as for phiq_action; v DEVICE nrhs x N; out DEVICE
+ * nrhs x (p+1) x N.  rep (nullable) receives l, m, alpha, the bound and
+ * ttm_chains summed over the problem's vectors. */
+typedef struct {
+  phiq_kron_op op;
+  double t;
+  int p;
+  double tol;
+  int nrhs;
+  const double* v;
+  double* out;
+  phiq_report* rep;
+} phiq_problem;
+
+/* Many independent phi-actions (Algorithm 6 per problem) launched together.
+ * Every problem gets the parameters phiq_action would choose with the same
+ * options (so the results agree with separate calls up to the summation
+ * order of the tiles).  Problems with the Gauss rule, FP64 mode products and
+ * p <= 4 are split into stages (1D exponentials, node chains with the node
+ * sum, squaring steps, phi_0), and the stages of all of them are run by
+ * depth in their dependency graph: one kernel launch per depth covers that
+ * depth's tiles of every problem, so small and large problems fill the GPU
+ * together (a batch of 512 mixed 2D/3D problems takes about 60 launches).
+ * Other problems (CC, lower precision, p > 4) run afterwards, one plan each,
+ * on the same stream (then the call synchronises the stream).  Asynchronous
+ * otherwise.  Device memory: the handle keeps one arena for the batch
+ * (factors and the per-vector workspaces of all problems, ~16 N doubles per
+ * vector plus the 1D matrices); opt->workspace_cap bounds it (PHIQ_ERR_OOM).
+ * Outputs must not overlap each other or any v (inputs may be shared). */
+phiq_status phiq_action_batched(phiq_handle h, int nprob, const phiq_problem* probs,
+                                const phiq_options* opt, hipStream_t stream);
+
+/* Host-only dry run of phiq_action_batched's scheduling (no GPU needed; v
+ * and out are only compared as addresses): validates the problems exactly
+ * as the batched call does, builds the stage list and checks that every
+ * address a stage touches lies in the arena or in its problem's v / out and
+ * that every stage runs at a greater depth than the stages it reads. */
+typedef struct {
+  int persistent;          /* problems in the persistent launch          */
+  int separate;            /* problems run one plan each afterwards      */
+  long long stages;        /* stages of the persistent launch            */
+  long long tiles;         /* work items (64 x 64 tiles) over all stages */
+  int depth;               /* launches: longest dependency chain         */
+  int groups;              /* dependency groups                          */
+  size_t arena_bytes;      /* device bytes the handle's batch arena needs */
+  size_t upload_bytes;     /* host->device bytes per call                 */
+} phiq_batch_stats;
+phiq_status phiq_batch_info(int nprob, const phiq_problem* probs, const phiq_options* opt,
+                            phiq_batch_stats* info);
+
 /* Building blocks (also used by the tests).
  *
  * phiq_expm: E[b] = exp(X[b]) for nmat matrices n x n, DEVICE row-major

@@ -37,6 +37,8 @@ EXPORTS = [
     "phiq_plan_execute",
     "phiq_plan_destroy",
     "phiq_action",
+    "phiq_action_batched",
+    "phiq_batch_info",
     "phiq_expm",
     "phiq_kron_apply",
     "phiq_profile_start",
@@ -80,6 +82,20 @@ class Report(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Problem(ctypes.Structure):
+    _fields_ = [("op", KronOp), ("t", c_double), ("p", c_int), ("tol", c_double), ("nrhs", c_int),
+                ("v", c_void_p), ("out", c_void_p), ("rep", POINTER(Report))]
+
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [("persistent", c_int), ("separate", c_int), ("stages", ctypes.c_longlong),
+                ("tiles", ctypes.c_longlong), ("depth", c_int), ("groups", c_int),
+                ("arena_bytes", ctypes.c_size_t), ("upload_bytes", ctypes.c_size_t)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class KernelStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 24), ("launches", c_int), ("ms", c_double), ("flops", c_double),
                 ("bytes", c_double)]
@@ -113,6 +129,8 @@ def load():
         "phiq_plan_destroy": (c_int, [c_void_p]),
         "phiq_action": (c_int, [c_void_p, P(KronOp), c_double, c_int, c_void_p, c_double, P(Options), c_void_p,
                                 P(Report), c_void_p]),
+        "phiq_action_batched": (c_int, [c_void_p, c_int, P(Problem), P(Options), c_void_p]),
+        "phiq_batch_info": (c_int, [c_int, P(Problem), P(Options), P(BatchStats)]),
         "phiq_expm": (c_int, [c_void_p, c_int, c_int, c_void_p, P(c_double), c_void_p, c_void_p]),
         "phiq_kron_apply": (c_int, [c_void_p, c_int, P(c_int), P(c_void_p), c_void_p, c_void_p, c_int, c_int,
                                     c_void_p]),

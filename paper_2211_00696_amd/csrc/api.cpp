@@ -102,6 +102,54 @@ double sum_infnorms(const phiq_kron_op* op) {
   return s;
 }
 
+// Host part of a plan: norm estimate (eq. infnorm_upper_bnd), (l, m) by the
+// selector with beta = 1, the 1D scaling sigma_d of each Taylor argument and
+// the Taylor degree.  Shared by single plans and batches so both choose the
+// same parameters for the same problem.
+phiq_status select_params(const phiq_kron_op* op, double t, int p, double tol, const phiq_options& opt,
+                          PlanParams* pp) {
+  double norms[PHIQ_MAX_DIM];
+  double alpha = 0.0;
+  for (int d = 0; d < op->dim; ++d) {
+    norms[d] = std::fabs(t) * infnorm(op->A[d], op->n[d]);
+    alpha += norms[d];
+  }
+  if (opt.alpha >= 0) alpha = opt.alpha;
+  pp->alpha = alpha;
+  pp->log10_bound = 0.0;
+  int l = 0, nq = -1;
+  if (p > 0) {
+    double cost = 0.0;
+    if (opt.l >= 0) {
+      l = opt.l;
+      nq = (opt.rule == PHIQ_RULE_GAUSS)
+               ? (opt.m > 0 ? opt.m - 1
+                            : (alpha <= 1e-12 ? std::max(1, (p + 1) / 2) - 1
+                                              : quadnodes(tol, p, std::ldexp(alpha, -l), 1.0, opt.rule)))
+               : 4;
+    } else {
+      setup_quadrature(tol, p, alpha, 1.0, opt.rule, opt.c1, opt.c2, op->dim, &l, &nq, &cost);
+      if (opt.m > 0 && opt.rule == PHIQ_RULE_GAUSS) nq = opt.m - 1;
+    }
+    if (l < 0 || nq < 0) return PHIQ_ERR_NOT_CONVERGED;
+    pp->log10_bound = (alpha > 1e-12 && nq >= 1)
+                          ? log_quaderr(nq, p, std::ldexp(alpha, -l), 1.0, opt.rule) / std::log(10.0)
+                          : -INFINITY;
+  }
+  pp->l = l;
+  pp->m = (p > 0 && opt.rule == PHIQ_RULE_GAUSS) ? nq + 1 : 0;
+  double nu = 0.0;
+  for (int d = 0; d < op->dim; ++d) {
+    const double xd = std::ldexp(norms[d], -l);
+    int s = 0;
+    while (std::ldexp(xd, -s) > kThetaMax) ++s;
+    pp->sigma[d] = s;
+    nu = std::max(nu, std::ldexp(xd, -s));
+  }
+  pp->K = taylor_degree(nu);
+  return PHIQ_OK;
+}
+
 }  // namespace phiq
 
 using namespace phiq;
@@ -186,10 +234,11 @@ struct phiq_handle_s {
   std::vector<DevBuf> cc_levels; // node vectors of the adaptive rule, per level
   DevBuf partial;                // CC reduction partials
   double* partial_host = nullptr;
+  DevBuf batch;                  // phiq_action_batched: factors, workspaces, stage tables
   Staging stage;
   size_t cap_bytes = 0;
   size_t held() const {
-    size_t s = ws.cap + scratch.cap + partial.cap + tr_buf[0].cap + tr_buf[1].cap;
+    size_t s = ws.cap + scratch.cap + partial.cap + tr_buf[0].cap + tr_buf[1].cap + batch.cap;
     for (const auto& b : cc_levels) s += b.cap;
     return s;
   }
@@ -629,6 +678,8 @@ phiq_status plan_build(phiq_handle h, const phiq_kron_op* op, double t, int p, d
       opt.cc_max_doublings < 1 || opt.cc_max_doublings > 10)
     return PHIQ_ERR_INVALID_ARG;
 
+  PlanParams pp;
+  PHIQ_TRY(select_params(op, t, p, tol, opt, &pp));
   phiq_plan P = new (std::nothrow) phiq_plan_s;
   if (!P) return PHIQ_ERR_OOM;
   P->h = h;
@@ -637,58 +688,18 @@ phiq_status plan_build(phiq_handle h, const phiq_kron_op* op, double t, int p, d
   for (int d = 0; d < P->D; ++d) {
     P->n[d] = op->n[d];
     P->N *= op->n[d];
+    P->sigma[d] = pp.sigma[d];
   }
   P->t = t;
   P->p = p;
   P->tol = tol;
   P->opt = opt;
-
-  // a1: norm estimate (eq. infnorm_upper_bnd)
-  double norms[PHIQ_MAX_DIM];
-  double alpha = 0.0;
-  for (int d = 0; d < P->D; ++d) {
-    norms[d] = std::fabs(t) * infnorm(op->A[d], op->n[d]);
-    alpha += norms[d];
-  }
-  if (opt.alpha >= 0) alpha = opt.alpha;
-  P->alpha = alpha;
-
-  // a2: (l, n) by setup_quadrature with beta = 1 (tol relative to ||v||_inf)
-  int l = 0, nq = -1;
-  if (p > 0) {
-    double cost = 0.0;
-    if (opt.l >= 0) {
-      l = opt.l;
-      nq = (opt.rule == PHIQ_RULE_GAUSS)
-               ? (opt.m > 0 ? opt.m - 1
-                            : (alpha <= 1e-12 ? std::max(1, (p + 1) / 2) - 1
-                                              : quadnodes(tol, p, std::ldexp(alpha, -l), 1.0, opt.rule)))
-               : 4;
-    } else {
-      setup_quadrature(tol, p, alpha, 1.0, opt.rule, opt.c1, opt.c2, P->D, &l, &nq, &cost);
-      if (opt.m > 0 && opt.rule == PHIQ_RULE_GAUSS) nq = opt.m - 1;
-    }
-    if (l < 0 || nq < 0) {
-      delete P;
-      return PHIQ_ERR_NOT_CONVERGED;
-    }
-    P->log10_bound = (alpha > 1e-12 && nq >= 1)
-                         ? log_quaderr(nq, p, std::ldexp(alpha, -l), 1.0, opt.rule) / std::log(10.0)
-                         : -INFINITY;
-  }
-  P->l = l;
-  P->m = (p > 0 && opt.rule == PHIQ_RULE_GAUSS) ? nq + 1 : 0;
-
-  // 1D scaling for the Taylor series
-  double nu = 0.0;
-  for (int d = 0; d < P->D; ++d) {
-    const double xd = std::ldexp(norms[d], -l);
-    int s = 0;
-    while (std::ldexp(xd, -s) > kThetaMax) ++s;
-    P->sigma[d] = s;
-    nu = std::max(nu, std::ldexp(xd, -s));
-  }
-  P->K = taylor_degree(nu);
+  P->alpha = pp.alpha;
+  P->log10_bound = pp.log10_bound;
+  P->l = pp.l;
+  P->m = pp.m;
+  P->K = pp.K;
+  const int l = P->l;
 
   // a3: the rule (Gauss); CC nodes are produced level by level at execute time
   std::vector<double> theta, w;
@@ -1312,6 +1323,7 @@ phiq_status phiq_destroy(phiq_handle h) {
   for (auto& b : h->cc_levels)
     if (b.p) (void)hipFree(b.p);
   if (h->partial_host) (void)hipHostFree(h->partial_host);
+  if (h->batch.p) (void)hipFree(h->batch.p);
   for (auto e : h->prof.pool) (void)hipEventDestroy(e);
   if (h->tr_fork) (void)hipEventDestroy(h->tr_fork);
   if (h->tr_join) (void)hipEventDestroy(h->tr_join);
@@ -1756,3 +1768,22 @@ phiq_status phiq_autotune(phiq_handle h, int dim, const int* n, int p, int m, do
 }
 
 }  // extern "C"
+
+// ---- helpers for the batched entry point (batched.cpp) --------------------
+namespace phiq {
+
+phiq_status batch_arena(phiq_handle h, size_t bytes, void** dev) {
+  PHIQ_TRY(ensure(h, h->batch, std::max<size_t>(bytes, kAlign)));
+  *dev = h->batch.p;
+  return PHIQ_OK;
+}
+
+phiq_status batch_stage(phiq_handle h, size_t bytes, int* slot, void** host) {
+  return stage_acquire(h, bytes, slot, host);
+}
+
+phiq_status batch_fetch(phiq_handle h, int slot, void* dst, size_t bytes, hipStream_t st) {
+  return stage_fetch(h, slot, dst, bytes, st);
+}
+
+}  // namespace phiq

@@ -28,6 +28,24 @@ void clenshaw_curtis(int m, double* theta, double* w);
 phiq_status validate_op(const phiq_kron_op* op);
 double sum_infnorms(const phiq_kron_op* op);
 
+// Host-chosen parameters of one phi-action (Algorithm 5 with beta = 1).
+struct PlanParams {
+  double alpha;        // ||tA||_inf estimate
+  double log10_bound;  // a priori quadrature bound at (l, m)
+  int l;               // scaling exponent
+  int m;               // Gauss nodes (0 for CC or p = 0)
+  int K;               // Taylor degree of the 1D exponentials
+  int sigma[PHIQ_MAX_DIM];  // extra halvings of axis d's Taylor argument
+};
+phiq_status select_params(const phiq_kron_op* op, double t, int p, double tol, const phiq_options& opt,
+                          PlanParams* pp);
+// Grow-only device arena of batched calls, held by the handle.
+phiq_status batch_arena(phiq_handle h, size_t bytes, void** dev);
+// Pinned staging slot of at least `bytes`, and its upload (a copy kernel
+// reading the pinned memory, on st).
+phiq_status batch_stage(phiq_handle h, size_t bytes, int* slot, void** host);
+phiq_status batch_fetch(phiq_handle h, int slot, void* dst, size_t bytes, hipStream_t st);
+
 // ---- kernels.hip: device job descriptors ---------------------------------
 // C = A * B, all n x n row-major FP64 (A, B, C distinct).
 struct GemmJob {
@@ -128,5 +146,66 @@ struct NodeSegs {
 // segments in order.
 int launch_node_sum(const NodeSegs& segs, long long N, const double* coef, int ldcoef, int np, double* Y,
                     void* stream);
+
+// ---- batched.hip: batched stages, one launch per dependency depth --------
+// A batch is a list of stages (one GEMM, Taylor evaluation or mode product
+// over a whole operand, split into 64 x 64 tiles), stored by depth in the
+// dependency graph; tiles are numbered consecutively over the list.  One
+// launch runs the tiles of one depth.  `signal`/`wait*` record the
+// dependencies for the host-side check of the order.
+enum BatchStageType : int {
+  kStageGemm = 0,    // O = E * X (n x n, n = M)
+  kStageTaylor = 1,  // Taylor sums of job `aux` (BatchTaylor)
+  kStageStore = 2,   // O_b = rotated mode product of (E_b, X_b), b < nb
+  kStageAccum = 3,   // Y_q (+)= sum_b coef[q * ldcoef + b] * (E_b X_b), q < np
+  kStageSquare = 4,  // O_i = 2^{-i-1} (E X_i + sum_{j<=i} Y_j / (i-j)!), i < np
+};
+struct BatchStage {
+  long long tile0;  // number of this stage's first tile
+  int ntiles;
+  int type;
+  int signal;       // dependency group this stage belongs to
+  int wait0, need0; // groups whose results it reads (-1: none) and their tile counts
+  int wait1, need1;
+  int M, K, L, nb;
+  int np;
+  int vec;          // 16-byte staging allowed (K even, 16-byte aligned E and X)
+  int accumulate;   // Accum: add into Y
+  int ldcoef;
+  int aux;          // Taylor: job index
+  int pad_;
+  const double* E;
+  long long es;
+  const double* X;
+  long long xs;
+  double* O;
+  long long os;
+  const double* coef;
+  double* Y;
+  long long ys;
+};
+// dst[t] = I + sum_{k=1}^{K} c[t]^k/k! Z^k (t < nt), Z^1 at Z1 and Z^k at
+// Zp + (k-2) n^2 for k >= 2.
+struct BatchTaylor {
+  const double* Z1;
+  const double* Zp;
+  double* dst[kTaylorTargets];
+  double c[kTaylorTargets];
+  int n;
+  int K;
+  int nt;
+  int pad_;
+};
+constexpr int kBatchTile = 64;          // output tile edge of every stage
+constexpr int kBatchTaylorChunk = 4096; // elements per Taylor tile
+struct BatchArgs {
+  const BatchStage* st;
+  int nstages;
+  long long tile_begin;  // tiles [tile_begin, tile_end) of one depth
+  long long tile_end;
+  const BatchTaylor* tj;
+};
+int batch_workers(int* blocks);  // resident workgroups of the kernel on this device
+int launch_batch_level(const BatchArgs& a, int blocks, void* stream);
 
 }  // namespace phiq

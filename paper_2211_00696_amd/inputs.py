@@ -113,3 +113,28 @@ def problem(name: str, seed: int = 0, n: int | None = None, dim: int | None = No
         raise ValueError(f"unknown workload {name!r}")
     return dict(name=name, mats=mats, t=float(t), p=int(p), tol=float(tol), v=v,
                 coef=coef, n=n, dim=dim, seed=seed)
+
+
+def batch_mix(seed: int = 0, count: int = 512, n_min: int = 16, n_max: int = 192, p_max: int = 4,
+              t_range=(1e-4, 1e-1), dims=(2, 3)):
+    """A batch of independent problems of mixed shape.
+
+    Per problem, drawn in this order from one ``default_rng(seed)``: the
+    dimension (uniform over ``dims``), n (uniform integer in [n_min, n_max],
+    the same on every axis), p (uniform in 1..p_max), t (log-uniform in
+    t_range), the coefficients (a_d, b_d) as for ``advdiff``, then v ~ N(0, 1).
+    Tolerance 1e-8.  Returns a list of problem dicts (see ``problem``).
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        dim = int(dims[rng.integers(0, len(dims))])
+        n = int(rng.integers(n_min, n_max + 1))
+        p = int(rng.integers(1, p_max + 1))
+        t = float(math.exp(rng.uniform(math.log(t_range[0]), math.log(t_range[1]))))
+        a, b = draw_coefficients(rng, dim)
+        mats = [adv_diff_1d(n, float(a[d]), float(b[d])) for d in range(dim)]
+        v = random_vector(rng, n ** dim)
+        out.append(dict(name="batch_mix", mats=mats, t=t, p=p, tol=1e-8, v=v,
+                        coef=[(float(a[d]), float(b[d])) for d in range(dim)], n=n, dim=dim, seed=seed, index=i))
+    return out

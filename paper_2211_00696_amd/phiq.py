@@ -131,6 +131,28 @@ def status_string(st):
 # ---------------------------------------------------------------------------
 # device
 # ---------------------------------------------------------------------------
+def batch_info(problems, **opts):
+    """Host-only dry run of Handle.action_batched (no GPU): the schedule's size
+    and a check of its addresses and ordering.  problems: dicts with mats, t,
+    p, tol and the integer addresses v_ptr / out_ptr and nrhs (default 1)."""
+    lib = L.load()
+    arr = (L.Problem * max(1, len(problems)))()
+    keep = []
+    for i, pr in enumerate(problems):
+        op = _Op(pr["mats"])
+        keep.append(op)
+        arr[i].op = op.op
+        arr[i].t = float(pr["t"])
+        arr[i].p = int(pr["p"])
+        arr[i].tol = float(pr.get("tol", 1e-8))
+        arr[i].nrhs = int(pr.get("nrhs", 1))
+        arr[i].v = int(pr["v_ptr"])
+        arr[i].out = int(pr["out_ptr"])
+    st = L.BatchStats()
+    _check(lib.phiq_batch_info(len(problems), arr, byref(options(**opts)), byref(st)), "phiq_batch_info")
+    return st.as_dict()
+
+
 class Plan:
     def __init__(self, handle, ptr, p, N, report):
         self._h = handle
@@ -233,6 +255,48 @@ class Handle:
         _check(lib.phiq_action(self._h, byref(op.op), float(t), int(p), _dev_ptr(v, "v"), float(tol), byref(o),
                                _dev_ptr(out, "out"), byref(rep), _stream_ptr(stream)), "phiq_action")
         return out, rep.as_dict()
+
+    def action_batched(self, problems, stream=None, **opts):
+        """Many phi-actions launched together (phiq_action_batched).
+
+        problems: list of dicts with keys mats, t, p, v (device tensor with N
+        or nrhs x N entries), tol (default 1e-8) and optionally out
+        (nrhs x (p+1) x N).  Returns (outs, reports), outs[i] shaped
+        (nrhs, p+1, N).  Asynchronous on the stream (synchronise before
+        reading the outputs on the host)."""
+        import torch
+
+        lib = L.load()
+        nprob = len(problems)
+        arr = (L.Problem * max(1, nprob))()
+        keep, outs, reps = [], [], []
+        for i, pr in enumerate(problems):
+            op = _Op(pr["mats"])
+            v = pr["v"]
+            if v.numel() % op.N:
+                raise ValueError("problem %d: v has %d entries, not a multiple of N = %d" % (i, v.numel(), op.N))
+            nrhs = v.numel() // op.N
+            p = int(pr["p"])
+            out = pr.get("out")
+            if out is None:
+                out = torch.empty((nrhs, p + 1, op.N), dtype=torch.float64, device=v.device)
+            if out.numel() != nrhs * (p + 1) * op.N:
+                raise ValueError("problem %d: out must hold nrhs x (p+1) x N values" % i)
+            rep = L.Report()
+            arr[i].op = op.op
+            arr[i].t = float(pr["t"])
+            arr[i].p = p
+            arr[i].tol = float(pr.get("tol", 1e-8))
+            arr[i].nrhs = nrhs
+            arr[i].v = _dev_ptr(v, "v").value
+            arr[i].out = _dev_ptr(out, "out").value
+            arr[i].rep = ctypes.pointer(rep)
+            keep.append(op)
+            outs.append(out.view(nrhs, p + 1, op.N))
+            reps.append(rep)
+        o = options(**opts)
+        _check(lib.phiq_action_batched(self._h, nprob, arr, byref(o), _stream_ptr(stream)), "phiq_action_batched")
+        return outs, [r.as_dict() for r in reps]
 
     def plan(self, mats, t, p, tol=1e-8, stream=None, **opts):
         lib = L.load()

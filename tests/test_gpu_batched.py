@@ -1,0 +1,138 @@
+"""phiq_action_batched (stages of all problems, one launch per dependency
+depth) against the oracle and against separate phiq_action calls.
+
+Parity bar: relative max-norm error per phi_k against the oracle below
+1e-10 (requested tolerance 1e-8; the method reaches ~1e-13 here), and
+against the single-problem HIP path (same parameters, same kernels' tile
+arithmetic in another order) below 1e-12.
+"""
+import numpy as np
+import pytest
+
+from oracle import phi_exact as X, phiquad as Q
+from paper_2211_00696_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def h():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2211_00696_amd import phiq
+
+    hd = phiq.Handle(0)
+    yield hd
+    hd.close()
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def rel(a, b):
+    d = np.max(np.abs(b))
+    return float(np.max(np.abs(a - b)) / d) if d > 0 else float(np.max(np.abs(a)))
+
+
+def oracle(pr, v):
+    N = v.size
+    if N <= 1200:
+        return X.phi_dense_aug(pr["mats"], pr["t"], v, pr["p"])
+    return Q.phiquadmv(pr["mats"], pr["t"], v, pr["p"], eps=1e-14, beta=1.0)
+
+
+def small_mix():
+    rng = np.random.default_rng(11)
+    cases = [(1, 7, 2, 1e-2, 1), (1, 130, 4, 1e-3, 2), (2, 9, 3, 1e-2, 1), (2, 33, 4, 0.0, 1),
+             (2, 20, 1, 5e-2, 3), (3, 9, 0, 1e-2, 1), (3, 10, 3, 1e-2, 2), (3, 13, 4, 2e-3, 1),
+             (2, 65, 2, 1e-1, 1), (4, 5, 2, 1e-2, 1)]
+    probs = []
+    for dim, n, p, t, nrhs in cases:
+        a, b = I.draw_coefficients(rng, dim)
+        mats = [I.adv_diff_1d(n, float(a[d]), float(b[d])) for d in range(dim)]
+        v = rng.standard_normal((nrhs, n ** dim))
+        probs.append(dict(mats=mats, t=t, p=p, tol=1e-8, vh=v, name=f"dim{dim} n{n} p{p} t{t} nrhs{nrhs}"))
+    return probs
+
+
+def run_and_check(h, probs, oracle_idx, **opts):
+    print("batch of", len(probs), [p.get("name", "") for p in probs[:3]], flush=True)
+    bp = [dict(mats=p["mats"], t=p["t"], p=p["p"], tol=p["tol"], v=dev(p["vh"])) for p in probs]
+    outs, reps = h.action_batched(bp, **opts)
+    torch.cuda.synchronize()
+    worst_sep, worst_orc = 0.0, 0.0
+    for i, pr in enumerate(probs):
+        o = outs[i].cpu().numpy()
+        vh = np.atleast_2d(pr["vh"])
+        for r in range(vh.shape[0]):
+            ref, rep = h.action(pr["mats"], pr["t"], pr["p"], dev(vh[r]), tol=pr["tol"], **opts)
+            ref = ref.cpu().numpy()
+            e = max(rel(o[r, k], ref[k]) for k in range(pr["p"] + 1))
+            worst_sep = max(worst_sep, e)
+            assert e < 1e-12, (i, r, pr.get("name"), e)
+            assert reps[i]["l"] == rep["l"] and reps[i]["m"] == rep["m"], (i, reps[i], rep)
+            if i in oracle_idx:
+                orc = oracle(pr, vh[r])
+                eo = max(rel(o[r, k], orc[k]) for k in range(pr["p"] + 1))
+                worst_orc = max(worst_orc, eo)
+                assert eo < 1e-10, (i, r, pr.get("name"), eo)
+    print("worst vs separate calls %.2e, vs oracle %.2e" % (worst_sep, worst_orc), flush=True)
+    return outs, reps
+
+
+def test_batched_small_mix_vs_oracle(h):
+    probs = small_mix()
+    run_and_check(h, probs, oracle_idx=set(range(len(probs))))
+
+
+def test_batched_phi_of_zero_time(h):
+    # t = 0: phi_k(0) v = v / k!
+    probs = small_mix()
+    pr = probs[3]
+    outs, _ = h.action_batched([dict(mats=pr["mats"], t=0.0, p=4, v=dev(pr["vh"]))])
+    o = outs[0].cpu().numpy()[0]
+    f = 1.0
+    for k in range(5):
+        assert np.max(np.abs(o[k] - pr["vh"][0] / f)) <= 1e-15 * np.max(np.abs(pr["vh"])), k
+        f *= k + 1
+
+
+def test_batched_with_separate_problems(h):
+    # p > 4 leaves the batched launches; the call still returns every result
+    probs = small_mix()[:4]
+    probs[1] = dict(probs[1], p=6, name="p6")
+    run_and_check(h, probs, oracle_idx={0, 1})
+
+
+def test_batched_mixed_sizes_sampled_oracle(h):
+    mix = I.batch_mix(seed=7, count=40, n_min=16, n_max=72)
+    probs = [dict(mats=p["mats"], t=p["t"], p=p["p"], tol=p["tol"], vh=p["v"][None, :],
+                  name="mix%d dim%d n%d p%d" % (p["index"], p["dim"], p["n"], p["p"])) for p in mix]
+    small = [i for i, p in enumerate(mix) if p["n"] ** p["dim"] <= 40000][:5]
+    run_and_check(h, probs, oracle_idx=set(small))
+
+
+def test_batched_arena_reuse_smaller_second_call(h):
+    probs = small_mix()
+    run_and_check(h, probs[:6], oracle_idx={0})
+    run_and_check(h, probs[6:8], oracle_idx={0})
+
+
+def test_batched_rejects_overlapping_outputs(h):
+    from paper_2211_00696_amd.phiq import PhiqError
+
+    probs = small_mix()[:2]
+    out = torch.empty(2 * 4 * 130, dtype=torch.float64, device="cuda")
+    bp = [dict(mats=probs[0]["mats"], t=0.01, p=2, v=dev(probs[0]["vh"]), out=out[: 3 * 7]),
+          dict(mats=probs[0]["mats"], t=0.01, p=2, v=dev(probs[0]["vh"]), out=out[10: 10 + 3 * 7])]
+    with pytest.raises(PhiqError, match="INVALID_ARG"):
+        h.action_batched(bp)
+
+
+@pytest.mark.skip(reason="a single persistent launch whose workgroups waited on completion counters "
+                         "blocked until the 120 s test timeout on its first GPU run; the cause was not "
+                         "shown, so that variant was removed (batches run one launch per dependency depth)")
+def test_batched_single_persistent_launch():
+    pass
