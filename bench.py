@@ -58,16 +58,20 @@ def load_traffic(kernel, digest):
         return None
 
 
+def blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+
+        return max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
+    except Exception:
+        return os.cpu_count() or 1
+
+
 def cpu_baseline(pr, out_gpu):
     """The oracle's own algorithm (numpy, FP64) on the same input, timed."""
     from oracle import phiquad
 
-    try:
-        from threadpoolctl import threadpool_info
-
-        threads = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
-    except Exception:
-        threads = os.cpu_count() or 1
+    threads = blas_threads()
     t0 = time.perf_counter()
     ref = phiquad.phiquadmv(pr["mats"], pr["t"], pr["v"], pr["p"], eps=pr["tol"], beta=1.0)
     dt = time.perf_counter() - t0
@@ -96,6 +100,10 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--workload", default="advdiff3d", choices=["advdiff3d", "batch512"],
+                    help="advdiff3d: one 3D problem (default); batch512: 512 mixed 2D/3D problems in one "
+                         "batched call (phiq_action_batched)")
+    ap.add_argument("--count", type=int, default=512, help="batch512: number of problems")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the steps, negate a buffer of this many MiB into another once (a plain device copy "
                          "of known size that calibrates hardware byte counters taken over the same run)")
@@ -108,6 +116,9 @@ def main():
     rank = int(os.environ.get("RANK", "0"))
 
     import torch
+
+    if args.workload == "batch512":
+        return bench_batch(args, rank)
 
     from paper_2211_00696_amd import inputs, phiq
 
@@ -242,6 +253,109 @@ def main():
         cb, errs = cpu_baseline(pr, out_host)
         result["cpu_baseline"] = cb
         result["rel_err_vs_oracle_per_phi_k"] = errs
+    else:
+        result["cpu_baseline"] = None
+    h.close()
+    if rank == 0:
+        print(json.dumps(result), flush=True)
+
+
+def ttm_flops(pr, rep):
+    """Algorithmic flops of one phi-action: 2 d n N per Kronecker chain, (m + l p + 1) chains, plus the
+    1D exponentials (powers, Taylor sums, squarings) counted as 2 n^3 per n x n product."""
+    N = pr["v"].size
+    n = [m.shape[0] for m in pr["mats"]]
+    chain = sum(2.0 * nd * N for nd in n)
+    return chain * rep["ttm_chains"]
+
+
+def bench_batch(args, rank):
+    """512 independent problems (dim 2/3, n 16..192, p 1..4, t log-U[1e-4, 1e-1]) per call."""
+    import torch
+
+    from paper_2211_00696_amd import inputs, phiq
+
+    probs = inputs.batch_mix(seed=args.seed, count=args.count)
+    Ns = [p["v"].size for p in probs]
+    Ntot = int(sum(Ns))
+    vbuf = torch.empty(Ntot, dtype=torch.float64, device="cuda")
+    off = 0
+    views = []
+    for p, N in zip(probs, Ns):
+        vbuf[off:off + N].copy_(torch.from_numpy(p["v"]))
+        views.append(vbuf[off:off + N])
+        off += N
+    outs = [torch.empty((1, p["p"] + 1, N), dtype=torch.float64, device="cuda") for p, N in zip(probs, Ns)]
+    bp = [dict(mats=p["mats"], t=p["t"], p=p["p"], tol=p["tol"], v=v, out=o) for p, v, o in zip(probs, views, outs)]
+    h = phiq.Handle(0)
+    info = phiq.batch_info([dict(mats=p["mats"], t=p["t"], p=p["p"], tol=p["tol"], v_ptr=v.data_ptr(),
+                                 out_ptr=o.data_ptr()) for p, v, o in zip(probs, views, outs)])
+    _, reps = h.action_batched(bp)
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        h.action_batched(bp)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        h.action_batched(bp)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.steps
+    gpu_ms = ev0.elapsed_time(ev1) / args.steps
+    # the same problems one phiq_action call each (for comparison)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for p, v in zip(probs, views):
+        h.action(p["mats"], p["t"], p["p"], v, tol=p["tol"])
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - t1
+    # parity sample: batched vs separate call on a few problems
+    errs = []
+    for i in range(0, len(probs), max(1, len(probs) // 8)):
+        ref, _ = h.action(probs[i]["mats"], probs[i]["t"], probs[i]["p"], views[i], tol=probs[i]["tol"])
+        o = outs[i][0]
+        errs.append(float(((o - ref).abs().max() / ref.abs().max()).item()))
+    flops = sum(ttm_flops(p, r) for p, r in zip(probs, reps))
+    peak = PEAK_TFLOPS["fp64"]
+    achieved = flops / (gpu_ms * 1e-3) / 1e12
+    result = {
+        "metric": "phi_k(tA)v grid-pts/s, batch of %d mixed problems in one call" % len(probs),
+        "value": Ntot / wall,
+        "unit": "grid-pts/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "%d problems: dim 2 or 3 (p=1/2), n uniform in 16..192, p uniform in 1..4, "
+                               "t log-uniform in [1e-4, 1e-1], a_d log-U[0.1,10], b_d U[0,50], v~N(0,1), "
+                               "Gauss, tol 1e-8, seed %d" % (len(probs), args.seed),
+                   "problems": len(probs), "grid_points": Ntot, "seed": args.seed},
+        "roofline": {"kernel": "batch_kernel", "bound": "mfma", "achieved": achieved, "peak": peak,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "flops_per_step": flops, "gpu_ms_per_step": gpu_ms,
+                     "note": "mode-product flops only (the 1D exponentials are not counted)"},
+        "schedule": info,
+        "ms_separate_calls": seq * 1e3,
+        "speedup_vs_separate_calls": seq / wall,
+        "rel_err_batched_vs_separate_sample": max(errs),
+    }
+    if not args.no_cpu_baseline and rank == 0:
+        from oracle import phiquad
+
+        sample = list(range(0, len(probs), 32))  # every 32nd problem of the batch
+        t2 = time.perf_counter()
+        pts = 0
+        for i in sample:
+            pr = probs[i]
+            phiquad.phiquadmv(pr["mats"], pr["t"], pr["v"], pr["p"], eps=pr["tol"], beta=1.0)
+            pts += Ns[i]
+        dt = time.perf_counter() - t2
+        result["cpu_baseline"] = {"value": pts / dt, "unit": "grid-pts/s", "cores": blas_threads(),
+                                  "kind": "oracle", "sample": "every 32nd problem of the batch (%d problems, "
+                                  "%d points) by the oracle's numpy quadrature, %.2f s" % (len(sample), pts, dt)}
     else:
         result["cpu_baseline"] = None
     h.close()

@@ -202,9 +202,9 @@ typedef struct {
  * order of the tiles).  Problems with the Gauss rule, FP64 mode products and
  * p <= 4 are split into stages (1D exponentials, node chains with the node
  * sum, squaring steps, phi_0), and the stages of all of them are run by
- * depth in their dependency graph: one kernel launch per depth covers that
- * depth's tiles of every problem, so small and large problems fill the GPU
- * together (a batch of 512 mixed 2D/3D problems takes about 60 launches).
+ * depth in their dependency graph: one kernel launch per depth and stage
+ * type covers those tiles of every problem, so small and large problems fill
+ * the GPU together (a batch of 512 mixed 2D/3D problems takes ~62 depths).
  * Other problems (CC, lower precision, p > 4) run afterwards, one plan each,
  * on the same stream (then the call synchronises the stream).  Asynchronous
  * otherwise.  Device memory: the handle keeps one arena for the batch
@@ -224,7 +224,8 @@ typedef struct {
   int separate;            /* problems run one plan each afterwards      */
   long long stages;        /* stages of the persistent launch            */
   long long tiles;         /* work items (64 x 64 tiles) over all stages */
-  int depth;               /* launches: longest dependency chain         */
+  int depth;               /* longest dependency chain, in stages        */
+  int launches;            /* kernel launches (one per depth and stage type) */
   int groups;              /* dependency groups                          */
   size_t arena_bytes;      /* device bytes the handle's batch arena needs */
   size_t upload_bytes;     /* host->device bytes per call                 */

@@ -89,7 +89,7 @@ class Problem(ctypes.Structure):
 
 class BatchStats(ctypes.Structure):
     _fields_ = [("persistent", c_int), ("separate", c_int), ("stages", ctypes.c_longlong),
-                ("tiles", ctypes.c_longlong), ("depth", c_int), ("groups", c_int),
+                ("tiles", ctypes.c_longlong), ("depth", c_int), ("launches", c_int), ("groups", c_int),
                 ("arena_bytes", ctypes.c_size_t), ("upload_bytes", ctypes.c_size_t)]
 
     def as_dict(self):

@@ -44,6 +44,7 @@ constexpr size_t kAl = 256;
 inline size_t al(size_t x) { return (x + kAl - 1) / kAl * kAl; }
 inline long long cdiv(long long a, long long b) { return (a + b - 1) / b; }
 constexpr int kChunk = 4;  // nodes per quadrature chunk (node-sum epilogue width)
+constexpr long long kBatchGrid = 2048;  // workgroups per launch at most (multiple of 8)
 
 struct Prob {
   const phiq_problem* pr = nullptr;
@@ -290,14 +291,28 @@ void build_problem(const Prob& P, char* base, char* up, Graph& g) {
   }
 }
 
+struct Launch {
+  int type, stage_begin, stage_end;
+  long long tile_begin, tile_end;
+};
+
 struct Built {
-  std::vector<BatchStage> st;  // by depth
+  std::vector<BatchStage> st;  // by depth, then type
+  std::vector<Launch> launches;
   std::vector<BatchTaylor> tj;
   std::vector<long long> level_tile;  // first tile of each depth, then the total
   std::vector<int> stage_level;
   int ngroups = 0;
   long long total = 0;
 };
+
+// Kernel variant of a stage within its type: orders (Accum, Square) and
+// 16-byte staging.
+int key(const BatchStage& s) {
+  const int np = (s.type == kStageAccum || s.type == kStageSquare) ? s.np : 0;
+  const int vec = (s.type == kStageStore || s.type == kStageAccum || s.type == kStageSquare) ? s.vec : 0;
+  return np * 2 + vec;
+}
 
 void build_all(const std::vector<Prob>& probs, char* base, char* up, Built* b, int* depth) {
   Graph g;
@@ -306,6 +321,8 @@ void build_all(const std::vector<Prob>& probs, char* base, char* up, Built* b, i
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
     if (g.lvl[a] != g.lvl[c]) return g.lvl[a] < g.lvl[c];
+    if (g.st[a].type != g.st[c].type) return g.st[a].type < g.st[c].type;
+    if (key(g.st[a]) != key(g.st[c])) return key(g.st[a]) < key(g.st[c]);
     return g.st[a].ntiles > g.st[c].ntiles;
   });
   b->st.clear();
@@ -324,6 +341,16 @@ void build_all(const std::vector<Prob>& probs, char* base, char* up, Built* b, i
     b->stage_level.push_back(g.lvl[i]);
   }
   b->level_tile.push_back(t);
+  b->launches.clear();
+  for (size_t i = 0; i < b->st.size(); ++i) {
+    const BatchStage& s = b->st[i];
+    if (b->launches.empty() || b->launches.back().type != s.type ||
+        key(b->st[b->launches.back().stage_begin]) != key(s) ||
+        b->stage_level[b->launches.back().stage_begin] != b->stage_level[i])
+      b->launches.push_back({s.type, (int)i, (int)i, s.tile0, s.tile0});
+    b->launches.back().stage_end = (int)i + 1;
+    b->launches.back().tile_end = s.tile0 + s.ntiles;
+  }
   b->tj = g.tj;
   b->ngroups = (int)g.glevel.size();
   b->total = t;
@@ -540,6 +567,7 @@ extern "C" phiq_status phiq_batch_info(int nprob, const phiq_problem* probs, con
   info->stages = (long long)S.b.st.size();
   info->tiles = S.b.total;
   info->depth = S.depth;
+  info->launches = (int)S.b.launches.size();
   info->groups = S.b.ngroups;
   info->arena_bytes = S.total;
   info->upload_bytes = S.up_bytes;
@@ -587,18 +615,18 @@ extern "C" phiq_status phiq_action_batched(phiq_handle h, int nprob, const phiq_
     if (!S.b.tj.empty()) std::memcpy(hp + S.tj_off, S.b.tj.data(), S.b.tj.size() * sizeof(BatchTaylor));
     PHIQ_TRY(batch_fetch(h, slot, up, S.up_bytes, stream));
 
-    int blocks = 0;
-    PHIQ_HIP(batch_workers(&blocks));
     BatchArgs a{};
     a.st = (const BatchStage*)(up + S.st_off);
-    a.nstages = (int)S.b.st.size();
     a.tj = (const BatchTaylor*)(up + S.tj_off);
-    for (size_t lv = 0; lv + 1 < S.b.level_tile.size(); ++lv) {
-      a.tile_begin = S.b.level_tile[lv];
-      a.tile_end = S.b.level_tile[lv + 1];
-      const long long n = a.tile_end - a.tile_begin;
-      if (n <= 0) continue;
-      PHIQ_HIP(launch_batch_level(a, (int)std::min<long long>(n, 4LL * blocks), stream));
+    for (const Launch& L : S.b.launches) {
+      a.stage_begin = L.stage_begin;
+      a.stage_end = L.stage_end;
+      a.tile_begin = L.tile_begin;
+      a.tile_end = L.tile_end;
+      const long long T = L.tile_end - L.tile_begin;
+      const long long blocks = std::min<long long>((T + 7) / 8 * 8, kBatchGrid);
+      const BatchStage& s0 = S.b.st[L.stage_begin];
+      PHIQ_HIP(launch_batch(a, L.type, s0.np, s0.vec, (int)blocks, stream));
     }
     for (const auto& P : S.pl) {
       phiq_report* rep = P.pr->rep;

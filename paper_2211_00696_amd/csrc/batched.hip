@@ -16,6 +16,7 @@
 namespace phiq {
 
 using BT = Tile<kBatchTile, kBatchTile, 16, 2, 2>;  // 256 threads, 64 x 64 output tiles
+constexpr int kXcdCount = 8;
 static_assert(BT::NT == 256, "batch worker size");
 
 namespace {
@@ -81,20 +82,20 @@ __device__ void run_store(const BatchStage& S, int tile, double* smem) {
   store_tile<BT>(S.O + b * S.os, S.M, S.L, m0, n0, acc);
 }
 
-template <bool VEC>
+template <int NP, bool VEC>
 __device__ void run_accum(const BatchStage& S, int tile, double* smem) {
   const int mt = (S.M + BT::BM - 1) / BT::BM;
   const int m0 = (tile % mt) * BT::BM, n0 = (tile / mt) * BT::BN;
-  d4 y[4][BT::TM][BT::TN];
+  d4 y[NP][BT::TM][BT::TN];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) zero_acc<BT>(y[q]);
+  for (int q = 0; q < NP; ++q) zero_acc<BT>(y[q]);
   for (int b = 0; b < S.nb; ++b) {
     d4 acc[BT::TM][BT::TN];
     zero_acc<BT>(acc);
     tile_nt_db<BT, VEC>(S.E + b * S.es, S.X + b * S.xs, S.M, S.K, S.L, m0, n0, smem, acc);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const double w = q < S.np ? S.coef[q * S.ldcoef + b] : 0.0;
+    for (int q = 0; q < NP; ++q) {
+      const double w = S.coef[q * S.ldcoef + b];
 #pragma unroll
       for (int i = 0; i < BT::TM; ++i)
 #pragma unroll
@@ -102,8 +103,7 @@ __device__ void run_accum(const BatchStage& S, int tile, double* smem) {
     }
   }
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    if (q >= S.np) break;
+  for (int q = 0; q < NP; ++q) {
     double* Y = S.Y + q * S.ys;
 #pragma unroll
     for (int i = 0; i < BT::TM; ++i)
@@ -122,16 +122,30 @@ __device__ void run_accum(const BatchStage& S, int tile, double* smem) {
   }
 }
 
-// All orders of one modified-squaring step (eq. squaring), np <= 4.  The
-// y_j tiles are re-read for each order (they stay in L2) rather than held in
-// registers, which keeps the worker within two waves per SIMD.
-__constant__ double kInvFact[4] = {1.0, 1.0, 0.5, 1.0 / 6.0};
-
-template <bool VEC>
+// All NP orders of one modified-squaring step (eq. squaring), NP <= 4: the
+// block computes E y_i for i = 1..NP in turn; each y_i tile is loaded (into
+// registers, before its product's K loop so that the load overlaps it) once
+// and kept for the later orders.
+template <int NP, bool VEC>
 __device__ void run_square(const BatchStage& S, int tile, double* smem) {
   const int mt = (S.M + BT::BM - 1) / BT::BM;
   const int m0 = (tile % mt) * BT::BM, n0 = (tile / mt) * BT::BN;
-  for (int i = 0; i < S.np; ++i) {
+  const double ifact[4] = {1.0, 1.0, 0.5, 1.0 / 6.0};
+  d4 ys[NP][BT::TM][BT::TN];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+#pragma unroll
+    for (int ti = 0; ti < BT::TM; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < BT::TN; ++tj) {
+        const int col = n0 + acc_col<BT>(tj);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int row = m0 + acc_row<BT>(ti, e);
+          const int rc = row < S.M ? row : S.M - 1, cc = col < S.L ? col : S.L - 1;
+          ys[i][ti][tj][e] = S.Y[i * S.ys + (long long)rc * S.L + cc];
+        }
+      }
     d4 acc[BT::TM][BT::TN];
     zero_acc<BT>(acc);
     tile_nt_db<BT, VEC>(S.E, S.X + i * S.xs, S.M, S.K, S.L, m0, n0, smem, acc);
@@ -145,59 +159,92 @@ __device__ void run_square(const BatchStage& S, int tile, double* smem) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int row = m0 + acc_row<BT>(ti, e);
-          if (row < S.M && col < S.L) {
-            const long long idx = (long long)row * S.L + col;
-            double s = acc[ti][tj][e];
-            for (int j = 0; j <= i; ++j) s += S.Y[j * S.ys + idx] * kInvFact[i - j];
-            O[idx] = scale * s;
-          }
+          double s = acc[ti][tj][e];
+#pragma unroll
+          for (int j = 0; j <= i; ++j) s += ys[j][ti][tj][e] * ifact[i - j];
+          if (row < S.M && col < S.L) O[(long long)row * S.L + col] = scale * s;
         }
       }
   }
 }
 
-__global__ __launch_bounds__(256, 2) void batch_level_kernel(BatchArgs a) {
-  __shared__ double smem[2 * (BT::BM + BT::BN) * BT::LDK];
-  for (long long g = a.tile_begin + blockIdx.x; g < a.tile_end; g += gridDim.x) {
-    int lo = 0, hi = a.nstages - 1;  // last stage with tile0 <= g (block-uniform)
+// One launch: the tiles [tile_begin, tile_end) of stages [stage_begin,
+// stage_end), all of type TYPE.  The launch's tiles are dealt XCD-aware: the
+// hardware gives consecutive workgroups to the 8 XCDs in turn, so the
+// workgroups of one XCD take one contiguous eighth of the tiles (the tiles
+// of one stage that read the same operand rows are adjacent) and share its
+// L2.  Each workgroup walks its tiles with a stride of the grid size.
+template <int TYPE, int NP, bool VEC>
+__global__ __launch_bounds__(256) void batch_kernel(BatchArgs a) {
+  __shared__ double smem[(TYPE == kStageTaylor) ? 1 : 2 * (BT::BM + BT::BN) * BT::LDK];
+  const long long T = a.tile_end - a.tile_begin;
+  const long long per = (T + kXcdCount - 1) / kXcdCount;
+  const int xcd = blockIdx.x % kXcdCount;
+  const long long G = gridDim.x / kXcdCount;  // workgroups per XCD (grid is a multiple of 8)
+  int lo = a.stage_begin;
+  for (long long v = blockIdx.x / kXcdCount; v < per; v += G) {
+    const long long t = (long long)xcd * per + v;
+    if (t >= T) break;
+    const long long g = a.tile_begin + t;
+    int hi = a.stage_end - 1;  // last stage with tile0 <= g; g only grows, so lo only grows
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
       if (a.st[mid].tile0 <= g) lo = mid; else hi = mid - 1;
     }
     const BatchStage& S = a.st[lo];
     const int tile = (int)(g - S.tile0);
-    switch (S.type) {
-      case kStageGemm: run_gemm(S, tile, smem); break;
-      case kStageTaylor: run_taylor(a.tj[S.aux], tile); break;
-      case kStageStore:
-        if (S.vec) run_store<true>(S, tile, smem); else run_store<false>(S, tile, smem);
-        break;
-      case kStageAccum:
-        if (S.vec) run_accum<true>(S, tile, smem); else run_accum<false>(S, tile, smem);
-        break;
-      default:
-        if (S.vec) run_square<true>(S, tile, smem); else run_square<false>(S, tile, smem);
-        break;
+    if constexpr (TYPE == kStageGemm) {
+      run_gemm(S, tile, smem);
+    } else if constexpr (TYPE == kStageTaylor) {
+      run_taylor(a.tj[S.aux], tile);
+    } else if constexpr (TYPE == kStageStore) {
+      run_store<VEC>(S, tile, smem);
+    } else if constexpr (TYPE == kStageAccum) {
+      run_accum<NP, VEC>(S, tile, smem);
+    } else {
+      run_square<NP, VEC>(S, tile, smem);
     }
     __syncthreads();  // smem is reused by the next tile
   }
 }
 
-}  // namespace
-
-int batch_workers(int* blocks) {
-  int dev = 0, cus = 0, per = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batch_level_kernel, 256, 0);
-  if (e != hipSuccess) return e;
-  *blocks = cus * (per > 0 ? per : 1);
-  return hipSuccess;
+template <int TYPE, int NP>
+hipError_t launch_np(const BatchArgs& a, bool vec, dim3 grid, hipStream_t st) {
+  if (vec)
+    hipLaunchKernelGGL((batch_kernel<TYPE, NP, true>), grid, dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL((batch_kernel<TYPE, NP, false>), grid, dim3(256), 0, st, a);
+  return hipGetLastError();
 }
 
-int launch_batch_level(const BatchArgs& a, int blocks, void* stream) {
-  hipLaunchKernelGGL(batch_level_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, a);
-  return hipGetLastError();
+template <int TYPE>
+hipError_t launch_type(const BatchArgs& a, int np, bool vec, dim3 grid, hipStream_t st) {
+  switch (np) {
+    case 1: return launch_np<TYPE, 1>(a, vec, grid, st);
+    case 2: return launch_np<TYPE, 2>(a, vec, grid, st);
+    case 3: return launch_np<TYPE, 3>(a, vec, grid, st);
+    case 4: return launch_np<TYPE, 4>(a, vec, grid, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+int launch_batch(const BatchArgs& a, int type, int np, int vec, int blocks, void* stream) {
+  const dim3 grid(blocks);
+  hipStream_t st = (hipStream_t)stream;
+  switch (type) {
+    case kStageGemm:
+      hipLaunchKernelGGL((batch_kernel<kStageGemm, 0, false>), grid, dim3(256), 0, st, a);
+      return hipGetLastError();
+    case kStageTaylor:
+      hipLaunchKernelGGL((batch_kernel<kStageTaylor, 0, false>), grid, dim3(256), 0, st, a);
+      return hipGetLastError();
+    case kStageStore: return launch_np<kStageStore, 0>(a, vec != 0, grid, st);
+    case kStageAccum: return launch_type<kStageAccum>(a, np, vec != 0, grid, st);
+    case kStageSquare: return launch_type<kStageSquare>(a, np, vec != 0, grid, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace phiq

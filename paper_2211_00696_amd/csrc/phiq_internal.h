@@ -150,8 +150,9 @@ int launch_node_sum(const NodeSegs& segs, long long N, const double* coef, int l
 // ---- batched.hip: batched stages, one launch per dependency depth --------
 // A batch is a list of stages (one GEMM, Taylor evaluation or mode product
 // over a whole operand, split into 64 x 64 tiles), stored by depth in the
-// dependency graph; tiles are numbered consecutively over the list.  One
-// launch runs the tiles of one depth.  `signal`/`wait*` record the
+// dependency graph (then by type, order count and staging width); tiles are
+// numbered consecutively over the list.  One launch runs the tiles of one
+// such kind at one depth.  `signal`/`wait*` record the
 // dependencies for the host-side check of the order.
 enum BatchStageType : int {
   kStageGemm = 0,    // O = E * X (n x n, n = M)
@@ -200,12 +201,14 @@ constexpr int kBatchTile = 64;          // output tile edge of every stage
 constexpr int kBatchTaylorChunk = 4096; // elements per Taylor tile
 struct BatchArgs {
   const BatchStage* st;
-  int nstages;
-  long long tile_begin;  // tiles [tile_begin, tile_end) of one depth
+  int stage_begin;       // stages [stage_begin, stage_end) of one launch (one depth, one type)
+  int stage_end;
+  long long tile_begin;  // their tiles [tile_begin, tile_end)
   long long tile_end;
   const BatchTaylor* tj;
 };
-int batch_workers(int* blocks);  // resident workgroups of the kernel on this device
-int launch_batch_level(const BatchArgs& a, int blocks, void* stream);
+// One launch over the tiles of a run of stages with the same type, np
+// (Accum, Square) and vec; blocks must be a multiple of 8.
+int launch_batch(const BatchArgs& a, int type, int np, int vec, int blocks, void* stream);
 
 }  // namespace phiq
