@@ -233,6 +233,30 @@ typedef struct {
 phiq_status phiq_batch_info(int nprob, const phiq_problem* probs, const phiq_options* opt,
                             phiq_batch_stats* info);
 
+/* Exponential time differencing of order four (Cox and Matthews' ETD-RK4,
+ * the paper's reference cox2002exponential; Section 5 runs lower-order
+ * exponential integrators on the same phi-function actions) for
+ *   u' = -A u + c1 u + c3 u^3,   A = sum_d A^d as for phiq_action,
+ * nsteps steps of size tau, in place on u (DEVICE, N values).  Each step uses
+ * e^{-tau A/2}, phi_1(-tau A/2), e^{-tau A} and phi_1..3(-tau A) (four plans
+ * built once per call, tolerance tol relative to the vector's max norm);
+ * the last one acts on three vectors in one plan execution.
+ * use_graph = 1: the first step runs directly, the second is captured into a
+ * hipGraph (on a stream of the call's own) and replayed for every later step.
+ * The call allocates a work buffer of 27 N doubles and returns when the
+ * steps have finished.  rep (nullable) gets the plans and how the steps ran. */
+typedef struct {
+  int steps_eager;          /* steps launched directly                      */
+  int steps_graph;          /* steps replayed from the captured graph       */
+  int graph_nodes;          /* nodes (kernels) of one captured step         */
+  int ttm_chains_per_step;  /* Kronecker chains of 1D factors per step      */
+  int l_half, m_half;       /* plan of phi_0..1(-tau A/2)                   */
+  int l_full, m_full;       /* plan of phi_0..3(-tau A)                     */
+} phiq_etd_report;
+phiq_status phiq_etdrk4(phiq_handle h, const phiq_kron_op* op, double tau, int nsteps,
+                        double c1, double c3, double tol, int use_graph, double* u,
+                        phiq_etd_report* rep, hipStream_t stream);
+
 /* Building blocks (also used by the tests).
  *
  * phiq_expm: E[b] = exp(X[b]) for nmat matrices n x n, DEVICE row-major

@@ -39,6 +39,7 @@ EXPORTS = [
     "phiq_action",
     "phiq_action_batched",
     "phiq_batch_info",
+    "phiq_etdrk4",
     "phiq_expm",
     "phiq_kron_apply",
     "phiq_profile_start",
@@ -96,6 +97,15 @@ class BatchStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class EtdReport(ctypes.Structure):
+    _fields_ = [("steps_eager", c_int), ("steps_graph", c_int), ("graph_nodes", c_int),
+                ("ttm_chains_per_step", c_int), ("l_half", c_int), ("m_half", c_int),
+                ("l_full", c_int), ("m_full", c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class KernelStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 24), ("launches", c_int), ("ms", c_double), ("flops", c_double),
                 ("bytes", c_double)]
@@ -131,6 +141,8 @@ def load():
                                 P(Report), c_void_p]),
         "phiq_action_batched": (c_int, [c_void_p, c_int, P(Problem), P(Options), c_void_p]),
         "phiq_batch_info": (c_int, [c_int, P(Problem), P(Options), P(BatchStats)]),
+        "phiq_etdrk4": (c_int, [c_void_p, P(KronOp), c_double, c_int, c_double, c_double, c_double, c_int,
+                                c_void_p, P(EtdReport), c_void_p]),
         "phiq_expm": (c_int, [c_void_p, c_int, c_int, c_void_p, P(c_double), c_void_p, c_void_p]),
         "phiq_kron_apply": (c_int, [c_void_p, c_int, P(c_int), P(c_void_p), c_void_p, c_void_p, c_int, c_int,
                                     c_void_p]),

@@ -10,7 +10,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libphiq.so")
 
-SOURCES = ["kernels.hip", "kernels_lowp.hip", "batched.hip", "planner.cpp", "api.cpp", "batched.cpp"]
+SOURCES = ["kernels.hip", "kernels_lowp.hip", "batched.hip", "etd.hip", "planner.cpp", "api.cpp", "batched.cpp",
+           "etd.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

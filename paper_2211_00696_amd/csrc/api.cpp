@@ -1786,4 +1786,14 @@ phiq_status batch_fetch(phiq_handle h, int slot, void* dst, size_t bytes, hipStr
   return stage_fetch(h, slot, dst, bytes, st);
 }
 
+phiq_status plan_settle(phiq_plan P) {
+  if (!P) return PHIQ_ERR_INVALID_ARG;
+  DeviceGuard g(P->h->device);
+  if (P->has_join) PHIQ_HIP(hipEventSynchronize(P->join));
+  P->has_join = false;
+  return PHIQ_OK;
+}
+
+bool plan_profiling(phiq_plan P) { return P && P->h->prof.on; }
+
 }  // namespace phiq

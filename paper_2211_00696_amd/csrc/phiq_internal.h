@@ -45,6 +45,23 @@ phiq_status batch_arena(phiq_handle h, size_t bytes, void** dev);
 // reading the pinned memory, on st).
 phiq_status batch_stage(phiq_handle h, size_t bytes, int* slot, void** host);
 phiq_status batch_fetch(phiq_handle h, int slot, void* dst, size_t bytes, hipStream_t st);
+// Wait until the plan's own device work (1D exponentials) has finished and
+// stop its executions from waiting on it: after this, execution enqueues
+// only kernels on the caller's stream (what a stream capture needs).
+phiq_status plan_settle(phiq_plan P);
+bool plan_profiling(phiq_plan P);  // live kernel timing is on for the plan's handle
+
+// ---- etd.hip: elementwise steps of the ETD-RK4 integrator ----------------
+// F(x) = c1 x + c3 x^3.  All arrays DEVICE, n elements.
+int launch_etd_nonlin(const double* x, double* fx, long long n, double c1, double c3, void* stream);
+// a = x + s y; fa = F(a) (a may be null: not stored)
+int launch_etd_stage(const double* x, const double* y, double s, double* a, double* fa, long long n, double c1,
+                     double c3, void* stream);
+// b = x + s y; fb = F(b); mix = 2 fb - fu; sum = fa + fb
+int launch_etd_stage_b(const double* x, const double* y, double s, const double* fu, const double* fa, double* mix,
+                       double* sum, long long n, double c1, double c3, void* stream);
+// u = e + h [(g1_1 - 3 g1_2 + 4 g1_3) + 2 (g2_2 - 2 g2_3) + (-g3_2 + 4 g3_3)], gr_k = g + (4 r + k) n
+int launch_etd_final(const double* e, const double* g, double h, double* u, long long n, void* stream);
 
 // ---- kernels.hip: device job descriptors ---------------------------------
 // C = A * B, all n x n row-major FP64 (A, B, C distinct).

@@ -298,6 +298,18 @@ class Handle:
         _check(lib.phiq_action_batched(self._h, nprob, arr, byref(o), _stream_ptr(stream)), "phiq_action_batched")
         return outs, [r.as_dict() for r in reps]
 
+    def etdrk4(self, mats, tau, nsteps, u, c1=1.0, c3=-1.0, tol=1e-8, graph=True, stream=None):
+        """ETD-RK4 steps of u' = -A u + c1 u + c3 u^3 in place on the device tensor u (phiq_etdrk4).
+        Returns the report dict."""
+        lib = L.load()
+        op = _Op(mats)
+        if u.numel() != op.N:
+            raise ValueError("u has %d entries, the operator needs %d" % (u.numel(), op.N))
+        rep = L.EtdReport()
+        _check(lib.phiq_etdrk4(self._h, byref(op.op), float(tau), int(nsteps), float(c1), float(c3), float(tol),
+                               int(bool(graph)), _dev_ptr(u, "u"), byref(rep), _stream_ptr(stream)), "phiq_etdrk4")
+        return rep.as_dict()
+
     def plan(self, mats, t, p, tol=1e-8, stream=None, **opts):
         lib = L.load()
         op = _Op(mats)
