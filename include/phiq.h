@@ -69,6 +69,9 @@ typedef enum {
   PHIQ_PREC_BF16X3 = 2   /* x = hi + lo in bf16, hi*hi + hi*lo + lo*hi, FP32 */
 } phiq_precision;
 
+/* Choice of (l, m) for the Gauss rule. */
+typedef enum { PHIQ_SEL_PAPER = 0, PHIQ_SEL_MLP = 1 } phiq_selector;
+
 /* The Kronecker-sum operator: D = dim factors, HOST pointers. */
 typedef struct {
   int dim;                        /* 1..PHIQ_MAX_DIM                          */
@@ -90,6 +93,11 @@ typedef struct {
                             /* hipGraph (bitwise the same result).  Default 0: on   */
                             /* ROCm 7 a replay of the ~45-node graph costs more     */
                             /* than the eager launches it replaces.                 */
+  int selector;             /* Gauss (l, m) choice when l and m are not forced:     */
+                            /* PHIQ_SEL_PAPER (default, Algorithm setup_quadrature) */
+                            /* or PHIQ_SEL_MLP (the handle's network, see           */
+                            /* phiq_selector_set; the bound judges its choice and   */
+                            /* Algorithm setup_quadrature is the fallback)          */
 } phiq_options;
 
 /* What a plan / call did.  Times are filled by phiq_action only. */
@@ -102,6 +110,9 @@ typedef struct {
   double log10_bound;  /* log10 of the a priori bound at (l, m), relative to ||v||_inf */
   double cc_err;       /* last relative change of Algorithm 2 (0 for Gauss)     */
   size_t workspace_bytes; /* device bytes held by the handle after the call     */
+  int selector;        /* how (l, m) was chosen: 0 Algorithm setup_quadrature   */
+                       /* (or forced), 1 network, 2 network with m raised to    */
+                       /* what the bound needs, 3 network rejected (fallback)   */
 } phiq_report;
 
 typedef struct phiq_handle_s* phiq_handle;
@@ -135,6 +146,11 @@ phiq_status phiq_setup_quadrature(double eps, int p, double alpha, double beta,
  * (n+1)-node rule at norm alpha and vector factor beta.  n may be real. */
 phiq_status phiq_log_quaderr(double n, int p, double alpha, double beta,
                              phiq_rule rule, double* log_err);
+
+/* Algorithm quadnodes: the smallest n (the rule has n+1 nodes) whose
+ * Thm 3.2 bound at norm alpha and vector factor beta is <= eps, for orders
+ * 1..p (root of the bound in n, rounded up; n >= 2 Gauss, >= 4 CC). */
+phiq_status phiq_quadnodes(double eps, int p, double alpha, double beta, phiq_rule rule, int* n);
 
 /* Nodes theta and weights w on [0, 1] of the m-point Gauss-Legendre rule
  * (rule = GAUSS) or the m-point Clenshaw-Curtis rule (rule = CC, m >= 2,
@@ -256,6 +272,32 @@ typedef struct {
 phiq_status phiq_etdrk4(phiq_handle h, const phiq_kron_op* op, double tau, int nsteps,
                         double c1, double c3, double tol, int use_graph, double* u,
                         phiq_etd_report* rep, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned (l, m) selector: a network 8 -> 64 -> 64 -> 2 with tanh hidden
+ * layers in FP32.  Parameters, one vector of PHIQ_MLP_NPARAM floats: W1
+ * (64 x 8, row-major), b1 (64), W2 (64 x 64), b2 (64), W3 (2 x 64), b3 (2).
+ * Inputs (8): log10 t||A^d||_inf for axes 0..2 (-3 for an absent axis),
+ * max_d n_d / 256, dim, p, log10 t, log10 tol; outputs: l / 8, m / 16.
+ * Loss: mean of (y - target)^2 over the B x 2 outputs.
+ * ------------------------------------------------------------------------ */
+#define PHIQ_MLP_NPARAM 4866
+
+/* Y = net(X): X DEVICE B x 8, w DEVICE PHIQ_MLP_NPARAM, Y DEVICE B x 2. */
+phiq_status phiq_mlp_forward(phiq_handle h, int B, const float* X, const float* w, float* Y,
+                             hipStream_t stream);
+/* Gradient of the loss at w (DEVICE grad, PHIQ_MLP_NPARAM), summed over the
+ * samples in a fixed order; *loss (HOST, nullable) = the loss.  T DEVICE
+ * B x 2 targets.  Synchronises the stream when loss is requested. */
+phiq_status phiq_mlp_grad(phiq_handle h, int B, const float* X, const float* T, const float* w,
+                          float* grad, double* loss, hipStream_t stream);
+/* Full-batch Adam (beta1 0.9, beta2 0.999, eps 1e-8) for `steps` steps from
+ * the HOST weights w (updated in place), HOST data X (B x 8) and T (B x 2);
+ * loss_history (HOST, nullable) gets the loss before each step.  Blocks. */
+phiq_status phiq_mlp_train(phiq_handle h, int B, const float* X, const float* T, float* w, int steps,
+                           float lr, float* loss_history);
+/* The handle's selector network (HOST w copied; NULL clears it). */
+phiq_status phiq_selector_set(phiq_handle h, const float* w);
 
 /* Building blocks (also used by the tests).
  *

@@ -22,6 +22,7 @@ STATUS = {
 RULE = {"gauss": 1, "cc": 2}
 PROFILE_CLASSES = ["ttm_store", "ttm_accum", "ttm_square", "gemm", "taylor", "scale", "node_sum", "absdiff"]
 PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+SELECTOR = {"paper": 0, "mlp": 1}
 
 # Every symbol include/phiq.h declares.
 EXPORTS = [
@@ -30,6 +31,7 @@ EXPORTS = [
     "phiq_norm_bound",
     "phiq_setup_quadrature",
     "phiq_log_quaderr",
+    "phiq_quadnodes",
     "phiq_quadrature_rule",
     "phiq_create",
     "phiq_destroy",
@@ -40,6 +42,10 @@ EXPORTS = [
     "phiq_action_batched",
     "phiq_batch_info",
     "phiq_etdrk4",
+    "phiq_mlp_forward",
+    "phiq_mlp_grad",
+    "phiq_mlp_train",
+    "phiq_selector_set",
     "phiq_expm",
     "phiq_kron_apply",
     "phiq_profile_start",
@@ -64,6 +70,7 @@ class Options(ctypes.Structure):
         ("cc_max_doublings", c_int),
         ("workspace_cap", c_size_t),
         ("use_graphs", c_int),
+        ("selector", c_int),
     ]
 
 
@@ -77,6 +84,7 @@ class Report(ctypes.Structure):
         ("log10_bound", c_double),
         ("cc_err", c_double),
         ("workspace_bytes", c_size_t),
+        ("selector", c_int),
     ]
 
     def as_dict(self):
@@ -130,6 +138,7 @@ def load():
         "phiq_setup_quadrature": (c_int, [c_double, c_int, c_double, c_double, c_int, c_double, c_double, c_int,
                                           P(c_int), P(c_int), P(c_double)]),
         "phiq_log_quaderr": (c_int, [c_double, c_int, c_double, c_double, c_int, P(c_double)]),
+        "phiq_quadnodes": (c_int, [c_double, c_int, c_double, c_double, c_int, P(c_int)]),
         "phiq_quadrature_rule": (c_int, [c_int, c_int, P(c_double), P(c_double)]),
         "phiq_create": (c_int, [P(c_void_p), c_int]),
         "phiq_destroy": (c_int, [c_void_p]),
@@ -143,6 +152,11 @@ def load():
         "phiq_batch_info": (c_int, [c_int, P(Problem), P(Options), P(BatchStats)]),
         "phiq_etdrk4": (c_int, [c_void_p, P(KronOp), c_double, c_int, c_double, c_double, c_double, c_int,
                                 c_void_p, P(EtdReport), c_void_p]),
+        "phiq_mlp_forward": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
+        "phiq_mlp_grad": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, P(c_double), c_void_p]),
+        "phiq_mlp_train": (c_int, [c_void_p, c_int, P(ctypes.c_float), P(ctypes.c_float), P(ctypes.c_float), c_int,
+                                   ctypes.c_float, P(ctypes.c_float)]),
+        "phiq_selector_set": (c_int, [c_void_p, P(ctypes.c_float)]),
         "phiq_expm": (c_int, [c_void_p, c_int, c_int, c_void_p, P(c_double), c_void_p, c_void_p]),
         "phiq_kron_apply": (c_int, [c_void_p, c_int, P(c_int), P(c_void_p), c_void_p, c_void_p, c_int, c_int,
                                     c_void_p]),

@@ -107,7 +107,7 @@ double sum_infnorms(const phiq_kron_op* op) {
 // the Taylor degree.  Shared by single plans and batches so both choose the
 // same parameters for the same problem.
 phiq_status select_params(const phiq_kron_op* op, double t, int p, double tol, const phiq_options& opt,
-                          PlanParams* pp) {
+                          PlanParams* pp, const float* mlp) {
   double norms[PHIQ_MAX_DIM];
   double alpha = 0.0;
   for (int d = 0; d < op->dim; ++d) {
@@ -117,6 +117,7 @@ phiq_status select_params(const phiq_kron_op* op, double t, int p, double tol, c
   if (opt.alpha >= 0) alpha = opt.alpha;
   pp->alpha = alpha;
   pp->log10_bound = 0.0;
+  pp->selector = 0;
   int l = 0, nq = -1;
   if (p > 0) {
     double cost = 0.0;
@@ -129,6 +130,15 @@ phiq_status select_params(const phiq_kron_op* op, double t, int p, double tol, c
                : 4;
     } else {
       setup_quadrature(tol, p, alpha, 1.0, opt.rule, opt.c1, opt.c2, op->dim, &l, &nq, &cost);
+      if (opt.selector == PHIQ_SEL_MLP && mlp && opt.rule == PHIQ_RULE_GAUSS && opt.m <= 0 && alpha > 1e-12 &&
+          l >= 0 && nq >= 0) {
+        int lm = l, nm = nq, used = 0;
+        if (mlp_choose(mlp, op, norms, t, p, tol, alpha, l, nq, &lm, &nm, &used)) {
+          l = lm;
+          nq = nm;
+        }
+        pp->selector = used;
+      }
       if (opt.m > 0 && opt.rule == PHIQ_RULE_GAUSS) nq = opt.m - 1;
     }
     if (l < 0 || nq < 0) return PHIQ_ERR_NOT_CONVERGED;
@@ -235,6 +245,7 @@ struct phiq_handle_s {
   DevBuf partial;                // CC reduction partials
   double* partial_host = nullptr;
   DevBuf batch;                  // phiq_action_batched: factors, workspaces, stage tables
+  std::vector<float> mlp;        // selector network (phiq_selector_set), empty if none
   Staging stage;
   size_t cap_bytes = 0;
   size_t held() const {
@@ -258,6 +269,7 @@ struct phiq_plan_s {
   phiq_options opt{};
   int l = 0, m = 0, K = 1;
   int sigma[PHIQ_MAX_DIM] = {};
+  int selector = 0;  // phiq_report::selector
   double alpha = 0.0, log10_bound = 0.0;
   // device pointers (inside mem)
   double* Z[PHIQ_MAX_DIM] = {};      // Z^1..Z^K
@@ -679,7 +691,7 @@ phiq_status plan_build(phiq_handle h, const phiq_kron_op* op, double t, int p, d
     return PHIQ_ERR_INVALID_ARG;
 
   PlanParams pp;
-  PHIQ_TRY(select_params(op, t, p, tol, opt, &pp));
+  PHIQ_TRY(select_params(op, t, p, tol, opt, &pp, h->mlp.empty() ? nullptr : h->mlp.data()));
   phiq_plan P = new (std::nothrow) phiq_plan_s;
   if (!P) return PHIQ_ERR_OOM;
   P->h = h;
@@ -699,6 +711,7 @@ phiq_status plan_build(phiq_handle h, const phiq_kron_op* op, double t, int p, d
   P->l = pp.l;
   P->m = pp.m;
   P->K = pp.K;
+  P->selector = pp.selector;
   const int l = P->l;
 
   // a3: the rule (Gauss); CC nodes are produced level by level at execute time
@@ -886,6 +899,7 @@ phiq_status plan_build(phiq_handle h, const phiq_kron_op* op, double t, int p, d
     rep->m = P->m;
     rep->alpha = P->alpha;
     rep->log10_bound = P->log10_bound;
+    rep->selector = P->selector;
     rep->workspace_bytes = h->held();
   }
   *out = P;
@@ -1295,6 +1309,7 @@ phiq_status phiq_options_default(phiq_options* o) {
   o->cc_max_doublings = 6;
   o->workspace_cap = 0;
   o->use_graphs = 0;
+  o->selector = PHIQ_SEL_PAPER;
   return PHIQ_OK;
 }
 
@@ -1378,6 +1393,7 @@ phiq_status phiq_plan_execute(phiq_plan plan, const double* v, int nrhs, double*
     if (plan->opt.rule == PHIQ_RULE_GAUSS) rep->m = plan->m;
     rep->alpha = plan->alpha;
     rep->log10_bound = plan->log10_bound;
+    rep->selector = plan->selector;
     const int chains_per = (plan->p > 0 ? rep->m + plan->l * plan->p : 0) + 1;
     rep->ttm_chains = chains_per * nrhs;
     rep->workspace_bytes = plan->h->held();
@@ -1795,5 +1811,23 @@ phiq_status plan_settle(phiq_plan P) {
 }
 
 bool plan_profiling(phiq_plan P) { return P && P->h->prof.on; }
+
+const float* handle_mlp(phiq_handle h) { return (h && !h->mlp.empty()) ? h->mlp.data() : nullptr; }
+
+}  // namespace phiq
+
+extern "C" phiq_status phiq_selector_set(phiq_handle h, const float* w) {
+  if (!h) return PHIQ_ERR_INVALID_ARG;
+  if (!w) {
+    h->mlp.clear();
+    return PHIQ_OK;
+  }
+  for (int i = 0; i < kMlpParams; ++i)
+    if (!std::isfinite(w[i])) return PHIQ_ERR_NONFINITE;
+  h->mlp.assign(w, w + kMlpParams);
+  return PHIQ_OK;
+}
+
+namespace phiq {
 
 }  // namespace phiq

@@ -377,7 +377,7 @@ struct Schedule {
   Built b;
   int depth = 0;
 
-  phiq_status make(int nprob, const phiq_problem* probs, const phiq_options* uopt) {
+  phiq_status make(int nprob, const phiq_problem* probs, const phiq_options* uopt, const float* mlp) {
     phiq_options_default(&opt);
     if (uopt) opt = *uopt;
     std::vector<std::pair<uintptr_t, uintptr_t>> outs, ins;
@@ -407,7 +407,7 @@ struct Schedule {
       }
       Prob P;
       P.pr = &pr;
-      PHIQ_TRY(select_params(&pr.op, pr.t, pr.p, pr.tol, opt, &P.pp));
+      PHIQ_TRY(select_params(&pr.op, pr.t, pr.p, pr.tol, opt, &P.pp, mlp));
       P.D = pr.op.dim;
       for (int d = 0; d < P.D; ++d) {
         P.n[d] = pr.op.n[d];
@@ -556,7 +556,7 @@ extern "C" phiq_status phiq_batch_info(int nprob, const phiq_problem* probs, con
   if (nprob < 0 || (nprob > 0 && !probs) || !info) return PHIQ_ERR_INVALID_ARG;
   std::memset(info, 0, sizeof(*info));
   Schedule S;
-  PHIQ_TRY(S.make(nprob, probs, opt));
+  PHIQ_TRY(S.make(nprob, probs, opt, nullptr));
   info->persistent = (int)S.pl.size();
   info->separate = (int)S.rest.size();
   if (S.pl.empty()) return PHIQ_OK;
@@ -579,7 +579,7 @@ extern "C" phiq_status phiq_action_batched(phiq_handle h, int nprob, const phiq_
   if (!h || nprob < 0 || (nprob > 0 && !probs)) return PHIQ_ERR_INVALID_ARG;
   if (nprob == 0) return PHIQ_OK;
   Schedule S;
-  PHIQ_TRY(S.make(nprob, probs, uopt));
+  PHIQ_TRY(S.make(nprob, probs, uopt, handle_mlp(h)));
   const phiq_options& opt = S.opt;
   if (!S.pl.empty()) {
     if (opt.workspace_cap && S.total > opt.workspace_cap) return PHIQ_ERR_OOM;
@@ -636,6 +636,7 @@ extern "C" phiq_status phiq_action_batched(phiq_handle h, int nprob, const phiq_
       rep->m = P.pp.m;
       rep->alpha = P.pp.alpha;
       rep->log10_bound = P.pp.log10_bound;
+      rep->selector = P.pp.selector;
       rep->ttm_chains = P.pr->nrhs * ((P.pr->p > 0 ? P.pp.m + P.pp.l * P.pr->p : 0) + 1);
       rep->workspace_bytes = S.total;
     }

@@ -36,9 +36,30 @@ struct PlanParams {
   int m;               // Gauss nodes (0 for CC or p = 0)
   int K;               // Taylor degree of the 1D exponentials
   int sigma[PHIQ_MAX_DIM];  // extra halvings of axis d's Taylor argument
+  int selector;        // phiq_report::selector
 };
+// mlp: the handle's selector network (nullable).
 phiq_status select_params(const phiq_kron_op* op, double t, int p, double tol, const phiq_options& opt,
-                          PlanParams* pp);
+                          PlanParams* pp, const float* mlp);
+const float* handle_mlp(phiq_handle h);  // the handle's selector network or null
+
+// ---- mlp.hip / mlp.cpp: the selector network ------------------------------
+constexpr int kMlpIn = 8, kMlpHidden = 64, kMlpOut = 2;
+constexpr int kMlpParams = kMlpHidden * kMlpIn + kMlpHidden + kMlpHidden * kMlpHidden + kMlpHidden +
+                           kMlpOut * kMlpHidden + kMlpOut;
+int launch_mlp_forward(const float* w, const float* X, int B, float* H1, float* H2, float* Y, void* stream);
+int launch_mlp_backward(const float* w, const float* T, const float* H1, const float* H2, const float* Y, int B,
+                        float* dY, float* dZ2, float* dZ1, double* loss_part, void* stream);
+int launch_mlp_wgrad(const float* X, const float* H1, const float* H2, const float* dZ1, const float* dZ2,
+                     const float* dY, int B, int chunks, double* part, float* grad, void* stream);
+int launch_mlp_adam(float* w, const float* g, float* m, float* v, float lr, float b1, float b2, float eps, int step,
+                    void* stream);
+// Host forward pass (the same arithmetic as the kernel) and the planner's
+// use of it: features, prediction, the bound as judge.  Returns false when
+// the prediction is rejected (the caller keeps Algorithm 5's choice).
+void mlp_predict_host(const float* w, const float x[kMlpIn], float y[kMlpOut]);
+bool mlp_choose(const float* w, const phiq_kron_op* op, const double* norms, double t, int p, double tol,
+                double alpha, int l5, int n5, int* l, int* n, int* used);
 // Grow-only device arena of batched calls, held by the handle.
 phiq_status batch_arena(phiq_handle h, size_t bytes, void** dev);
 // Pinned staging slot of at least `bytes`, and its upload (a copy kernel

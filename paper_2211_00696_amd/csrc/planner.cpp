@@ -327,6 +327,14 @@ phiq_status phiq_log_quaderr(double n, int p, double alpha, double beta, phiq_ru
   return PHIQ_OK;
 }
 
+phiq_status phiq_quadnodes(double eps, int p, double alpha, double beta, phiq_rule rule, int* n) {
+  if (!n || !(eps > 0) || p < 1 || p > PHIQ_MAX_P || !(alpha > 0) || !(beta > 0)) return PHIQ_ERR_INVALID_ARG;
+  if (!std::isfinite(eps) || !std::isfinite(alpha) || !std::isfinite(beta)) return PHIQ_ERR_NONFINITE;
+  if (rule != PHIQ_RULE_GAUSS && rule != PHIQ_RULE_CC) return PHIQ_ERR_INVALID_ARG;
+  *n = phiq::quadnodes(eps, p, alpha, beta, rule);
+  return *n < 0 ? PHIQ_ERR_NOT_CONVERGED : PHIQ_OK;
+}
+
 phiq_status phiq_quadrature_rule(phiq_rule rule, int m, double* theta, double* w) {
   if (!theta || !w || m < 1 || m > 100000) return PHIQ_ERR_INVALID_ARG;
   if (rule == PHIQ_RULE_GAUSS) {

@@ -43,6 +43,16 @@ def _dev_ptr(x, name):
     return c_void_p(x.data_ptr())
 
 
+def _f32_ptr(x, name):
+    import torch
+
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if x.dtype != torch.float32 or not x.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float32 tensor")
+    return c_void_p(x.data_ptr())
+
+
 class _Op:
     """Keeps the host copies of A^d alive while the KronOp points at them."""
 
@@ -62,7 +72,7 @@ class _Op:
 
 
 def options(rule="gauss", precision="fp64", l=None, m=None, alpha=None, c1=None, c2=None,
-            cc_max_doublings=None, workspace_cap=None, use_graphs=None):
+            cc_max_doublings=None, workspace_cap=None, use_graphs=None, selector=None):
     lib = L.load()
     o = L.Options()
     _check(lib.phiq_options_default(byref(o)), "phiq_options_default")
@@ -84,6 +94,8 @@ def options(rule="gauss", precision="fp64", l=None, m=None, alpha=None, c1=None,
         o.workspace_cap = int(workspace_cap)
     if use_graphs is not None:
         o.use_graphs = int(bool(use_graphs))
+    if selector is not None:
+        o.selector = L.SELECTOR[selector]
     return o
 
 
@@ -113,6 +125,14 @@ def log_quaderr(n, p, alpha, beta=1.0, rule="gauss"):
     _check(lib.phiq_log_quaderr(float(n), int(p), float(alpha), float(beta), L.RULE[rule], byref(e)),
            "phiq_log_quaderr")
     return e.value
+
+
+def quadnodes(eps, p, alpha, beta=1.0, rule="gauss"):
+    """Algorithm quadnodes: smallest n (n+1 nodes) meeting eps at norm alpha."""
+    lib = L.load()
+    n = c_int()
+    _check(lib.phiq_quadnodes(float(eps), int(p), float(alpha), float(beta), L.RULE[rule], byref(n)), "phiq_quadnodes")
+    return n.value
 
 
 def quadrature_rule(rule, m):
@@ -309,6 +329,51 @@ class Handle:
         _check(lib.phiq_etdrk4(self._h, byref(op.op), float(tau), int(nsteps), float(c1), float(c3), float(tol),
                                int(bool(graph)), _dev_ptr(u, "u"), byref(rep), _stream_ptr(stream)), "phiq_etdrk4")
         return rep.as_dict()
+
+    # ---- the learned selector's network (FP32) ----
+    def mlp_forward(self, X, w, stream=None):
+        """Y = net(X) on the device: X (B, 8) float32, w (NPARAM,) float32 device tensors."""
+        import torch
+
+        lib = L.load()
+        B = X.shape[0]
+        Y = torch.empty((B, 2), dtype=torch.float32, device=X.device)
+        _check(lib.phiq_mlp_forward(self._h, int(B), _f32_ptr(X, "X"), _f32_ptr(w, "w"), _f32_ptr(Y, "Y"),
+                                    _stream_ptr(stream)), "phiq_mlp_forward")
+        return Y
+
+    def mlp_grad(self, X, T, w, stream=None):
+        """(gradient (NPARAM,) float32 device tensor, loss) of the mean squared error."""
+        import torch
+
+        lib = L.load()
+        g = torch.empty_like(w)
+        loss = c_double()
+        _check(lib.phiq_mlp_grad(self._h, int(X.shape[0]), _f32_ptr(X, "X"), _f32_ptr(T, "T"), _f32_ptr(w, "w"),
+                                 _f32_ptr(g, "grad"), byref(loss), _stream_ptr(stream)), "phiq_mlp_grad")
+        return g, loss.value
+
+    def mlp_train(self, X, T, w, steps, lr=1e-3):
+        """Full-batch Adam on the GPU from host arrays; returns (weights, loss history)."""
+        lib = L.load()
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        T = np.ascontiguousarray(T, dtype=np.float32)
+        w = np.array(w, dtype=np.float32, copy=True)
+        hist = np.zeros(max(1, steps), dtype=np.float32)
+        fp = ctypes.POINTER(ctypes.c_float)
+        _check(lib.phiq_mlp_train(self._h, int(X.shape[0]), X.ctypes.data_as(fp), T.ctypes.data_as(fp),
+                                  w.ctypes.data_as(fp), int(steps), float(lr), hist.ctypes.data_as(fp)),
+               "phiq_mlp_train")
+        return w, hist[:steps]
+
+    def selector_set(self, w):
+        """Install the selector network (host float32 array) or clear it (None)."""
+        lib = L.load()
+        if w is None:
+            _check(lib.phiq_selector_set(self._h, None), "phiq_selector_set")
+            return
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        _check(lib.phiq_selector_set(self._h, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float))), "phiq_selector_set")
 
     def plan(self, mats, t, p, tol=1e-8, stream=None, **opts):
         lib = L.load()

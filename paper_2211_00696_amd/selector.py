@@ -1,0 +1,268 @@
+"""Learned choice of (l, m) for the Gauss-rule phi-action.
+
+The paper picks the scaling exponent l and the node count m with
+Algorithm setup_quadrature: the cheapest pair, under the cost model
+C = c1 d n + c2 (n + l p), whose a priori bound (Thm 3.2) meets the
+tolerance.  On the MI355X the two kinds of work do not cost the same: the m
+node chains run as batched mode products, while each of the l squaring
+steps runs p chains and a GEMM one after another.  This module
+
+  1. measures that cost (`measure`, GPU): phi-action time over forced
+     (l, m) for 3D grids n = 32..256 and p = 1..4, and fits, per n,
+        T(l, m) = a m + (b p + c) l + d                       (milliseconds);
+  2. labels generated problems (`dataset`, host): for every l, the smallest
+     m that meets the bound (Algorithm quadnodes), and the (l, m) with the
+     least fitted T;
+  3. trains the 8 -> 64 -> 64 -> 2 network on those labels (`train`, GPU,
+     through the library's own forward / backward / Adam kernels);
+and the planner uses the network with the bound as the judge (Algorithm 5
+is the fallback): phiq_options.selector = PHIQ_SEL_MLP.
+
+Features (8): log10 of t ||A^d||_inf for axes 0..2 (-3 for an absent axis),
+n / 256, dim, p, log10 t, log10 tol.  Outputs (2): l / 8 and m / 16.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import inputs as I
+from . import phiq
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+COSTS = os.path.join(PKG, "selector_costs.json")
+WEIGHTS = os.path.join(PKG, "selector_weights.json")
+NFEAT, NHID, NOUT = 8, 64, 2
+NPARAM = NHID * NFEAT + NHID + NHID * NHID + NHID + NOUT * NHID + NOUT
+L_SCALE, M_SCALE = 8.0, 16.0
+
+
+def features(norms, n, dim, p, t, tol):
+    """norms: t ||A^d||_inf per axis (already multiplied by t)."""
+    f = [math.log10(max(float(x), 1e-300)) for x in list(norms)[:3]]
+    f += [-3.0] * (3 - len(f))
+    return np.array(f + [n / 256.0, float(dim), float(p), math.log10(t), math.log10(tol)], dtype=np.float64)
+
+
+def infnorm(a):
+    return float(np.max(np.sum(np.abs(a), axis=1)))
+
+
+def feasible_m(tol, p, alpha, l):
+    """Gauss nodes the bound needs at scaling l (Algorithm quadnodes, n + 1 nodes)."""
+    return phiq.quadnodes(tol, p, math.ldexp(alpha, -l)) + 1
+
+
+# ---------------------------------------------------------------------------
+# 1. cost measurement on the GPU
+# ---------------------------------------------------------------------------
+def measure(sizes=(32, 48, 64, 96, 128, 160, 192, 256), ps=(1, 2, 3, 4), reps=5, seed=0, log=print):
+    import torch
+
+    h = phiq.Handle(0)
+    rng = np.random.default_rng(seed)
+    recs = []
+    for n in sizes:
+        for p in ps:
+            for t in (1e-3, 1e-2):
+                a, b = I.draw_coefficients(rng, 3)
+                mats = [I.adv_diff_1d(n, float(a[d]), float(b[d])) for d in range(3)]
+                alpha = t * sum(infnorm(m) for m in mats)
+                v = torch.from_numpy(rng.standard_normal(n ** 3)).cuda()
+                _, rep = h.action(mats, t, p, v, tol=1e-8)
+                l0 = rep["l"]
+                for l in range(max(0, l0 - 3), l0 + 3):
+                    m = feasible_m(1e-8, p, alpha, l)
+                    if m > 48:
+                        continue
+                    for extra in (0, 3):
+                        kw = dict(l=l, m=m + extra)
+                        # two warm-up calls: one-call plans alternate between two
+                        # buffers, each may grow once for a new size
+                        h.action(mats, t, p, v, tol=1e-8, **kw)
+                        h.action(mats, t, p, v, tol=1e-8, **kw)
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        for _ in range(reps):
+                            h.action(mats, t, p, v, tol=1e-8, **kw)
+                        torch.cuda.synchronize()
+                        ms = (time.perf_counter() - t0) * 1e3 / reps
+                        recs.append(dict(n=n, p=p, l=l, m=m + extra, t=t, ms=ms))
+                log("n=%d p=%d t=%g done (%d records)" % (n, p, t, len(recs)))
+    h.close()
+    return recs
+
+
+def fit(recs):
+    """Per n: least squares T = a m + b p l + c l + d, then once more without the
+    points whose residual exceeds five times the median absolute residual
+    (one-off stalls such as a buffer growing inside a timed call)."""
+    out = {}
+    for n in sorted(set(r["n"] for r in recs)):
+        rs = [r for r in recs if r["n"] == n]
+        A = np.array([[r["m"], r["p"] * r["l"], r["l"], 1.0] for r in rs])
+        y = np.array([r["ms"] for r in rs])
+        coef, *_ = np.linalg.lstsq(A, y, rcond=None)
+        res = np.abs(A @ coef - y)
+        keep = res <= 5.0 * max(np.median(res), 1e-6)
+        coef, *_ = np.linalg.lstsq(A[keep], y[keep], rcond=None)
+        resid = float(np.sqrt(np.mean((A[keep] @ coef - y[keep]) ** 2)))
+        out[int(n)] = dict(a=float(coef[0]), b=float(coef[1]), c=float(coef[2]), d=float(coef[3]),
+                           rms_ms=resid, points=int(keep.sum()), dropped=int((~keep).sum()))
+    return out
+
+
+def cost_fn(costs):
+    ns = np.array(sorted(int(k) for k in costs))
+    tab = {k: np.array([costs[str(n)][k] if str(n) in costs else costs[n][k] for n in ns]) for k in "abcd"}
+    ln = np.log(ns)
+
+    def interp(key, n):
+        return float(np.interp(math.log(n), ln, tab[key]))
+
+    def T(n, p, l, m):
+        return interp("a", n) * m + (interp("b", n) * p + interp("c", n)) * l + interp("d", n)
+
+    return T
+
+
+# ---------------------------------------------------------------------------
+# 2. labels
+# ---------------------------------------------------------------------------
+def label(T, n, p, alpha, tol):
+    """(l, m) with the least modelled time among the pairs the bound accepts."""
+    if alpha <= 1e-12:
+        return 0, max(1, (p + 1) // 2)
+    lmax = max(0, math.ceil(math.log2(alpha))) + 2
+    best = None
+    for l in range(0, lmax + 1):
+        try:
+            m = feasible_m(tol, p, alpha, l)
+        except phiq.PhiqError:
+            continue
+        c = T(n, p, l, m)
+        if best is None or c < best[0]:
+            best = (c, l, m)
+    return best[1], best[2]
+
+
+def draw_problem(rng, n_range=(16, 256), dims=(2, 3)):
+    dim = int(dims[rng.integers(0, len(dims))])
+    n = int(rng.integers(n_range[0], n_range[1] + 1))
+    p = int(rng.integers(1, 5))
+    t = float(math.exp(rng.uniform(math.log(1e-4), math.log(1e-1))))
+    tol = float(math.exp(rng.uniform(math.log(1e-10), math.log(1e-6))))
+    a, b = I.draw_coefficients(rng, dim)
+    norms = [t * (4 * a[d] * (n + 1) ** 2 + 2 * b[d] * (n + 1)) for d in range(dim)]
+    return dict(dim=dim, n=n, p=p, t=t, tol=tol, a=a.tolist(), b=b.tolist(), norms=norms)
+
+
+def dataset(count, seed, costs):
+    T = cost_fn(costs)
+    rng = np.random.default_rng(seed)
+    X = np.zeros((count, NFEAT))
+    Y = np.zeros((count, NOUT))
+    meta = []
+    for i in range(count):
+        pr = draw_problem(rng)
+        alpha = sum(pr["norms"])
+        l, m = label(T, pr["n"], pr["p"], alpha, pr["tol"])
+        X[i] = features(pr["norms"], pr["n"], pr["dim"], pr["p"], pr["t"], pr["tol"])
+        Y[i] = (l / L_SCALE, m / M_SCALE)
+        meta.append(dict(pr, l=l, m=m))
+    return X, Y, meta
+
+
+# ---------------------------------------------------------------------------
+# 3. the network (host copy of the forward pass, for checks)
+# ---------------------------------------------------------------------------
+def unpack(w):
+    w = np.asarray(w, dtype=np.float64)
+    o = 0
+    parts = []
+    for shape in ((NHID, NFEAT), (NHID,), (NHID, NHID), (NHID,), (NOUT, NHID), (NOUT,)):
+        k = int(np.prod(shape))
+        parts.append(w[o:o + k].reshape(shape))
+        o += k
+    return parts
+
+
+def init_weights(seed):
+    """Glorot-uniform weights, zero biases (the random draw is made here and passed to the kernels)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for fan_in, fan_out in ((NFEAT, NHID), (NHID, NHID), (NHID, NOUT)):
+        lim = math.sqrt(6.0 / (fan_in + fan_out))
+        out.append(rng.uniform(-lim, lim, fan_out * fan_in))
+        out.append(np.zeros(fan_out))
+    return np.concatenate(out).astype(np.float32)
+
+
+def load_costs(path=COSTS):
+    d = json.load(open(path))
+    return d["fit"]
+
+
+def train(h, count=20000, seed=1, steps=3000, lr=3e-3, costs=None, log=print):
+    """Generate `count` labelled problems and fit the network on the GPU."""
+    costs = load_costs() if costs is None else costs
+    X, Y, meta = dataset(count, seed, costs)
+    w0 = init_weights(seed + 1000)
+    w, hist = h.mlp_train(X, Y, w0, steps, lr)
+    pred = predict(w, X)
+    l_err = np.abs(np.rint(pred[:, 0] * L_SCALE) - np.rint(Y[:, 0] * L_SCALE))
+    m_err = np.abs(np.rint(pred[:, 1] * M_SCALE) - np.rint(Y[:, 1] * M_SCALE))
+    stats = dict(count=count, seed=seed, steps=steps, lr=lr, loss_first=float(hist[0]), loss_last=float(hist[-1]),
+                 l_exact=float(np.mean(l_err == 0)), m_within_1=float(np.mean(m_err <= 1)))
+    log(json.dumps(stats))
+    return w, hist, stats
+
+
+def predict(w, X):
+    """Host FP64 forward pass (the same network), for statistics."""
+    W1, b1, W2, b2, W3, b3 = unpack(w)
+    h1 = np.tanh(np.asarray(X) @ W1.T + b1)
+    h2 = np.tanh(h1 @ W2.T + b2)
+    return h2 @ W3.T + b3
+
+
+def save_weights(w, stats, path=WEIGHTS):
+    json.dump({"weights": [float(x) for x in np.asarray(w, dtype=np.float32)], "stats": stats}, open(path, "w"))
+
+
+def load_weights(path=WEIGHTS):
+    return np.array(json.load(open(path))["weights"], dtype=np.float32)
+
+
+def main(argv):
+    if len(argv) >= 1 and argv[0] == "train":
+        out = argv[1] if len(argv) > 1 else WEIGHTS
+        h = phiq.Handle(0)
+        w, hist, stats = train(h, log=lambda s: print(s, flush=True))
+        h.close()
+        save_weights(w, stats, out)
+        return 0
+    if len(argv) >= 1 and argv[0] == "refit":
+        d = json.load(open(COSTS))
+        d["fit"] = fit(d["records"])
+        json.dump(d, open(COSTS, "w"), indent=1)
+        print(json.dumps(d["fit"], indent=1))
+        return 0
+    if len(argv) >= 1 and argv[0] == "measure":
+        out = argv[1] if len(argv) > 1 else COSTS
+        recs = measure(log=lambda s: print(s, flush=True))
+        costs = fit(recs)
+        json.dump({"records": recs, "fit": costs}, open(out, "w"), indent=1)
+        print(json.dumps(costs, indent=1))
+        return 0
+    print(__doc__)
+    return 2
+
+
+if __name__ == "__main__":
+    sys.exit(main(sys.argv[1:]))

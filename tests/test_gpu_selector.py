@@ -1,0 +1,138 @@
+"""The learned (l, m) selector on the GPU.
+
+* The network's forward pass and loss gradient (HIP kernels, FP32) against
+  the FP64 oracle: relative 2-norm difference of the gradient below 1e-4
+  (FP32 products over 64-wide sums, FP64 sums over samples).
+* Training with the library's Adam kernels lowers the loss.
+* The judge: a network that asks for too few nodes is corrected to what the
+  bound needs (report.selector == 2) or rejected (3), and the result still
+  meets the tolerance against the oracle.
+* The trained network (selector_weights.json): on held-out 3D problems at
+  n = 64, 96, 128, 192 its choice meets the tolerance and is not slower
+  than Algorithm setup_quadrature's; the measured ratio is printed.
+"""
+import math
+import os
+import time
+
+import numpy as np
+import pytest
+
+from oracle import mlp as M
+from oracle import phi_exact as X
+from oracle import phiquad as Q
+from paper_2211_00696_amd import inputs as I
+from paper_2211_00696_amd import selector as S
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def h():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2211_00696_amd import phiq
+
+    hd = phiq.Handle(0)
+    yield hd
+    hd.close()
+
+
+def f32(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+@pytest.mark.parametrize("B", [1, 255, 1000, 4097])
+def test_mlp_forward_and_grad_vs_oracle(h, B):
+    rng = np.random.default_rng(B)
+    w = S.init_weights(B)
+    w[w.size - 2:] = [0.3, -0.2]
+    Xh = rng.standard_normal((B, 8)).astype(np.float32)
+    Th = rng.standard_normal((B, 2)).astype(np.float32)
+    Y = h.mlp_forward(f32(Xh), f32(w)).cpu().numpy()
+    _, _, yo = M.forward(w.astype(np.float64), Xh.astype(np.float64))
+    assert np.max(np.abs(Y - yo)) < 1e-5 * max(1.0, np.max(np.abs(yo)))
+    g, loss = h.mlp_grad(f32(Xh), f32(Th), f32(w))
+    go = M.grad(w.astype(np.float64), Xh.astype(np.float64), Th.astype(np.float64))
+    lo = M.loss(w.astype(np.float64), Xh.astype(np.float64), Th.astype(np.float64))
+    e = float(np.linalg.norm(g.cpu().numpy() - go) / np.linalg.norm(go))
+    print(B, "grad rel", e, "loss", loss, lo, flush=True)
+    assert e < 1e-4
+    assert abs(loss - lo) < 1e-5 * lo
+
+
+def test_mlp_training_lowers_loss(h):
+    rng = np.random.default_rng(3)
+    Xh = rng.standard_normal((2000, 8))
+    Th = np.stack([np.tanh(Xh[:, 0] - Xh[:, 1]), 0.5 * Xh[:, 2] * Xh[:, 3]], axis=1)
+    w, hist = h.mlp_train(Xh, Th, S.init_weights(7), 400, 3e-3)
+    print(hist[0], hist[-1], flush=True)
+    assert hist[-1] < 0.1 * hist[0]
+    # the returned weights reproduce the last loss (host oracle forward)
+    assert abs(M.loss(w.astype(np.float64), Xh, Th) - hist[-1]) < 0.5 * hist[-1] + 1e-3
+
+
+def test_judge_corrects_or_rejects(h):
+    w = np.zeros(S.NPARAM, dtype=np.float32)
+    w[-2:] = [0.0, 1.0 / 16.0]  # always predicts l = 0, m = 1: far too few nodes
+    h.selector_set(w)
+    try:
+        pr = I.problem("advdiff", seed=3, n=8, dim=3, t=1e-2)
+        out, rep = h.action(pr["mats"], pr["t"], 3, dev(pr["v"]), tol=1e-8, selector="mlp")
+        assert rep["selector"] in (2, 3), rep
+        ref = X.phi_dense_aug(pr["mats"], pr["t"], pr["v"], 3)
+        o = out.cpu().numpy()
+        e = max(float(np.max(np.abs(o[k] - ref[k])) / np.max(np.abs(ref[k]))) for k in range(4))
+        print(rep, e, flush=True)
+        assert e < 1e-8
+        # without weights the option falls back to the paper's choice
+        h.selector_set(None)
+        _, rep2 = h.action(pr["mats"], pr["t"], 3, dev(pr["v"]), tol=1e-8, selector="mlp")
+        assert rep2["selector"] == 0
+    finally:
+        h.selector_set(None)
+
+
+@pytest.mark.skipif(not os.path.exists(S.WEIGHTS), reason="no trained selector weights in the package")
+def test_trained_selector_gain(h):
+    w = S.load_weights()
+    h.selector_set(w)
+    rng = np.random.default_rng(2024)
+    t_mlp = t_pap = 0.0
+    rows = []
+    try:
+        for n in (64, 96, 128, 192):
+            for _ in range(3):
+                pr = S.draw_problem(rng, n_range=(n, n), dims=(3,))
+                pr["tol"] = 1e-8
+                mats = [I.adv_diff_1d(n, pr["a"][d], pr["b"][d]) for d in range(3)]
+                v = dev(rng.standard_normal(n ** 3))
+                res = {}
+                for sel in ("paper", "mlp"):
+                    out, rep = h.action(mats, pr["t"], pr["p"], v, tol=pr["tol"], selector=sel)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    for _ in range(3):
+                        h.action(mats, pr["t"], pr["p"], v, tol=pr["tol"], selector=sel)
+                    torch.cuda.synchronize()
+                    res[sel] = ((time.perf_counter() - t0) / 3, rep, out)
+                ref, _ = h.action(mats, pr["t"], pr["p"], v, tol=1e-13)
+                for sel in ("paper", "mlp"):
+                    o = res[sel][2]
+                    e = max(float(((o[k] - ref[k]).abs().max() / ref[k].abs().max()).item()) for k in range(pr["p"] + 1))
+                    assert e < pr["tol"], (n, sel, e, res[sel][1])
+                t_pap += res["paper"][0]
+                t_mlp += res["mlp"][0]
+                rows.append((n, pr["p"], res["paper"][1]["l"], res["paper"][1]["m"], res["mlp"][1]["l"],
+                             res["mlp"][1]["m"], res["mlp"][1]["selector"], res["paper"][0] / res["mlp"][0]))
+        for r in rows:
+            print("n=%d p=%d paper (l=%d, m=%d) mlp (l=%d, m=%d, sel %d) speedup %.3f" % r, flush=True)
+        print("total paper %.2f ms, mlp %.2f ms, ratio %.3f" % (t_pap * 1e3, t_mlp * 1e3, t_pap / t_mlp), flush=True)
+        assert t_mlp <= 1.05 * t_pap
+    finally:
+        h.selector_set(None)
