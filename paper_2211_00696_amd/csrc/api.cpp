@@ -218,6 +218,8 @@ struct phiq_handle_s {
   int device = 0;
   Profiler prof;
   hipStream_t aux = nullptr;      // side stream: scaling chain of the 1D factors, phi_0
+  hipStream_t ps = nullptr;       // plan stream of phiq_action: the next call's plan overlaps this execution
+  hipEvent_t tr_ready = nullptr;  // a one-call plan's factors are ready
   hipStream_t copy = nullptr;     // upload stream of transient plans
   hipEvent_t tr_fork = nullptr;   // fork/join events of transient plans
   hipEvent_t tr_join = nullptr;
@@ -754,6 +756,12 @@ phiq_status plan_build(phiq_handle h, const phiq_kron_op* op, double t, int p, d
   if (transient) {
     const int k = h->tr_next;
     h->tr_next ^= 1;
+    // the call before last used this buffer: its execution must be done
+    // before the upload (on st) overwrites it
+    if (h->tr_used[k] && h->tr_free[k] && hipStreamWaitEvent(st, h->tr_free[k], 0) != hipSuccess) {
+      delete P;
+      return PHIQ_ERR_HIP;
+    }
     phiq_status s = ensure(h, h->tr_buf[k], P->bytes);
     if (s != PHIQ_OK) {
       delete P;
@@ -1344,6 +1352,8 @@ phiq_status phiq_destroy(phiq_handle h) {
   if (h->tr_join) (void)hipEventDestroy(h->tr_join);
   for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
   if (h->aux) (void)hipStreamDestroy(h->aux);
+  if (h->ps) (void)hipStreamDestroy(h->ps);
+  if (h->tr_ready) (void)hipEventDestroy(h->tr_ready);
   if (h->copy) (void)hipStreamDestroy(h->copy);
   if (h->tr_fork2) (void)hipEventDestroy(h->tr_fork2);
   if (h->tr_phi0) (void)hipEventDestroy(h->tr_phi0);
@@ -1420,9 +1430,24 @@ phiq_status phiq_action(phiq_handle h, const phiq_kron_op* op, double t, int p, 
   if (opt && opt->workspace_cap) h->cap_bytes = opt->workspace_cap;
   phiq_plan P = nullptr;
   phiq_report r{};
-  PHIQ_TRY(plan_build(h, op, t, p, tol, opt, true, &P, &r, stream, /*defer_device=*/true));
+  const bool want_graph = (!opt || opt->use_graphs) && !h->prof.on;
+  // Without graphs, the plan (upload, 1D exponentials) goes on the handle's
+  // plan stream and the caller's stream waits for it: the next call's plan
+  // then runs while this call's quadrature and squaring do.
+  hipStream_t pst = stream;
+  if (!want_graph) {
+    if (!h->ps) PHIQ_HIP(hipStreamCreateWithFlags(&h->ps, hipStreamNonBlocking));
+    if (!h->tr_ready) PHIQ_HIP(hipEventCreateWithFlags(&h->tr_ready, hipEventDisableTiming));
+    for (int k = 0; k < 2; ++k)
+      if (!h->tr_free[k]) PHIQ_HIP(hipEventCreateWithFlags(&h->tr_free[k], hipEventDisableTiming));
+    pst = h->ps;
+    // the plan stream must not start before what the caller queued earlier
+    // on its stream that the plan could depend on: nothing (the plan reads
+    // only host data and its own buffer), so no wait here
+  }
+  PHIQ_TRY(plan_build(h, op, t, p, tol, opt, true, &P, &r, pst, /*defer_device=*/true));
   phiq_status s = PHIQ_OK;
-  const bool graphable = (!opt || opt->use_graphs) && P->opt.rule == PHIQ_RULE_GAUSS && !h->prof.on;
+  const bool graphable = want_graph && P->opt.rule == PHIQ_RULE_GAUSS;
   if (graphable) {
     // v and out must not overlap (checked by execute on the eager path)
     const char* vb = (const char*)v;
@@ -1494,10 +1519,16 @@ phiq_status phiq_action(phiq_handle h, const phiq_kron_op* op, double t, int p, 
       r.workspace_bytes = h->held();
     }
   } else {
-    s = plan_enqueue(P, stream);
+    s = plan_enqueue(P, pst);
+    if (s == PHIQ_OK && pst != stream) {
+      if (hipEventRecord(h->tr_ready, pst) != hipSuccess || hipStreamWaitEvent(stream, h->tr_ready, 0) != hipSuccess)
+        s = PHIQ_ERR_HIP;
+    }
     if (s == PHIQ_OK) s = phiq_plan_execute(P, v, 1, out, &r, stream);
   }
-  if (P->tr_slot >= 0 && h->tr_free[P->tr_slot]) (void)hipEventRecord(h->tr_free[P->tr_slot], stream);
+  if (P->tr_slot >= 0 && h->tr_free[P->tr_slot]) {
+    if (hipEventRecord(h->tr_free[P->tr_slot], stream) == hipSuccess) h->tr_used[P->tr_slot] = true;
+  }
   if (rep) *rep = r;
   if (!P->cc_E.empty()) (void)hipStreamSynchronize(stream);
   delete P;  // transient: memory stays in the handle
