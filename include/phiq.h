@@ -345,13 +345,21 @@ typedef struct {
 phiq_status phiq_profile_start(phiq_handle h, unsigned class_mask);
 phiq_status phiq_profile_stop(phiq_handle h, phiq_kernel_stat* stats, int max_stats, int* n_stats);
 
+/* Tile shape of the FP64 mode products for every later launch of one kind:
+ * kind 0 (plain mode product), 1 (with the node sum), 2 (with the squaring
+ * combination); cfg -1 restores the autotuned or default choice, 0..count-1
+ * forces that shape (tuning, testing; squaring shapes 7.. need p <= 4).
+ * *count (nullable) = number of shapes of the kind. */
+phiq_status phiq_tile_config(phiq_handle h, int kind, int cfg, int* count);
+
 /* ---------------------------------------------------------------------------
  * Autotuner.
  *
  * Times every tile shape of the FP64 mode-product kernels on the launch
  * shapes a phi-action with these sizes makes (dim axes of sizes n[d], p
- * orders, m quadrature nodes: node products with m+1 batches, squaring
- * products with p batches, the fused node sum and the fused squaring step)
+ * orders, m quadrature nodes: node products with m batches, phi_0 with 1,
+ * squaring products with p batches, the fused node sum and the fused
+ * squaring step)
  * and keeps the fastest shape per launch shape in the handle; later calls
  * with those shapes use it.  Synchronises the stream.  times may be NULL or
  * HOST [64][16]: row r = launch shape r in the order above, column c = the

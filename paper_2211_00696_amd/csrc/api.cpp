@@ -241,6 +241,7 @@ struct phiq_handle_s {
   std::vector<GraphEntry> graphs;
   std::vector<std::vector<long long>> seen;  // keys run once eagerly
   std::vector<TuneEntry> tune;  // fastest tile shape per launch shape (autotuner)
+  int force_cfg[3] = {-1, -1, -1};  // phiq_tile_config: one shape for every launch of a kind
   DevBuf ws;                     // execute workspace (T0, T1, Ya, Yb)
   DevBuf scratch;                // transient plans (phiq_action) and phiq_expm
   std::vector<DevBuf> cc_levels; // node vectors of the adaptive rule, per level
@@ -402,7 +403,7 @@ phiq_status L_ttm(phiq_handle h, int cls, const TtmArgs& a0, phiq_precision prec
   }
   ttm_work(a, cls, &fl, &by);
   const int kind = kind_of(cls);
-  const int cfg = (prec == PHIQ_PREC_FP64) ? tuned_cfg(h, kind, a) : -1;
+  const int cfg = (prec != PHIQ_PREC_FP64) ? -1 : (h->force_cfg[kind] >= 0 ? h->force_cfg[kind] : tuned_cfg(h, kind, a));
   return prof_launch(h, st, cls, fl, by, [&] { return launch_kind(kind, a, prec, st, cfg); });
 }
 
@@ -1716,6 +1717,15 @@ phiq_status phiq_profile_stop(phiq_handle h, phiq_kernel_stat* stats, int max_st
   return PHIQ_OK;
 }
 
+phiq_status phiq_tile_config(phiq_handle h, int kind, int cfg, int* count) {
+  if (!h || kind < 0 || kind > 2) return PHIQ_ERR_INVALID_ARG;
+  const int nc = ttm_num_configs(kind);
+  if (count) *count = nc;
+  if (cfg < -1 || cfg >= nc) return PHIQ_ERR_INVALID_ARG;
+  h->force_cfg[kind] = cfg;
+  return PHIQ_OK;
+}
+
 phiq_status phiq_autotune(phiq_handle h, int dim, const int* n, int p, int m, double* times, hipStream_t st) {
   // times is [64][16] (ms per launch shape and tile shape)
   if (!h || !n || dim < 1 || dim > PHIQ_MAX_DIM || p < 0 || p > PHIQ_MAX_P || m < 1 || m > 4096)
@@ -1751,8 +1761,9 @@ phiq_status phiq_autotune(phiq_handle h, int dim, const int* n, int p, int m, do
   std::vector<Shape> shapes;
   for (int d = 0; d < dim; ++d) {
     const int L = (int)(N / n[d]);
-    shapes.push_back({0, n[d], L, m + 1});
-    if (p > 0) shapes.push_back({0, n[d], L, p});
+    shapes.push_back({0, n[d], L, m});  // node chains
+    shapes.push_back({0, n[d], L, 1});  // phi_0
+    if (p > 0 && p != m && p != 1) shapes.push_back({0, n[d], L, p});  // squaring orders
     if (d == 0 && p > 0) {
       shapes.push_back({1, n[d], L, m});
       shapes.push_back({2, n[d], L, p});

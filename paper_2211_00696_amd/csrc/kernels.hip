@@ -57,7 +57,7 @@ __device__ __forceinline__ bool tile_of_block(int M, int L, int nb, int& m0, int
 }
 
 template <class C, bool VEC>
-__global__ __launch_bounds__(C::NT) void ttm_store_kernel(TtmArgs a) {
+__global__ __launch_bounds__(C::NT, C::MINW) void ttm_store_kernel(TtmArgs a) {
   __shared__ double smem[2 * (C::BM + C::BN) * C::LDK];
   int m0, n0, b;
   if (!tile_of_block<C>(a.M, a.L, a.nbatch, m0, n0, b)) return;
@@ -81,7 +81,7 @@ __global__ __launch_bounds__(C::NT) void ttm_store_kernel(TtmArgs a) {
 // Node sum fused into the last mode product: every block loops over all
 // nodes b and keeps the NP running sums in registers.
 template <class C, int NP, bool VEC>
-__global__ __launch_bounds__(C::NT) void ttm_accum_kernel(TtmArgs a) {
+__global__ __launch_bounds__(C::NT, C::MINW) void ttm_accum_kernel(TtmArgs a) {
   __shared__ double smem[2 * (C::BM + C::BN) * C::LDK];
   int m0, n0, bb;
   if (!tile_of_block<C>(a.M, a.L, 1, m0, n0, bb)) return;
@@ -121,7 +121,7 @@ __global__ __launch_bounds__(C::NT) void ttm_accum_kernel(TtmArgs a) {
 // Modified squaring fused into the last mode product (eq. squaring):
 // batch b is order i = b+1, out = 2^{-i} (E y_i + sum_{j=1}^{i} y_j/(i-j)!).
 template <class C, bool VEC>
-__global__ __launch_bounds__(C::NT) void ttm_square_kernel(TtmArgs a) {
+__global__ __launch_bounds__(C::NT, C::MINW) void ttm_square_kernel(TtmArgs a) {
   __shared__ double smem[2 * (C::BM + C::BN) * C::LDK];
   int m0, n0, b;
   if (!tile_of_block<C>(a.M, a.L, a.nbatch, m0, n0, b)) return;
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(C::NT) void ttm_square_kernel(TtmArgs a) {
 // block computes E y_i for i = 1..p in turn and reads every y_j tile once,
 // keeping it in registers for the later orders.  Same factor E for all i.
 template <class C, int NP, bool VEC>
-__global__ __launch_bounds__(C::NT) void ttm_square_all_kernel(TtmArgs a) {
+__global__ __launch_bounds__(C::NT, C::MINW) void ttm_square_all_kernel(TtmArgs a) {
   __shared__ double smem[2 * (C::BM + C::BN) * C::LDK];
   int m0, n0, bb;
   if (!tile_of_block<C>(a.M, a.L, 1, m0, n0, bb)) return;
@@ -409,7 +409,7 @@ int default_cfg(int kind, int M, int nb) {
 }
 }  // namespace
 
-int ttm_num_configs(int kind) { return kind == 1 ? 4 : (kind == 2 ? 10 : 8); }
+int ttm_num_configs(int kind) { return kind == 1 ? 6 : (kind == 2 ? 11 : 11); }
 
 int launch_ttm_store(const TtmArgs& a, phiq_precision prec, void* stream, int cfg) {
   if (prec != PHIQ_PREC_FP64) return launch_ttm_store_lowp(a, prec, stream);
@@ -424,6 +424,9 @@ int launch_ttm_store(const TtmArgs& a, phiq_precision prec, void* stream, int cf
     case 5: return store_cfg<Tile64x128>(a, st);
     case 6: return store_cfg<Tile64k32>(a, st);
     case 7: return store_cfg<Tile128x128w8>(a, st);
+    case 8: return store_cfg<Tile64x128p1>(a, st);
+    case 9: return store_cfg<Tile128p1>(a, st);
+    case 10: return store_cfg<Tile64p1>(a, st);
   }
   return hipErrorInvalidValue;
 }
@@ -438,6 +441,8 @@ int launch_ttm_accum(const TtmArgs& a, phiq_precision prec, void* stream, int cf
     case 1: return accum_cfg<Tile128>(a, st);
     case 2: return accum_cfg<Tile64x128>(a, st);
     case 3: return accum_cfg<Tile64k32>(a, st);
+    case 4: return accum_cfg<Tile64x128p1r>(a, st);
+    case 5: return accum_cfg<Tile64p1>(a, st);
   }
   return hipErrorInvalidValue;
 }
@@ -471,6 +476,7 @@ int launch_ttm_square(const TtmArgs& a, phiq_precision prec, void* stream, int c
       case 7: return square_all_cfg<Tile64>(a, st);
       case 8: return square_all_cfg<Tile64k32>(a, st);
       case 9: return square_all_cfg<Tile128>(a, st);
+      case 10: return square_all_cfg<Tile64p1>(a, st);
     }
     return hipErrorInvalidValue;
   }

@@ -12,14 +12,18 @@ namespace phiq {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-template <int BM_, int BN_, int BK_, int WAVES_M_, int WAVES_N_>
+// PAD: doubles of padding per LDS row (2 keeps rows 16-byte aligned for
+// paired stores; 1 saves LDS so that one more block fits on a CU).
+// MINW: waves per SIMD the kernels must allow (register budget), 1 = any.
+template <int BM_, int BN_, int BK_, int WAVES_M_, int WAVES_N_, int PAD_ = 2, int MINW_ = 1>
 struct Tile {
   static constexpr int BM = BM_, BN = BN_, BK = BK_;
+  static constexpr int MINW = MINW_;
   static constexpr int WAVES_M = WAVES_M_, WAVES_N = WAVES_N_;
   static constexpr int NT = 64 * WAVES_M_ * WAVES_N_;
   static constexpr int WM = BM_ / WAVES_M_, WN = BN_ / WAVES_N_;
   static constexpr int TM = WM / 16, TN = WN / 16;
-  static constexpr int LDK = BK_ + 2;  // padded row length in LDS (doubles)
+  static constexpr int LDK = BK_ + PAD_;  // padded row length in LDS (doubles)
   static constexpr int A_PER = BM_ * BK_ / NT;
   static constexpr int B_PER = BN_ * BK_ / NT;
   static_assert(A_PER * NT == BM_ * BK_ && B_PER * NT == BN_ * BK_, "tile not divisible");
@@ -35,6 +39,12 @@ using Tile64x128 = Tile<64, 128, 16, 2, 2>;
 using Tile64k32 = Tile<64, 64, 32, 2, 2>;
 using Tile128x128w8 = Tile<128, 128, 16, 4, 2>;  // 8 waves: fewer, larger blocks
 using Tile32 = Tile<32, 32, 16, 1, 1>;
+// one double of padding: 52 KB (64x128) / 35 KB (64x64) per block, so three
+// (64x128, 128x64) or four (64x64) blocks fit in a CU's 160 KB of LDS
+using Tile64x128p1 = Tile<64, 128, 16, 2, 2, 1, 3>;
+using Tile128p1 = Tile<128, 64, 16, 2, 2, 1, 3>;
+using Tile64p1 = Tile<64, 64, 16, 2, 2, 1>;
+using Tile64x128p1r = Tile<64, 128, 16, 2, 2, 1>;  // the same without the register cap (fused epilogues)
 
 // ---------------------------------------------------------------------------
 // Staging of rows [r0, r0+ROWS) x k-chunk [k0, k0+BK) of a row-major matrix
@@ -83,7 +93,12 @@ __device__ __forceinline__ void store_kmajor(double* s, const double (&reg)[PER]
       const int e = threadIdx.x + i * NT;
       const int r = e / (BK / 2), kk = 2 * (e % (BK / 2));
       const bool ok = !ZK || k0 + kk < k_valid;
-      *(d2*)(s + r * LDK + kk) = ok ? (d2){reg[2 * i], reg[2 * i + 1]} : (d2){0.0, 0.0};
+      if constexpr (LDK % 2 == 0) {
+        *(d2*)(s + r * LDK + kk) = ok ? (d2){reg[2 * i], reg[2 * i + 1]} : (d2){0.0, 0.0};
+      } else {  // rows are only 8-byte aligned
+        s[r * LDK + kk] = ok ? reg[2 * i] : 0.0;
+        s[r * LDK + kk + 1] = ok ? reg[2 * i + 1] : 0.0;
+      }
     }
   } else {
 #pragma unroll

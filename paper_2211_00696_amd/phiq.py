@@ -366,6 +366,14 @@ class Handle:
                "phiq_mlp_train")
         return w, hist[:steps]
 
+    def tile_config(self, kind, cfg=-1):
+        """Force tile shape cfg for every FP64 launch of kind 0 (store), 1 (node sum), 2 (squaring);
+        -1 restores the tuned/default choice.  Returns the number of shapes of the kind."""
+        lib = L.load()
+        n = c_int()
+        _check(lib.phiq_tile_config(self._h, int(kind), int(cfg), byref(n)), "phiq_tile_config")
+        return n.value
+
     def selector_set(self, w):
         """Install the selector network (host float32 array) or clear it (None)."""
         lib = L.load()

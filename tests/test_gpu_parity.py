@@ -268,3 +268,25 @@ def test_graph_replay_matches_eager(h, precision):
         out.zero_()
         h.action(pr["mats"], pr["t"], 3, v, tol=1e-9, out=out, precision=precision)
         assert np.array_equal(host(out), e), k
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2])
+def test_every_tile_shape_vs_oracle(h, kind):
+    """Each FP64 tile shape (forced for every launch of its kind) on a 3D
+    problem with an even size (16-byte staging) and one with odd sizes."""
+    from oracle import phiquad as Q
+
+    cases = [I.problem("advdiff", seed=21, n=48, dim=3, t=1e-3), I.problem("advdiff", seed=22, n=33, dim=3, t=2e-3)]
+    refs = [Q.phiquadmv(pr["mats"], pr["t"], pr["v"], 3, eps=1e-14, beta=1.0) for pr in cases]
+    count = h.tile_config(kind, -1)
+    try:
+        for cfg in range(count):
+            h.tile_config(kind, cfg)
+            for pr, ref in zip(cases, refs):
+                print("kind", kind, "shape", cfg, "n", pr["n"], flush=True)
+                out, _ = h.action(pr["mats"], pr["t"], 3, torch.from_numpy(pr["v"]).cuda(), tol=1e-10)
+                o = out.cpu().numpy()
+                e = max(float(np.max(np.abs(o[k] - ref[k])) / np.max(np.abs(ref[k]))) for k in range(4))
+                assert e < 1e-9, (kind, cfg, pr["n"], e)
+    finally:
+        h.tile_config(kind, -1)
