@@ -409,7 +409,7 @@ int default_cfg(int kind, int M, int nb) {
 }
 }  // namespace
 
-int ttm_num_configs(int kind) { return kind == 1 ? 6 : (kind == 2 ? 11 : 11); }
+int ttm_num_configs(int kind) { return kind == 1 ? 7 : (kind == 2 ? 12 : 14); }
 
 int launch_ttm_store(const TtmArgs& a, phiq_precision prec, void* stream, int cfg) {
   if (prec != PHIQ_PREC_FP64) return launch_ttm_store_lowp(a, prec, stream);
@@ -427,6 +427,9 @@ int launch_ttm_store(const TtmArgs& a, phiq_precision prec, void* stream, int cf
     case 8: return store_cfg<Tile64x128p1>(a, st);
     case 9: return store_cfg<Tile128p1>(a, st);
     case 10: return store_cfg<Tile64p1>(a, st);
+    case 11: return store_cfg<Tile64x128p1w8>(a, st);
+    case 12: return store_cfg<Tile128p1w8>(a, st);
+    case 13: return store_cfg<Tile128x128p1>(a, st);
   }
   return hipErrorInvalidValue;
 }
@@ -443,6 +446,7 @@ int launch_ttm_accum(const TtmArgs& a, phiq_precision prec, void* stream, int cf
     case 3: return accum_cfg<Tile64k32>(a, st);
     case 4: return accum_cfg<Tile64x128p1r>(a, st);
     case 5: return accum_cfg<Tile64p1>(a, st);
+    case 6: return accum_cfg<Tile64p1w8>(a, st);
   }
   return hipErrorInvalidValue;
 }
@@ -477,6 +481,7 @@ int launch_ttm_square(const TtmArgs& a, phiq_precision prec, void* stream, int c
       case 8: return square_all_cfg<Tile64k32>(a, st);
       case 9: return square_all_cfg<Tile128>(a, st);
       case 10: return square_all_cfg<Tile64p1>(a, st);
+      case 11: return square_all_cfg<Tile64p1w8>(a, st);
     }
     return hipErrorInvalidValue;
   }

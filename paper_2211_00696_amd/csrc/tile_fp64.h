@@ -45,6 +45,12 @@ using Tile64x128p1 = Tile<64, 128, 16, 2, 2, 1, 3>;
 using Tile128p1 = Tile<128, 64, 16, 2, 2, 1, 3>;
 using Tile64p1 = Tile<64, 64, 16, 2, 2, 1>;
 using Tile64x128p1r = Tile<64, 128, 16, 2, 2, 1>;  // the same without the register cap (fused epilogues)
+// eight waves per block (32 x 32 or 32 x 16 per wave): fewer registers per
+// wave, more waves per CU to hide latency
+using Tile64x128p1w8 = Tile<64, 128, 16, 2, 4, 1>;
+using Tile128p1w8 = Tile<128, 64, 16, 4, 2, 1>;
+using Tile128x128p1 = Tile<128, 128, 16, 2, 2, 1, 2>;
+using Tile64p1w8 = Tile<64, 64, 16, 2, 4, 1>;
 
 // ---------------------------------------------------------------------------
 // Staging of rows [r0, r0+ROWS) x k-chunk [k0, k0+BK) of a row-major matrix
