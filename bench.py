@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import math
 import json
 import os
 import sys
@@ -100,7 +101,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--workload", default="advdiff3d", choices=["advdiff3d", "batch512", "etdrk4"],
+    ap.add_argument("--workload", default="advdiff3d",
+                    choices=["advdiff3d", "batch512", "etdrk4", "precision256", "problem1"],
                     help="advdiff3d: one 3D problem (default); batch512: 512 mixed 2D/3D problems in one "
                          "batched call (phiq_action_batched); etdrk4: 100 ETD-RK4 steps of Allen-Cahn on 3D n=128")
     ap.add_argument("--count", type=int, default=512, help="batch512: number of problems")
@@ -121,6 +123,10 @@ def main():
         return bench_batch(args, rank)
     if args.workload == "etdrk4":
         return bench_etd(args, rank)
+    if args.workload == "precision256":
+        return bench_precision(args, rank)
+    if args.workload == "problem1":
+        return bench_problem1(args, rank)
 
     from paper_2211_00696_amd import inputs, phiq
 
@@ -366,6 +372,110 @@ def bench_batch(args, rank):
     h.close()
     if rank == 0:
         print(json.dumps(result), flush=True)
+
+
+def bench_precision(args, rank):
+    """3D n=256 advection-diffusion, phi_0..phi_3: every precision form and selector at tol 1e-5, 1e-6
+    and 1e-10, error per phi_k against the oracle (its numpy quadrature at eps 1e-14), time per action."""
+    import torch
+
+    from oracle import phiquad
+    from paper_2211_00696_amd import inputs, phiq, selector
+
+    n = args.n if args.n != 128 else 256
+    pr = inputs.problem("advdiff3d", seed=args.seed, n=n)
+    N, p = pr["v"].size, pr["p"]
+    v = torch.from_numpy(pr["v"]).cuda()
+    h = phiq.Handle(0)
+    h.selector_set(selector.load_weights())
+    _, rep0 = h.action(pr["mats"], pr["t"], p, v, tol=1e-8)
+    h.autotune([n] * 3, p, rep0["m"])
+    t0 = time.perf_counter()
+    ref = phiquad.phiquadmv(pr["mats"], pr["t"], pr["v"], p, eps=1e-14, beta=1.0)
+    oracle_s = time.perf_counter() - t0
+    runs = []
+    for tol in (1e-5, 1e-6, 1e-10):
+        for prec in ("fp64", "fp32", "bf16x3"):
+            for sel in ("paper", "mlp"):
+                kw = dict(tol=tol, precision=prec, selector=sel)
+                out, rep = h.action(pr["mats"], pr["t"], p, v, **kw)
+                h.action(pr["mats"], pr["t"], p, v, **kw)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                for _ in range(args.steps):
+                    h.action(pr["mats"], pr["t"], p, v, out=out, **kw)
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t1) * 1e3 / args.steps
+                o = out.cpu().numpy()
+                errs = [float(np.max(np.abs(o[k] - ref[k])) / np.max(np.abs(ref[k]))) for k in range(p + 1)]
+                runs.append(dict(tol=tol, precision=prec, selector=sel, ms=ms, grid_pts_per_s=N / (ms * 1e-3),
+                                 l=rep["l"], m=rep["m"], selector_used=rep["selector"], rel_err_per_phi_k=errs,
+                                 meets_tol=max(errs) <= tol))
+                print(json.dumps(runs[-1]), file=sys.stderr, flush=True)
+    # FP64 mode-product utilisation at n=256 (live events, one action)
+    h.profile_start(["ttm_store", "ttm_accum", "ttm_square"])
+    h.action(pr["mats"], pr["t"], p, v, tol=1e-8)
+    st = h.profile_stop()
+    util = {k: s["flops"] / (s["ms"] * 1e-3) / 1e12 / PEAK_TFLOPS["fp64"] for k, s in st.items() if s["ms"] > 0}
+    base = {r["tol"]: r["ms"] for r in runs if r["precision"] == "fp64" and r["selector"] == "paper"}
+    speed = []
+    for r in runs:
+        if r["meets_tol"]:
+            speed.append(dict(tol=r["tol"], form=r["precision"] + "+" + r["selector"], speedup_vs_fp64_paper=base[r["tol"]] / r["ms"]))
+    best = {}
+    for s_ in speed:
+        if s_["tol"] not in best or s_["speedup_vs_fp64_paper"] > best[s_["tol"]]["speedup_vs_fp64_paper"]:
+            best[s_["tol"]] = s_
+    result = {"metric": "phi_k(tA)v grid-pts/s by precision form and selector, 3D n=%d" % n, "unit": "grid-pts/s",
+              "n_gpus": 1, "steps": args.steps, "data": "synthetic", "dtype": "f64/f32/bf16x3",
+              "config": {"workload": "3D advection-diffusion n=%d (N=%d), t=1e-3, phi_0..phi_3, seed %d" % (n, N, args.seed)},
+              "oracle_seconds": oracle_s, "runs": runs, "fp64_mfma_utilisation_tol1e-8": util,
+              "meets_tol_speedups": speed, "best_at_equal_accuracy": best}
+    h.close()
+    if rank == 0:
+        print(json.dumps(result), flush=True)
+
+
+def bench_problem1(args, rank):
+    """The paper's Problem 1 (Section 4): 3D heat, n = 2^r - 1, tau = 1/8, b = sin sin sin, phi_1..phi_20,
+    eps 1e-14, Gauss and Clenshaw-Curtis: our time per action next to the paper's (one thread of an
+    Intel i5-8279U, MATLAB), with the error against the closed form."""
+    import torch
+
+    from paper_2211_00696_amd import inputs, phiq
+
+    paper = {4: (0.19, 0.11), 5: (0.95, 1.15), 6: (1.34, 1.79), 7: (25.63, 31.50)}
+    h = phiq.Handle(0)
+    rows = []
+    for r in (4, 5, 6, 7):
+        n = 2 ** r - 1
+        pr = inputs.problem("heat3d_eig", n=n)
+        v = torch.from_numpy(pr["v"]).cuda()
+        lam = 3.0 * 4.0 * (n + 1) ** 2 * math.sin(math.pi / (2 * (n + 1))) ** 2
+        for rule in ("gauss", "cc"):
+            out, rep = h.action(pr["mats"], pr["t"], pr["p"], v, tol=pr["tol"], rule=rule)
+            h.action(pr["mats"], pr["t"], pr["p"], v, tol=pr["tol"], rule=rule)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                h.action(pr["mats"], pr["t"], pr["p"], v, tol=pr["tol"], rule=rule, out=out)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / args.steps
+            # phi_k(-tau A) b = phi_k(-tau lam) b exactly (b is an eigenvector)
+            from oracle import phi_exact
+
+            o = out.cpu().numpy()
+            err = max(float(np.max(np.abs(o[k] - phi_exact.phi_scalar(k, -pr["t"] * lam) * pr["v"]))
+                            / np.max(np.abs(phi_exact.phi_scalar(k, -pr["t"] * lam) * pr["v"]))) for k in range(1, pr["p"] + 1))
+            rows.append(dict(r=r, N=n ** 3, rule=rule, l=rep["l"], m=rep["m"] if rule == "gauss" else None,
+                             ms=ms, paper_seconds=paper[r][0 if rule == "gauss" else 1],
+                             ratio_paper_over_ours=paper[r][0 if rule == "gauss" else 1] / (ms * 1e-3),
+                             max_rel_err_phi_1_to_20=err))
+    h.close()
+    if rank == 0:
+        print(json.dumps({"metric": "Problem 1 (Section 4) time per phi_1..phi_20 action vs the paper",
+                          "unit": "ms", "note": "paper: serial MATLAB on one thread of an Intel i5-8279U "
+                          "(context, another machine)", "rows": rows}), flush=True)
 
 
 def bench_etd(args, rank):
