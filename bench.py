@@ -102,7 +102,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--workload", default="advdiff3d",
-                    choices=["advdiff3d", "batch512", "etdrk4", "precision256", "problem1"],
+                    choices=["advdiff3d", "batch512", "etdrk4", "precision256", "problem1", "problem3"],
                     help="advdiff3d: one 3D problem (default); batch512: 512 mixed 2D/3D problems in one "
                          "batched call (phiq_action_batched); etdrk4: 100 ETD-RK4 steps of Allen-Cahn on 3D n=128")
     ap.add_argument("--count", type=int, default=512, help="batch512: number of problems")
@@ -127,6 +127,8 @@ def main():
         return bench_precision(args, rank)
     if args.workload == "problem1":
         return bench_problem1(args, rank)
+    if args.workload == "problem3":
+        return bench_problem3(args, rank)
 
     from paper_2211_00696_amd import inputs, phiq
 
@@ -476,6 +478,56 @@ def bench_problem1(args, rank):
         print(json.dumps({"metric": "Problem 1 (Section 4) time per phi_1..phi_20 action vs the paper",
                           "unit": "ms", "note": "paper: serial MATLAB on one thread of an Intel i5-8279U "
                           "(context, another machine)", "rows": rows}), flush=True)
+
+
+# Tables TimesHochOster7 / TimesHochOster8 (seconds; Gauss, CC) per method and step count
+PAPER_P3 = {
+    127: {1: {2: (0.14, 0.17), 8: (0.12, 0.21), 32: (0.42, 0.77), 128: (1.23, 2.88), 512: (4.55, 11.15)},
+          2: {2: (0.10, 0.15), 8: (0.22, 0.40), 32: (0.67, 1.55), 128: (2.42, 5.69), 512: (8.94, 22.22)},
+          3: {2: (0.18, 0.41), 8: (0.57, 1.37), 32: (1.95, 5.19), 128: (6.56, 20.29), 512: (25.17, 78.17)}},
+    255: {1: {2: (0.13, 0.25), 8: (0.38, 0.78), 32: (1.32, 2.87), 128: (4.87, 11.07), 512: (19.20, 45.55)},
+          2: {2: (0.22, 0.41), 8: (0.81, 1.50), 32: (2.56, 5.76), 128: (10.07, 22.51), 512: (38.25, 91.02)},
+          3: {2: (0.59, 1.37), 8: (2.10, 5.20), 32: (7.74, 20.65), 128: (28.89, 80.64), 512: (108.33, 305.07)}},
+}
+
+
+def bench_problem3(args, rank):
+    """The paper's Problem 3 (Section 5): exponential Euler / RK2 / RK3 on 2D Hochbruck-Ostermann with
+    2^7 and 2^8 elements per axis, T = 1: total time per run next to the paper's Tables TimesHochOster7/8,
+    and the error against the exact solution."""
+    import torch
+
+    from oracle import exprk as OR
+    from paper_2211_00696_amd import inputs, phiq
+
+    h = phiq.Handle(0)
+    rows = []
+    for n in (127, 255):
+        mats = [inputs.fd_laplacian(n), inputs.fd_laplacian(n)]
+        u0 = torch.from_numpy(OR.exact(n, 0.0)).cuda()
+        ue = OR.exact(n, 1.0)
+        for method in (1, 2, 3):
+            for rule in ("gauss", "cc"):
+                u = u0.clone()
+                h.exprk(mats, method, 2, u, rule=rule)  # warm-up
+                for steps in (2, 8, 32, 128, 512):
+                    u = u0.clone()
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    h.exprk(mats, method, steps, u, rule=rule)
+                    torch.cuda.synchronize()
+                    dt = time.perf_counter() - t0
+                    err = float(np.max(np.abs(u.cpu().numpy() - ue)))
+                    ps = PAPER_P3[n][method][steps][0 if rule == "gauss" else 1]
+                    rows.append(dict(elements=n + 1, method=["", "Euler", "RK2", "RK3"][method], rule=rule,
+                                     steps=steps, seconds=dt, paper_seconds=ps, ratio_paper_over_ours=ps / dt,
+                                     err_vs_exact=err))
+                    print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    h.close()
+    if rank == 0:
+        print(json.dumps({"metric": "Problem 3 (Section 5) total time of an exponential Runge-Kutta run, T = 1",
+                          "unit": "s", "note": "paper: serial MATLAB on one thread of an Intel i5-8279U "
+                          "(context, another machine); tol 1e-8 (the paper: 1e-14)", "rows": rows}), flush=True)
 
 
 def bench_etd(args, rank):

@@ -273,6 +273,21 @@ phiq_status phiq_etdrk4(phiq_handle h, const phiq_kron_op* op, double tau, int n
                         double c1, double c3, double tol, int use_graph, double* u,
                         phiq_etd_report* rep, hipStream_t stream);
 
+/* The exponential Runge-Kutta methods of Section 5 (Table RK) on the paper's
+ * Problem 3 (Hochbruck-Ostermann): u' = -A u + 1/(1 + u^2) + f(x, y, t) on
+ * (0,1)^2 with A = A^0 (+) A^1 (dim 2, n x n interior grid, nodes
+ * x_i = (i+1)/(n+1), x slowest) and f the manufactured source for which
+ * u = x(1-x) y(1-y) e^t solves the PDE.  method 1 = exponential Euler,
+ * 2 = RK2 with c2, 3 = RK3 with c2 and c3 = 2/3.  nsteps steps of T/nsteps
+ * from t = 0, in place on u (DEVICE n^2 values, the initial condition on
+ * entry).  phi-actions with tolerance tol and options opt (rule etc.); the
+ * vectors of one stage go through one plan execution.  Allocates 13 n^2
+ * doubles and returns when the steps have finished.  rep (nullable): the
+ * full-step plan.  PHIQ_ERR_UNSUPPORTED for other dimensions. */
+phiq_status phiq_exprk(phiq_handle h, const phiq_kron_op* op, int method, double c2, int nsteps,
+                       double T, double tol, const phiq_options* opt, double* u, phiq_report* rep,
+                       hipStream_t stream);
+
 /* ---------------------------------------------------------------------------
  * Learned (l, m) selector: a network 8 -> 64 -> 64 -> 2 with tanh hidden
  * layers in FP32.  Parameters, one vector of PHIQ_MLP_NPARAM floats: W1

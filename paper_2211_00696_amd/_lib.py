@@ -42,6 +42,7 @@ EXPORTS = [
     "phiq_action_batched",
     "phiq_batch_info",
     "phiq_etdrk4",
+    "phiq_exprk",
     "phiq_mlp_forward",
     "phiq_mlp_grad",
     "phiq_mlp_train",
@@ -153,6 +154,8 @@ def load():
         "phiq_batch_info": (c_int, [c_int, P(Problem), P(Options), P(BatchStats)]),
         "phiq_etdrk4": (c_int, [c_void_p, P(KronOp), c_double, c_int, c_double, c_double, c_double, c_int,
                                 c_void_p, P(EtdReport), c_void_p]),
+        "phiq_exprk": (c_int, [c_void_p, P(KronOp), c_int, c_double, c_int, c_double, c_double, P(Options), c_void_p,
+                               P(Report), c_void_p]),
         "phiq_mlp_forward": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
         "phiq_mlp_grad": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, P(c_double), c_void_p]),
         "phiq_mlp_train": (c_int, [c_void_p, c_int, P(ctypes.c_float), P(ctypes.c_float), P(ctypes.c_float), c_int,

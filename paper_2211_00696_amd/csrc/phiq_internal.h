@@ -72,6 +72,15 @@ phiq_status batch_fetch(phiq_handle h, int slot, void* dst, size_t bytes, hipStr
 phiq_status plan_settle(phiq_plan P);
 bool plan_profiling(phiq_plan P);  // live kernel timing is on for the plan's handle
 
+// ---- exprk.hip: Problem 3 of Section 5 ---------------------------------------
+// g = g(t, e + sa a + sb b) with g(t, u) = 1/(1+u^2) + f(x, y, t) on the n x n
+// interior grid of (0,1)^2 (a, b nullable); copy (nullable) = e.
+int launch_exprk_stage(const double* e, const double* a, double sa, const double* b, double sb, int n, double t,
+                       double* g, double* copy, void* stream);
+// out = x + sa a + sb b (a, b nullable); out may alias x or a
+int launch_exprk_comb(const double* x, const double* a, double sa, const double* b, double sb, double* out,
+                      long long N, void* stream);
+
 // ---- etd.hip: elementwise steps of the ETD-RK4 integrator ----------------
 // F(x) = c1 x + c3 x^3.  All arrays DEVICE, n elements.
 int launch_etd_nonlin(const double* x, double* fx, long long n, double c1, double c3, void* stream);

@@ -330,6 +330,19 @@ class Handle:
                                int(bool(graph)), _dev_ptr(u, "u"), byref(rep), _stream_ptr(stream)), "phiq_etdrk4")
         return rep.as_dict()
 
+    def exprk(self, mats, method, nsteps, u, T=1.0, c2=None, tol=1e-8, stream=None, **opts):
+        """Section 5's exponential Euler (1), RK2 (2) or RK3 (3) on Problem 3, in place on u; report dict."""
+        lib = L.load()
+        op = _Op(mats)
+        if u.numel() != op.N:
+            raise ValueError("u has %d entries, the operator needs %d" % (u.numel(), op.N))
+        if c2 is None:
+            c2 = 0.5 if method == 2 else 1.0 / 3.0
+        rep = L.Report()
+        _check(lib.phiq_exprk(self._h, byref(op.op), int(method), float(c2), int(nsteps), float(T), float(tol),
+                              byref(options(**opts)), _dev_ptr(u, "u"), byref(rep), _stream_ptr(stream)), "phiq_exprk")
+        return rep.as_dict()
+
     # ---- the learned selector's network (FP32) ----
     def mlp_forward(self, X, w, stream=None):
         """Y = net(X) on the device: X (B, 8) float32, w (NPARAM,) float32 device tensors."""

@@ -2,6 +2,7 @@
 
   python -m paper_2211_00696_amd.rocprof_summary times   TRACE.csv BENCH.json
   python -m paper_2211_00696_amd.rocprof_summary traffic FETCH.csv WRITE.csv BENCH.json COPY_MIB
+  python -m paper_2211_00696_amd.rocprof_summary mfma   COUNTERS.csv BENCH.json SIMDS
 
 `times` reads a `--kernel-trace` CSV and prints a markdown table per kernel,
 plus the average duration of the dominant class's launches inside bench.py's
@@ -12,6 +13,11 @@ the same command, calibrates each counter with the plain device copy that
 `bench.py --copy-probe-mib COPY_MIB` launches (a negation of COPY_MIB MiB into
 another buffer: COPY_MIB MiB read, COPY_MIB MiB written), and prints the HBM
 bytes per launch of the dominant class as JSON for profiles/traffic.json.
+
+`mfma` reads one `--pmc SQ_INSTS_VALU_MFMA_MOPS_F64 SQ_VALU_MFMA_BUSY_CYCLES
+GRBM_GUI_ACTIVE` CSV and prints, for the dominant class's timed-region
+launches, the FP64 MFMA flops the hardware executed (MOPS x 512) next to the
+algorithmic flops, and the MFMA busy fraction busy / (active cycles x SIMDS).
 
 bench.py's step sequence after warm-up is: K timed actions, K untimed
 actions, one plan execution, K executions of the reused plan.  Every step
@@ -136,11 +142,35 @@ def traffic(fetch_csv, write_csv, bench_json, copy_mib):
                             "workload": bench["config"]["workload"]}}, indent=1))
 
 
+def mfma(csv_path, bench_json, simds):
+    bench = json.load(open(bench_json))
+    dom = bench["roofline"]["kernel"]
+    per = defaultdict(dict)
+    names = {}
+    for r in _rows(csv_path):
+        i = int(r.get("Dispatch_Id", r.get("Correlation_Id", 0)))
+        per[i][r["Counter_Name"]] = per[i].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        names[i] = _short(_name(r))
+    cls = [(names[i], per[i]) for i in sorted(per) if CLASS_RE[dom].search(names[i])]
+    sl = _timed_slice(cls, bench)
+    mops = sum(c.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0) for _, c in sl) / len(sl)
+    busy = sum(c.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) for _, c in sl)
+    active = sum(c.get("GRBM_GUI_ACTIVE", 0.0) for _, c in sl)
+    alg = bench["roofline"]["flops_per_launch"]
+    print(json.dumps({dom: {"launches": len(sl), "mfma_flops_executed_per_launch": mops * 512.0,
+                            "algorithmic_flops_per_launch": alg, "executed_over_algorithmic": mops * 512.0 / alg,
+                            "mfma_busy_fraction": busy / (active * float(simds)) if active > 0 else None,
+                            "kernel_digest": bench["kernel_digest"], "workload": bench["config"]["workload"]}},
+                     indent=1))
+
+
 if __name__ == "__main__":
     if len(sys.argv) >= 4 and sys.argv[1] == "times":
         times(sys.argv[2], sys.argv[3])
     elif len(sys.argv) >= 6 and sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
+    elif len(sys.argv) >= 5 and sys.argv[1] == "mfma":
+        mfma(sys.argv[2], sys.argv[3], sys.argv[4])
     else:
         print(__doc__)
         sys.exit(2)
