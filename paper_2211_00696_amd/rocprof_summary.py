@@ -2,7 +2,7 @@
 
   python -m paper_2211_00696_amd.rocprof_summary times   TRACE.csv BENCH.json
   python -m paper_2211_00696_amd.rocprof_summary traffic FETCH.csv WRITE.csv BENCH.json COPY_MIB
-  python -m paper_2211_00696_amd.rocprof_summary mfma   COUNTERS.csv BENCH.json SIMDS
+  python -m paper_2211_00696_amd.rocprof_summary mfma   COUNTERS.csv BENCH.json
 
 `times` reads a `--kernel-trace` CSV and prints a markdown table per kernel,
 plus the average duration of the dominant class's launches inside bench.py's
@@ -14,10 +14,11 @@ the same command, calibrates each counter with the plain device copy that
 another buffer: COPY_MIB MiB read, COPY_MIB MiB written), and prints the HBM
 bytes per launch of the dominant class as JSON for profiles/traffic.json.
 
-`mfma` reads one `--pmc SQ_INSTS_VALU_MFMA_MOPS_F64 SQ_VALU_MFMA_BUSY_CYCLES
-GRBM_GUI_ACTIVE` CSV and prints, for the dominant class's timed-region
-launches, the FP64 MFMA flops the hardware executed (MOPS x 512) next to the
-algorithmic flops, and the MFMA busy fraction busy / (active cycles x SIMDS).
+`mfma` reads a `--pmc SQ_INSTS_VALU_MFMA_MOPS_F64` and/or `--pmc MfmaUtil`
+CSV and prints, for the dominant class's timed-region launches, the FP64
+MFMA flops the hardware executed (MOPS x 512) next to the algorithmic flops,
+and rocprofv3's derived MFMA utilisation (busy cycles over active cycles x
+SIMDs, with the reductions the tool defines).
 
 bench.py's step sequence after warm-up is: K timed actions, K untimed
 actions, one plan execution, K executions of the reused plan.  Every step
@@ -142,7 +143,7 @@ def traffic(fetch_csv, write_csv, bench_json, copy_mib):
                             "workload": bench["config"]["workload"]}}, indent=1))
 
 
-def mfma(csv_path, bench_json, simds):
+def mfma(csv_path, bench_json):
     bench = json.load(open(bench_json))
     dom = bench["roofline"]["kernel"]
     per = defaultdict(dict)
@@ -153,15 +154,17 @@ def mfma(csv_path, bench_json, simds):
         names[i] = _short(_name(r))
     cls = [(names[i], per[i]) for i in sorted(per) if CLASS_RE[dom].search(names[i])]
     sl = _timed_slice(cls, bench)
-    mops = sum(c.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0) for _, c in sl) / len(sl)
-    busy = sum(c.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) for _, c in sl)
-    active = sum(c.get("GRBM_GUI_ACTIVE", 0.0) for _, c in sl)
     alg = bench["roofline"]["flops_per_launch"]
-    print(json.dumps({dom: {"launches": len(sl), "mfma_flops_executed_per_launch": mops * 512.0,
-                            "algorithmic_flops_per_launch": alg, "executed_over_algorithmic": mops * 512.0 / alg,
-                            "mfma_busy_fraction": busy / (active * float(simds)) if active > 0 else None,
-                            "kernel_digest": bench["kernel_digest"], "workload": bench["config"]["workload"]}},
-                     indent=1))
+    out = {"launches": len(sl), "kernel_digest": bench["kernel_digest"], "workload": bench["config"]["workload"],
+           "algorithmic_flops_per_launch": alg}
+    if any("SQ_INSTS_VALU_MFMA_MOPS_F64" in c for _, c in sl):
+        mops = sum(c.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0) for _, c in sl) / len(sl)
+        out["mfma_flops_executed_per_launch"] = mops * 512.0
+        out["executed_over_algorithmic"] = mops * 512.0 / alg
+    if any("MfmaUtil" in c for _, c in sl):
+        # rocprofv3's derived metric: MFMA busy cycles / (GPU active cycles x SIMDs), in percent
+        out["mfma_util_percent_mean"] = sum(c["MfmaUtil"] for _, c in sl) / len(sl)
+    print(json.dumps({dom: out}, indent=1))
 
 
 if __name__ == "__main__":
@@ -169,8 +172,8 @@ if __name__ == "__main__":
         times(sys.argv[2], sys.argv[3])
     elif len(sys.argv) >= 6 and sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
-    elif len(sys.argv) >= 5 and sys.argv[1] == "mfma":
-        mfma(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif len(sys.argv) >= 4 and sys.argv[1] == "mfma":
+        mfma(sys.argv[2], sys.argv[3])
     else:
         print(__doc__)
         sys.exit(2)
