@@ -187,6 +187,27 @@ phiq_status phiq_plan_create(phiq_handle h, const phiq_kron_op* op, double t, in
 phiq_status phiq_plan_execute(phiq_plan plan, const double* v, int nrhs, double* out,
                               phiq_report* rep, hipStream_t stream);
 
+/* out = sum_{j=0}^{p} phi_j(-tA) b_j for the plan's (A, t, p): one linear
+ * combination of the phi-functions against p+1 different vectors (the
+ * remark on linear combinations after Algorithm 2, which gives the one-pass
+ * quadrature of sum_{j>=1} phi_j b_j without scaling).  Here it is combined
+ * with scaling and squaring: the node sums of all b_j feed p scaled
+ * intermediates that obey eq. squaring, so the cost is p chains per node,
+ * p per squaring step (one in the last) and one for b_0, instead of
+ * (m + l j + 1) chains per vector for separate phi-actions.
+ *   b    HOST array of p+1 DEVICE pointers, b[j] -> N doubles (tensor layout
+ *        as for phiq_action); NULL entries are zero vectors, at least one
+ *        entry must be non-NULL.  out DEVICE N doubles, must not overlap any
+ *        b[j].
+ *   Errors: PHIQ_ERR_INVALID_ARG (NULL plan/b/out, all b[j] NULL, overlap),
+ *   PHIQ_ERR_UNSUPPORTED (Clenshaw-Curtis or lower-precision plans, or
+ *   l (p-1) > 900, which would overflow the 2^{l (p-j)} factors).
+ * Accuracy: the plan's bound holds for each term, so the error is at most
+ * tol * sum_j ||b_j||_inf plus rounding.  Asynchronous on `stream`; uses the
+ * handle's workspace like phiq_plan_execute. */
+phiq_status phiq_plan_execute_combo(phiq_plan plan, const double* const* b, double* out,
+                                    hipStream_t stream);
+
 phiq_status phiq_plan_destroy(phiq_plan plan);
 
 /* One call: plan_create + plan_execute + plan_destroy.  v DEVICE N,
@@ -254,13 +275,16 @@ phiq_status phiq_batch_info(int nprob, const phiq_problem* probs, const phiq_opt
  * exponential integrators on the same phi-function actions) for
  *   u' = -A u + c1 u + c3 u^3,   A = sum_d A^d as for phiq_action,
  * nsteps steps of size tau, in place on u (DEVICE, N values).  Each step uses
- * e^{-tau A/2}, phi_1(-tau A/2), e^{-tau A} and phi_1..3(-tau A) (four plans
- * built once per call, tolerance tol relative to the vector's max norm);
- * the last one acts on three vectors in one plan execution.
+ * e^{-tau A/2}, phi_1(-tau A/2), e^{-tau A} and phi_1..3(-tau A), tolerance
+ * tol relative to the vector's max norm, plans built once per call.
+ * form 0: four plans; phi_0..p of every stage vector, the last plan on three
+ * vectors in one execution; work buffer 27 N doubles.  form 1: every stage
+ * is one phiq_plan_execute_combo (two plans, about 30% fewer mode products
+ * at p = 3); work buffer 11 N doubles.
  * use_graph = 1: the first step runs directly, the second is captured into a
  * hipGraph (on a stream of the call's own) and replayed for every later step.
- * The call allocates a work buffer of 27 N doubles and returns when the
- * steps have finished.  rep (nullable) gets the plans and how the steps ran. */
+ * Returns when the steps have finished.  rep (nullable) gets the plans and
+ * how the steps ran. */
 typedef struct {
   int steps_eager;          /* steps launched directly                      */
   int steps_graph;          /* steps replayed from the captured graph       */
@@ -270,7 +294,7 @@ typedef struct {
   int l_full, m_full;       /* plan of phi_0..3(-tau A)                     */
 } phiq_etd_report;
 phiq_status phiq_etdrk4(phiq_handle h, const phiq_kron_op* op, double tau, int nsteps,
-                        double c1, double c3, double tol, int use_graph, double* u,
+                        double c1, double c3, double tol, int use_graph, int form, double* u,
                         phiq_etd_report* rep, hipStream_t stream);
 
 /* The exponential Runge-Kutta methods of Section 5 (Table RK) on the paper's
@@ -280,13 +304,16 @@ phiq_status phiq_etdrk4(phiq_handle h, const phiq_kron_op* op, double tau, int n
  * u = x(1-x) y(1-y) e^t solves the PDE.  method 1 = exponential Euler,
  * 2 = RK2 with c2, 3 = RK3 with c2 and c3 = 2/3.  nsteps steps of T/nsteps
  * from t = 0, in place on u (DEVICE n^2 values, the initial condition on
- * entry).  phi-actions with tolerance tol and options opt (rule etc.); the
- * vectors of one stage go through one plan execution.  Allocates 13 n^2
- * doubles and returns when the steps have finished.  rep (nullable): the
+ * entry).  phi-actions with tolerance tol and options opt (rule etc.).
+ * form 0: the vectors of one stage go through one plan execution (phi_0..p
+ * of each, then combined); allocates 13 n^2 doubles.  form 1: every stage
+ * is one phiq_plan_execute_combo (Gauss rule and FP64 only, else
+ * PHIQ_ERR_UNSUPPORTED), about half the mode products; allocates 6 n^2
+ * doubles.  Returns when the steps have finished.  rep (nullable): the
  * full-step plan.  PHIQ_ERR_UNSUPPORTED for other dimensions. */
 phiq_status phiq_exprk(phiq_handle h, const phiq_kron_op* op, int method, double c2, int nsteps,
-                       double T, double tol, const phiq_options* opt, double* u, phiq_report* rep,
-                       hipStream_t stream);
+                       double T, double tol, const phiq_options* opt, int form, double* u,
+                       phiq_report* rep, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Learned (l, m) selector: a network 8 -> 64 -> 64 -> 2 with tanh hidden

@@ -37,6 +37,7 @@ EXPORTS = [
     "phiq_destroy",
     "phiq_plan_create",
     "phiq_plan_execute",
+    "phiq_plan_execute_combo",
     "phiq_plan_destroy",
     "phiq_action",
     "phiq_action_batched",
@@ -147,15 +148,16 @@ def load():
         "phiq_plan_create": (c_int, [c_void_p, P(KronOp), c_double, c_int, c_double, P(Options), P(c_void_p),
                                      P(Report), c_void_p]),
         "phiq_plan_execute": (c_int, [c_void_p, c_void_p, c_int, c_void_p, P(Report), c_void_p]),
+        "phiq_plan_execute_combo": (c_int, [c_void_p, P(c_void_p), c_void_p, c_void_p]),
         "phiq_plan_destroy": (c_int, [c_void_p]),
         "phiq_action": (c_int, [c_void_p, P(KronOp), c_double, c_int, c_void_p, c_double, P(Options), c_void_p,
                                 P(Report), c_void_p]),
         "phiq_action_batched": (c_int, [c_void_p, c_int, P(Problem), P(Options), c_void_p]),
         "phiq_batch_info": (c_int, [c_int, P(Problem), P(Options), P(BatchStats)]),
         "phiq_etdrk4": (c_int, [c_void_p, P(KronOp), c_double, c_int, c_double, c_double, c_double, c_int,
-                                c_void_p, P(EtdReport), c_void_p]),
-        "phiq_exprk": (c_int, [c_void_p, P(KronOp), c_int, c_double, c_int, c_double, c_double, P(Options), c_void_p,
-                               P(Report), c_void_p]),
+                                c_int, c_void_p, P(EtdReport), c_void_p]),
+        "phiq_exprk": (c_int, [c_void_p, P(KronOp), c_int, c_double, c_int, c_double, c_double, P(Options), c_int,
+                               c_void_p, P(Report), c_void_p]),
         "phiq_mlp_forward": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
         "phiq_mlp_grad": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, P(c_double), c_void_p]),
         "phiq_mlp_train": (c_int, [c_void_p, c_int, P(ctypes.c_float), P(ctypes.c_float), P(ctypes.c_float), c_int,

@@ -366,7 +366,8 @@ void ttm_work(const TtmArgs& a, int cls, double* flops, double* bytes) {
   double out = (double)a.nbatch * a.M * a.L;
   double extra = 0.0;
   if (cls == K_TTM_ACCUM) out = (double)a.np * a.M * a.L;
-  if (cls == K_TTM_SQUARE) extra = (double)a.nbatch * a.M * a.L;  // the y_j read once
+  if (cls == K_TTM_SQUARE) extra = (double)(a.nbatch + a.order0) * a.M * a.L;  // the y_j read once
+  if (a.yacc) extra += out;  // the previous output read back
   const double xb = a.x_f32 ? 4.0 : 8.0;
   const double ob = (a.o_f32 && cls == K_TTM_STORE) ? 4.0 : 8.0;
   *bytes = xb * xin + ob * out + 8.0 * (extra + (double)a.nbatch * a.M * a.K * (a.es == 0 ? 0.0 : 1.0));
@@ -1086,6 +1087,128 @@ phiq_status execute_gauss(phiq_plan P, const double* v, double* out, hipStream_t
   return phi0_chain(P, v, out, T0, T1, st);
 }
 
+// ---- linear combinations sum_j phi_j(Z) b_j, Z = -tA ------------------------
+// The remark after Algorithm 2 writes sum_{j>=1} phi_j(Z) b_j as one integral
+// of e^{(1-theta) Z} against the forcing g(theta) = sum_j theta^{j-1}/(j-1)! b_j.
+// Scaling and squaring for it: x(s) = sum_j s^j phi_j(sZ) b_j solves
+// x' = Z x + g(s), x(0) = 0, and x(2s) = e^{sZ} x(s) + (the same problem over
+// [0, s] with g shifted by s), so the doubling needs the solutions for the
+// forcings shifted by 0..p-1 places, X_i(s) = sum_k s^k phi_k(sZ) b_{k+i}:
+//   X_i(2s) = e^{sZ} X_i(s) + sum_{r=0}^{p-1-i} s^r/r! X_{i+r}(s).
+// With y_k = X_{p-k}(s) / s^k this is exactly eq. squaring (the modified
+// squaring of y_1..y_p), so the squaring kernels are reused unchanged; the
+// result is y_p at s = 1.  At s = 2^{-l} the node sum gives, per vector b_j,
+//   y_{p-j+k} += 2^{l(p-j)} sum_q w_q theta_q^{k-1}/(k-1)! e^{(1-theta_q) s Z} b_j,
+// k = 1..j: the usual node coefficients with a power-of-two factor.  Only y_p
+// is needed after the last step, so that step applies one chain.
+phiq_status execute_combo(phiq_plan P, const double* const* b, double* out, hipStream_t st) {
+  phiq_handle h = P->h;
+  const long long N = P->N;
+  int pe = 0;  // highest order with a vector
+  for (int j = 1; j <= P->p; ++j)
+    if (b[j]) pe = j;
+  const int nb = std::max(P->m + 1, P->p);
+  const size_t tbytes = (P->D > 1 ? (size_t)nb * N * sizeof(double) : 0);
+  const size_t ybytes = (size_t)std::max(1, P->p) * N * sizeof(double);
+  const size_t t1bytes = (P->D > 1 ? (size_t)N * sizeof(double) : 0);
+  const size_t need = 2 * align_up(tbytes) + 2 * align_up(ybytes) + 2 * align_up(t1bytes);
+  PHIQ_TRY(ensure(h, h->ws, std::max<size_t>(need, kAlign)));
+  char* wb = (char*)h->ws.p;
+  void* T0 = wb;
+  void* T1 = wb + align_up(tbytes);
+  double* Ya = (double*)(wb + 2 * align_up(tbytes));
+  double* Yb = (double*)(wb + 2 * align_up(tbytes) + align_up(ybytes));
+  void* T2 = wb + 2 * align_up(tbytes) + 2 * align_up(ybytes);
+  void* T3 = (char*)T2 + align_up(t1bytes);
+
+  if (pe == 0) return phi0_chain(P, b[0], out, T0, T1, st);
+  // phi_0 b_0 into out first: on the side stream when the squaring follows
+  const bool side = b[0] && P->has_join && P->l > 0;
+  bool have_out = false;
+  if (b[0]) {
+    if (side) {
+      PHIQ_TRY(phi0_start(P, b[0], out, T2, T3, st));
+    } else {
+      PHIQ_TRY(phi0_chain(P, b[0], out, T0, T1, st));
+    }
+    have_out = true;
+  }
+
+  double* E[PHIQ_MAX_DIM];
+  long long es[PHIQ_MAX_DIM];
+  for (int d = 0; d < P->D; ++d) {
+    E[d] = P->Enode[d];
+    es[d] = (long long)P->n[d] * P->n[d];
+  }
+  // node sums, highest order first so that it writes every y_k
+  for (int j = pe; j >= 1; --j) {
+    if (!b[j]) continue;
+    Front f;
+    PHIQ_TRY(chain_front(P, b[j], 0, E, es, P->m, T0, T1, st, &f));
+    if (P->l == 0) {  // only y_pe = sum_j phi_j(Z) b_j, straight into out
+      TtmArgs a = final_args(P, P->Enode[0], es[0], f, P->m);
+      a.coef = P->coef + (size_t)(j - 1) * P->ldcoef;
+      a.ldcoef = P->ldcoef;
+      a.np = 1;
+      a.Y = out;
+      a.ys = N;
+      a.yacc = have_out ? 1 : 0;
+      PHIQ_TRY(L_ttm(h, K_TTM_ACCUM, a, P->opt.precision, st, &P->twins));
+      have_out = true;
+      continue;
+    }
+    for (int k0 = 0; k0 < j; k0 += 4) {
+      TtmArgs a = final_args(P, P->Enode[0], es[0], f, P->m);
+      a.coef = P->coef + (size_t)k0 * P->ldcoef;
+      a.ldcoef = P->ldcoef;
+      a.np = std::min(4, j - k0);
+      a.cexp = P->l * (pe - j);
+      a.Y = Ya + (size_t)(pe - j + k0) * N;
+      a.ys = N;
+      a.yacc = (j == pe) ? 0 : 1;
+      PHIQ_TRY(L_ttm(h, K_TTM_ACCUM, a, P->opt.precision, st, &P->twins));
+    }
+  }
+  if (P->l == 0) return PHIQ_OK;
+
+  // l squaring steps on y_1..y_pe; the last one forms y_pe only, into out
+  PHIQ_TRY(wait_join(P, st));
+  double* cur = Ya;
+  for (int k = 0; k < P->l; ++k) {
+    double* Ek[PHIQ_MAX_DIM];
+    long long e0[PHIQ_MAX_DIM];
+    for (int d = 0; d < P->D; ++d) {
+      Ek[d] = P->Esq[d] + (size_t)k * P->n[d] * P->n[d];
+      e0[d] = 0;
+    }
+    const bool last = (k == P->l - 1);
+    Front f;
+    if (!last) {
+      PHIQ_TRY(chain_front(P, cur, N, Ek, e0, pe, T0, T1, st, &f));
+      double* dst = (cur == Ya) ? Yb : Ya;
+      TtmArgs a = final_args(P, Ek[0], 0, f, pe);
+      a.O = dst;
+      a.os = N;
+      a.Yprev = cur;
+      a.yps = N;
+      PHIQ_TRY(L_ttm(h, K_TTM_SQUARE, a, P->opt.precision, st, &P->twins));
+      cur = dst;
+      continue;
+    }
+    PHIQ_TRY(chain_front(P, cur + (size_t)(pe - 1) * N, 0, Ek, e0, 1, T0, T1, st, &f));
+    TtmArgs a = final_args(P, Ek[0], 0, f, 1);
+    a.O = out;
+    a.os = 0;
+    a.Yprev = cur;
+    a.yps = N;
+    a.order0 = pe - 1;
+    if (side) PHIQ_TRY(phi0_finish(P, st));
+    a.yacc = have_out ? 1 : 0;
+    PHIQ_TRY(L_ttm(h, K_TTM_SQUARE, a, P->opt.precision, st, &P->twins));
+  }
+  return PHIQ_OK;
+}
+
 // ---- adaptive Clenshaw-Curtis (Algorithm 2) --------------------------------
 // Level 0 holds the 7 nodes j = 0..6 of the rule with n = 3 (2n+1 points);
 // level k >= 1 holds the 3*2^k new (odd-j) nodes of the rule with n = 3*2^k.
@@ -1410,6 +1533,27 @@ phiq_status phiq_plan_execute(phiq_plan plan, const double* v, int nrhs, double*
     rep->workspace_bytes = plan->h->held();
   }
   return PHIQ_OK;
+}
+
+phiq_status phiq_plan_execute_combo(phiq_plan plan, const double* const* b, double* out, hipStream_t stream) {
+  if (!plan || !b || !out) return PHIQ_ERR_INVALID_ARG;
+  if (plan->opt.rule != PHIQ_RULE_GAUSS || plan->opt.precision != PHIQ_PREC_FP64) return PHIQ_ERR_UNSUPPORTED;
+  const long long N = plan->N;
+  const char* ob = (const char*)out;
+  const char* oe = ob + (size_t)N * sizeof(double);
+  int pe = -1;
+  for (int j = 0; j <= plan->p; ++j) {
+    if (!b[j]) continue;
+    pe = j;
+    const char* vb = (const char*)b[j];
+    const char* ve = vb + (size_t)N * sizeof(double);
+    if (vb < oe && ob < ve) return PHIQ_ERR_INVALID_ARG;  // out must not overlap an input
+  }
+  if (pe < 0) return PHIQ_ERR_INVALID_ARG;
+  // the node coefficients are scaled by up to 2^{l (pe - 1)}
+  if (pe > 1 && (long long)plan->l * (pe - 1) > 900) return PHIQ_ERR_UNSUPPORTED;
+  DeviceGuard g(plan->h->device);
+  return execute_combo(plan, b, out, stream);
 }
 
 phiq_status phiq_plan_destroy(phiq_plan plan) {

@@ -8,9 +8,12 @@
 //   c  = e^{hL/2} a + h/2 phi_1(hL/2) (2 F(b) - F(u))
 //   u <- e^{hL} u + h [f1 F(u) + 2 f2 (F(a) + F(b)) + f3 F(c)],
 //   f1 = phi_1 - 3 phi_2 + 4 phi_3, f2 = phi_2 - 2 phi_3, f3 = -phi_2 + 4 phi_3.
-// Four plans serve every step: phi_0 and phi_0..1 at h/2, phi_0 and
+// form 0: four plans serve every step: phi_0 and phi_0..1 at h/2, phi_0 and
 // phi_0..3 at h; the last runs on the three vectors F(u), F(a)+F(b), F(c)
 // in one execution.
+// form 1: every stage is one linear combination sum_j phi_j b_j
+// (phiq_plan_execute_combo): a, b and c with phi_0..1 at h/2, and the update
+// with b_0 = u and the phi_1..3 vectors regrouped from f1, f2, f3.
 #include <cmath>
 #include <cstring>
 
@@ -79,6 +82,42 @@ phiq_status etd_step(const EtdPlans& P, const EtdBufs& B, double* u, double tau,
   return PHIQ_OK;
 }
 
+// Buffers of the linear-combination form (N doubles each).
+struct EtdComboBufs {
+  double *fu, *fa, *fab, *s, *a, *b, *c, *b1, *b2, *b3, *unew;
+};
+constexpr int kEtdComboBufN = 11;
+
+phiq_status etd_step_combo(const EtdPlans& P, const EtdComboBufs& B, double* u, double tau, double c1, double c3,
+                           long long N, hipStream_t st) {
+  const double hh = 0.5 * tau;
+  PHIQ_HIP(launch_etd_cf_stage(u, B.fu, B.s, hh, N, c1, c3, st));
+  {
+    const double* b[2] = {u, B.s};  // a = e^{hL/2} u + phi_1(hL/2) (h/2) F(u)
+    PHIQ_TRY(phiq_plan_execute_combo(P.half1, b, B.a, st));
+  }
+  PHIQ_HIP(launch_etd_cf_stage(B.a, B.fa, B.s, hh, N, c1, c3, st));
+  {
+    const double* b[2] = {u, B.s};  // b = e^{hL/2} u + phi_1(hL/2) (h/2) F(a)
+    PHIQ_TRY(phiq_plan_execute_combo(P.half1, b, B.b, st));
+  }
+  PHIQ_HIP(launch_etd_cf_b(B.b, B.fu, B.fa, B.s, B.fab, hh, N, c1, c3, st));
+  {
+    const double* b[2] = {B.a, B.s};  // c = e^{hL/2} a + phi_1(hL/2) (h/2) (2 F(b) - F(u))
+    PHIQ_TRY(phiq_plan_execute_combo(P.half1, b, B.c, st));
+  }
+  PHIQ_HIP(launch_etd_cf_final(B.c, B.fu, B.fab, B.b1, B.b2, B.b3, tau, N, c1, c3, st));
+  {
+    const double* b[4] = {u, B.b1, B.b2, B.b3};
+    PHIQ_TRY(phiq_plan_execute_combo(P.full3, b, B.unew, st));
+  }
+  PHIQ_HIP(launch_etd_copy(B.unew, u, N, st));
+  return PHIQ_OK;
+}
+
+// Kronecker chains of one phiq_plan_execute_combo with every b_j set.
+int combo_chains(int p, int m, int l) { return 1 + p * m + (l > 0 ? p * (l - 1) + 1 : 0); }
+
 struct GraphState {
   hipStream_t cs = nullptr;
   hipGraph_t graph = nullptr;
@@ -98,9 +137,9 @@ struct GraphState {
 using namespace phiq;
 
 extern "C" phiq_status phiq_etdrk4(phiq_handle h, const phiq_kron_op* op, double tau, int nsteps, double c1,
-                                   double c3, double tol, int use_graph, double* u, phiq_etd_report* rep,
-                                   hipStream_t stream) {
-  if (!h || !u || nsteps < 0) return PHIQ_ERR_INVALID_ARG;
+                                   double c3, double tol, int use_graph, int form, double* u,
+                                   phiq_etd_report* rep, hipStream_t stream) {
+  if (!h || !u || nsteps < 0 || form < 0 || form > 1) return PHIQ_ERR_INVALID_ARG;
   PHIQ_TRY(validate_op(op));
   if (!std::isfinite(tau) || !std::isfinite(c1) || !std::isfinite(c3) || !std::isfinite(tol))
     return PHIQ_ERR_NONFINITE;
@@ -112,15 +151,17 @@ extern "C" phiq_status phiq_etdrk4(phiq_handle h, const phiq_kron_op* op, double
 
   EtdPlans P;
   phiq_report r0{}, r1{}, r2{}, r3{};
-  PHIQ_TRY(phiq_plan_create(h, op, 0.5 * tau, 0, tol, nullptr, &P.half0, &r0, stream));
+  if (form == 0) PHIQ_TRY(phiq_plan_create(h, op, 0.5 * tau, 0, tol, nullptr, &P.half0, &r0, stream));
   PHIQ_TRY(phiq_plan_create(h, op, 0.5 * tau, 1, tol, nullptr, &P.half1, &r1, stream));
-  PHIQ_TRY(phiq_plan_create(h, op, tau, 0, tol, nullptr, &P.full0, &r2, stream));
+  if (form == 0) PHIQ_TRY(phiq_plan_create(h, op, tau, 0, tol, nullptr, &P.full0, &r2, stream));
   PHIQ_TRY(phiq_plan_create(h, op, tau, 3, tol, nullptr, &P.full3, &r3, stream));
   PHIQ_HIP(hipStreamSynchronize(stream));
-  for (phiq_plan p : {P.half0, P.half1, P.full0, P.full3}) PHIQ_TRY(plan_settle(p));
+  for (phiq_plan p : {P.half0, P.half1, P.full0, P.full3})
+    if (p) PHIQ_TRY(plan_settle(p));
 
   double* mem = nullptr;
-  if (hipMalloc((void**)&mem, sizeof(double) * kEtdBufN * (size_t)N) != hipSuccess) {
+  const int nbuf = (form == 0) ? kEtdBufN : kEtdComboBufN;
+  if (hipMalloc((void**)&mem, sizeof(double) * nbuf * (size_t)N) != hipSuccess) {
     (void)hipGetLastError();
     return PHIQ_ERR_OOM;
   }
@@ -131,27 +172,36 @@ extern "C" phiq_status phiq_etdrk4(phiq_handle h, const phiq_kron_op* op, double
       (void)hipFree(p);
     }
   } free_mem{mem};
-  EtdBufs B;
+  EtdBufs B{};
+  EtdComboBufs BC{};
   double* q = mem;
   auto take = [&](long long k) {
     double* r = q;
     q += k * N;
     return r;
   };
-  B.in2 = take(3);
-  B.e_u = take(1);
-  B.p1u = take(2);
-  B.a = take(1);
-  B.fa = take(1);
-  B.p1a = take(2);
-  B.mix = take(1);
-  B.e_a = take(1);
-  B.p1m = take(2);
-  B.e_full = take(1);
-  B.g = take(12);
+  if (form == 0) {
+    B.in2 = take(3);
+    B.e_u = take(1);
+    B.p1u = take(2);
+    B.a = take(1);
+    B.fa = take(1);
+    B.p1a = take(2);
+    B.mix = take(1);
+    B.e_a = take(1);
+    B.p1m = take(2);
+    B.e_full = take(1);
+    B.g = take(12);
+  } else {
+    for (double** b : {&BC.fu, &BC.fa, &BC.fab, &BC.s, &BC.a, &BC.b, &BC.c, &BC.b1, &BC.b2, &BC.b3, &BC.unew})
+      *b = take(1);
+  }
+  auto step = [&](hipStream_t s) {
+    return form == 0 ? etd_step(P, B, u, tau, c1, c3, N, s) : etd_step_combo(P, BC, u, tau, c1, c3, N, s);
+  };
 
   // first step eagerly (it also sizes the handle's workspace for all plans)
-  PHIQ_TRY(etd_step(P, B, u, tau, c1, c3, N, stream));
+  PHIQ_TRY(step(stream));
   int eager = 1, replay = 0;
   size_t nodes = 0;
   const bool graph = use_graph && nsteps > 1 && !plan_profiling(P.full3);
@@ -162,7 +212,7 @@ extern "C" phiq_status phiq_etdrk4(phiq_handle h, const phiq_kron_op* op, double
     PHIQ_HIP(hipEventRecord(G.ev, stream));
     PHIQ_HIP(hipStreamWaitEvent(G.cs, G.ev, 0));
     PHIQ_HIP(hipStreamBeginCapture(G.cs, hipStreamCaptureModeThreadLocal));
-    const phiq_status sc = etd_step(P, B, u, tau, c1, c3, N, G.cs);
+    const phiq_status sc = step(G.cs);
     const hipError_t ec = hipStreamEndCapture(G.cs, &G.graph);
     if (sc != PHIQ_OK) return sc;
     PHIQ_HIP(ec);
@@ -177,7 +227,7 @@ extern "C" phiq_status phiq_etdrk4(phiq_handle h, const phiq_kron_op* op, double
     PHIQ_HIP(hipStreamSynchronize(G.cs));
   } else {
     for (int s = 1; s < nsteps; ++s) {
-      PHIQ_TRY(etd_step(P, B, u, tau, c1, c3, N, stream));
+      PHIQ_TRY(step(stream));
       ++eager;
     }
   }
@@ -190,8 +240,10 @@ extern "C" phiq_status phiq_etdrk4(phiq_handle h, const phiq_kron_op* op, double
     rep->m_half = r1.m;
     rep->l_full = r3.l;
     rep->m_full = r3.m;
-    // chains per step: 2 phi_0 at h/2, 3 phi_0..1 at h/2, 1 phi_0 at h, 3 x phi_0..3 at h
-    rep->ttm_chains_per_step = 2 + 3 * (r1.m + r1.l + 1) + 1 + 3 * (r3.m + 3 * r3.l + 1);
+    // form 0: 2 phi_0 at h/2, 3 phi_0..1 at h/2, 1 phi_0 at h, 3 x phi_0..3 at h;
+    // form 1: three combinations at h/2 (p = 1) and one at h (p = 3)
+    rep->ttm_chains_per_step = (form == 0) ? 2 + 3 * (r1.m + r1.l + 1) + 1 + 3 * (r3.m + 3 * r3.l + 1)
+                                           : 3 * combo_chains(1, r1.m, r1.l) + combo_chains(3, r3.m, r3.l);
   }
   return PHIQ_OK;
 }

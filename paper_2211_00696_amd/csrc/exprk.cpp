@@ -10,9 +10,13 @@
 //   RK3:    U_2 as RK2;  U_3 = e^{-c3 tau A} u + (2/3) tau phi_1(-c3 tau A) g_1
 //                              + 4/(9 c2) tau phi_2(-c3 tau A)(g_2 - g_1)
 //           u+ = e^{-tau A} u + tau phi_1(-tau A) g_1 + (3/2) tau phi_2(-tau A)(g_3 - g_1)
-// The vectors of one stage ([u, g_1, ...]) go through one plan execution.
+// form 0: the vectors of one stage ([u, g_1, ...]) go through one plan
+// execution and the stage is combined from their phi_0..phi_p.
+// form 1: every stage is one linear combination sum_j phi_j(Z) b_j
+// (phiq_plan_execute_combo) with b_0 = u and the scaled sources as b_1, b_2.
 #include <cmath>
 #include <cstring>
+#include <utility>
 
 #include <hip/hip_runtime_api.h>
 
@@ -45,14 +49,90 @@ struct Plans {
 
 }  // namespace
 
+namespace {
+
+// form 1: stages as linear combinations.  Buffers G1, G2 (sources), B1, B2
+// (scaled combination vectors), U (stage value), W (next u).
+phiq_status exprk_combo(const Plans& P, int method, double c2, int nsteps, double tau, int n, double* u,
+                        hipStream_t st) {
+  const long long N = (long long)n * n;
+  const double c3 = 2.0 / 3.0;
+  double* mem = nullptr;
+  if (hipMalloc((void**)&mem, sizeof(double) * 6 * (size_t)N) != hipSuccess) {
+    (void)hipGetLastError();
+    return PHIQ_ERR_OOM;
+  }
+  struct Free {
+    double* p;
+    ~Free() {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(p);
+    }
+  } fr{mem};
+  double* G1 = mem;
+  double* G2 = mem + N;
+  double* B1 = mem + 2 * N;
+  double* B2 = mem + 3 * N;
+  double* U = mem + 4 * N;
+  double* cur = u;
+  double* nxt = mem + 5 * N;
+  for (int s = 0; s < nsteps; ++s) {
+    const double t = s * tau;
+    PHIQ_HIP(launch_exprk_stage(cur, nullptr, 0.0, nullptr, 0.0, n, t, G1, nullptr, st));
+    if (method == 1) {  // u+ = e^{-tau A} u + phi_1(-tau A) tau g_1
+      PHIQ_HIP(launch_exprk_axpby(G1, tau, nullptr, 0.0, B1, N, st));
+      const double* b[2] = {cur, B1};
+      PHIQ_TRY(phiq_plan_execute_combo(P.p[2], b, nxt, st));
+      std::swap(cur, nxt);
+      continue;
+    }
+    {  // U_2 = e^{-c2 tau A} u + phi_1(-c2 tau A) c2 tau g_1
+      PHIQ_HIP(launch_exprk_axpby(G1, c2 * tau, nullptr, 0.0, B1, N, st));
+      const double* b[2] = {cur, B1};
+      PHIQ_TRY(phiq_plan_execute_combo(P.p[0], b, U, st));
+    }
+    PHIQ_HIP(launch_exprk_stage(U, nullptr, 0.0, nullptr, 0.0, n, t + c2 * tau, G2, nullptr, st));
+    if (method == 2) {  // b_1 = tau ((1 - 1/(2 c2)) g_1 + g_2/(2 c2))
+      const double b2 = 1.0 / (2.0 * c2);
+      PHIQ_HIP(launch_exprk_axpby(G1, tau * (1.0 - b2), G2, tau * b2, B1, N, st));
+      const double* b[2] = {cur, B1};
+      PHIQ_TRY(phiq_plan_execute_combo(P.p[2], b, nxt, st));
+      std::swap(cur, nxt);
+      continue;
+    }
+    {  // U_3 = e^{-c3 tau A} u + phi_1 (2/3) tau g_1 + phi_2 4/(9 c2) tau (g_2 - g_1), at -c3 tau A
+      const double w = 4.0 / (9.0 * c2) * tau;
+      PHIQ_HIP(launch_exprk_axpby(G1, (2.0 / 3.0) * tau, nullptr, 0.0, B1, N, st));
+      PHIQ_HIP(launch_exprk_axpby(G2, w, G1, -w, B2, N, st));
+      const double* b[3] = {cur, B1, B2};
+      PHIQ_TRY(phiq_plan_execute_combo(P.p[1], b, U, st));
+    }
+    PHIQ_HIP(launch_exprk_stage(U, nullptr, 0.0, nullptr, 0.0, n, t + c3 * tau, G2, nullptr, st));  // g_3
+    {  // u+ = e^{-tau A} u + phi_1 tau g_1 + phi_2 (3/2) tau (g_3 - g_1)
+      PHIQ_HIP(launch_exprk_axpby(G1, tau, nullptr, 0.0, B1, N, st));
+      PHIQ_HIP(launch_exprk_axpby(G2, 1.5 * tau, G1, -1.5 * tau, B2, N, st));
+      const double* b[3] = {cur, B1, B2};
+      PHIQ_TRY(phiq_plan_execute_combo(P.p[2], b, nxt, st));
+      std::swap(cur, nxt);
+    }
+  }
+  if (cur != u) PHIQ_HIP(launch_exprk_axpby(cur, 1.0, nullptr, 0.0, u, N, st));
+  PHIQ_HIP(hipStreamSynchronize(st));
+  return PHIQ_OK;
+}
+
+}  // namespace
+
 extern "C" phiq_status phiq_exprk(phiq_handle h, const phiq_kron_op* op, int method, double c2, int nsteps, double T,
-                                  double tol, const phiq_options* opt, double* u, phiq_report* rep,
+                                  double tol, const phiq_options* opt, int form, double* u, phiq_report* rep,
                                   hipStream_t st) {
-  if (!h || !u || nsteps < 1 || method < 1 || method > 3) return PHIQ_ERR_INVALID_ARG;
+  if (!h || !u || nsteps < 1 || method < 1 || method > 3 || form < 0 || form > 1) return PHIQ_ERR_INVALID_ARG;
   PHIQ_TRY(validate_op(op));
   if (op->dim != 2 || op->n[0] != op->n[1]) return PHIQ_ERR_UNSUPPORTED;  // the source lives on the unit square
   if (!std::isfinite(c2) || !std::isfinite(T) || !std::isfinite(tol)) return PHIQ_ERR_NONFINITE;
   if (!(T > 0) || !(tol > 0) || (method > 1 && !(c2 > 0 && c2 <= 1))) return PHIQ_ERR_INVALID_ARG;
+  if (form == 1 && opt && (opt->rule != PHIQ_RULE_GAUSS || opt->precision != PHIQ_PREC_FP64))
+    return PHIQ_ERR_UNSUPPORTED;  // linear combinations: Gauss rule, FP64 plans
   const int n = op->n[0];
   const long long N = (long long)n * n;
   const double tau = T / nsteps, c3 = 2.0 / 3.0;
@@ -65,6 +145,11 @@ extern "C" phiq_status phiq_exprk(phiq_handle h, const phiq_kron_op* op, int met
   if (method >= 2) PHIQ_TRY(phiq_plan_create(h, op, c2 * tau, 1, tol, opt, &P.p[0], &r, st));
   if (method == 3) PHIQ_TRY(phiq_plan_create(h, op, c3 * tau, 2, tol, opt, &P.p[1], &r, st));
   PHIQ_TRY(phiq_plan_create(h, op, tau, pfull, tol, opt, &P.p[2], &r, st));
+  if (form == 1) {
+    PHIQ_TRY(exprk_combo(P, method, c2, nsteps, tau, n, u, st));
+    if (rep) *rep = r;
+    return PHIQ_OK;
+  }
 
   // R: the stage's vectors [u, g_1, w] (3 N); O: their phi_0..phi_2 (9 N); G2: g_2
   double* mem = nullptr;

@@ -44,6 +44,15 @@ __global__ void exprk_comb_kernel(const double* x, const double* a, double sa, c
   }
 }
 
+// out = sa a + sb b (b may be null; out may alias a or b)
+__global__ void exprk_axpby_kernel(const double* a, double sa, const double* b, double sb, double* out, long long N) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N; i += (long long)gridDim.x * blockDim.x) {
+    double v = sa * a[i];
+    if (b) v += sb * b[i];
+    out[i] = v;
+  }
+}
+
 inline int grid_for(long long n) {
   const long long b = (n + 255) / 256;
   return (int)(b < 2048 ? (b > 0 ? b : 1) : 2048);
@@ -62,6 +71,12 @@ int launch_exprk_stage(const double* e, const double* a, double sa, const double
 int launch_exprk_comb(const double* x, const double* a, double sa, const double* b, double sb, double* out,
                       long long N, void* stream) {
   hipLaunchKernelGGL(exprk_comb_kernel, dim3(grid_for(N)), dim3(256), 0, (hipStream_t)stream, x, a, sa, b, sb, out, N);
+  return hipGetLastError();
+}
+
+int launch_exprk_axpby(const double* a, double sa, const double* b, double sb, double* out, long long N,
+                       void* stream) {
+  hipLaunchKernelGGL(exprk_axpby_kernel, dim3(grid_for(N)), dim3(256), 0, (hipStream_t)stream, a, sa, b, sb, out, N);
   return hipGetLastError();
 }
 

@@ -94,7 +94,7 @@ __global__ __launch_bounds__(C::NT, C::MINW) void ttm_accum_kernel(TtmArgs a) {
     tile_nt_db<C, VEC>(a.E + b * a.es, (const double*)a.X + b * a.xs, a.M, a.K, a.L, m0, n0, smem, acc);
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
-      const double w = a.coef[q * a.ldcoef + b];
+      const double w = ldexp(a.coef[q * a.ldcoef + b], a.cexp);
 #pragma unroll
       for (int i = 0; i < C::TM; ++i)
 #pragma unroll
@@ -112,14 +112,18 @@ __global__ __launch_bounds__(C::NT, C::MINW) void ttm_accum_kernel(TtmArgs a) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int row = m0 + acc_row<C>(i, e);
-          if (row < a.M && col < a.L) Y[(long long)row * a.L + col] = y[q][i][j][e];
+          if (row < a.M && col < a.L) {
+            const long long idx = (long long)row * a.L + col;
+            Y[idx] = a.yacc ? Y[idx] + y[q][i][j][e] : y[q][i][j][e];
+          }
         }
       }
   }
 }
 
 // Modified squaring fused into the last mode product (eq. squaring):
-// batch b is order i = b+1, out = 2^{-i} (E y_i + sum_{j=1}^{i} y_j/(i-j)!).
+// batch b is order i = b+1+order0, out = 2^{-i} (E y_i + sum_{j=1}^{i} y_j/(i-j)!),
+// added to out when yacc is set.
 template <class C, bool VEC>
 __global__ __launch_bounds__(C::NT, C::MINW) void ttm_square_kernel(TtmArgs a) {
   __shared__ double smem[2 * (C::BM + C::BN) * C::LDK];
@@ -128,7 +132,7 @@ __global__ __launch_bounds__(C::NT, C::MINW) void ttm_square_kernel(TtmArgs a) {
   d4 acc[C::TM][C::TN];
   zero_acc<C>(acc);
   tile_nt_db<C, VEC>(a.E + b * a.es, (const double*)a.X + b * a.xs, a.M, a.K, a.L, m0, n0, smem, acc);
-  const int order = b + 1;
+  const int order = b + 1 + a.order0;
   const double scale = ldexp(1.0, -order);
   double* O = (double*)a.O + b * a.os;
 #pragma unroll
@@ -143,7 +147,7 @@ __global__ __launch_bounds__(C::NT, C::MINW) void ttm_square_kernel(TtmArgs a) {
           const long long idx = (long long)row * a.L + col;
           double s = acc[i][j][e];
           for (int jj = 1; jj <= order; ++jj) s += a.Yprev[(jj - 1) * a.yps + idx] * a.ifact[order - jj];
-          O[idx] = scale * s;
+          O[idx] = a.yacc ? O[idx] + scale * s : scale * s;
         }
       }
     }
@@ -472,6 +476,8 @@ int square_all_cfg(const TtmArgs& a, hipStream_t st) {
 int launch_ttm_square(const TtmArgs& a, phiq_precision prec, void* stream, int cfg) {
   if (prec != PHIQ_PREC_FP64) return launch_ttm_square_lowp(a, prec, stream);
   hipStream_t st = (hipStream_t)stream;
+  // an order offset or an accumulating store needs the per-order kernel
+  if ((a.order0 != 0 || a.yacc) && (cfg < 0 || cfg >= 7)) cfg = a.M >= 128 ? 5 : 6;
   if (cfg < 0) cfg = default_cfg(2, a.M, a.nbatch);
   // shapes 7.. : all orders per block (p <= 4)
   if (cfg >= 7) {

@@ -80,6 +80,9 @@ int launch_exprk_stage(const double* e, const double* a, double sa, const double
 // out = x + sa a + sb b (a, b nullable); out may alias x or a
 int launch_exprk_comb(const double* x, const double* a, double sa, const double* b, double sb, double* out,
                       long long N, void* stream);
+// out = sa a + sb b (b may be null)
+int launch_exprk_axpby(const double* a, double sa, const double* b, double sb, double* out, long long N,
+                       void* stream);
 
 // ---- etd.hip: elementwise steps of the ETD-RK4 integrator ----------------
 // F(x) = c1 x + c3 x^3.  All arrays DEVICE, n elements.
@@ -92,6 +95,16 @@ int launch_etd_stage_b(const double* x, const double* y, double s, const double*
                        double* sum, long long n, double c1, double c3, void* stream);
 // u = e + h [(g1_1 - 3 g1_2 + 4 g1_3) + 2 (g2_2 - 2 g2_3) + (-g3_2 + 4 g3_3)], gr_k = g + (4 r + k) n
 int launch_etd_final(const double* e, const double* g, double h, double* u, long long n, void* stream);
+// linear-combination form: fx = F(x), s = hs fx
+int launch_etd_cf_stage(const double* x, double* fx, double* s, double hs, long long n, double c1, double c3,
+                        void* stream);
+// s = hs (2 F(b) - fu), fab = fa + F(b)
+int launch_etd_cf_b(const double* b, const double* fu, const double* fa, double* s, double* fab, double hs,
+                    long long n, double c1, double c3, void* stream);
+// the phi_1..3 vectors of the final update from F(u), F(a) + F(b) and c
+int launch_etd_cf_final(const double* c, const double* fu, const double* fab, double* b1, double* b2, double* b3,
+                        double h, long long n, double c1, double c3, void* stream);
+int launch_etd_copy(const double* x, double* y, long long n, void* stream);
 
 // ---- kernels.hip: device job descriptors ---------------------------------
 // C = A * B, all n x n row-major FP64 (A, B, C distinct).
@@ -146,16 +159,20 @@ struct TtmArgs {
   long long os;
   int x_f32, o_f32;
   int M, K, L, nbatch;
-  // node-sum epilogue: Y + j*ys = sum_b coef[j * ldcoef + b] * C_b, j < np
+  // node-sum epilogue: Y + j*ys = sum_b 2^cexp coef[j * ldcoef + b] * C_b, j < np
   const double* coef;
   int ldcoef;
   int np;
+  int cexp;
   double* Y;
   long long ys;
-  // squaring epilogue: batch b is order i = b + 1;
+  // squaring epilogue: batch b is order i = b + 1 + order0;
   // O_b = 2^{-i} (C_b + sum_{j=1}^{i} (Yprev + (j-1)*yps)/(i-j)!)
   const double* Yprev;
   long long yps;
+  int order0;
+  // node sum and per-order squaring (FP64): 1 = add the result to Y / O
+  int yacc;
   double ifact[PHIQ_MAX_P + 1];  // ifact[k] = 1/k!
 };
 

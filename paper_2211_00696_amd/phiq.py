@@ -195,6 +195,32 @@ class Plan:
                                      _stream_ptr(stream)), "phiq_plan_execute")
         return out, rep.as_dict()
 
+    def execute_combo(self, bs, out=None, stream=None):
+        """out = sum_j phi_j(-tA) bs[j], j = 0..p; bs holds p+1 entries, each a
+        float64 CUDA tensor of N values or None (a zero vector)."""
+        import torch
+
+        lib = L.load()
+        if len(bs) != self.p + 1:
+            raise ValueError("bs must hold p+1 entries")
+        arr = (c_void_p * (self.p + 1))()
+        dev = None
+        for j, b in enumerate(bs):
+            if b is None:
+                arr[j] = None
+                continue
+            if b.numel() != self.N:
+                raise ValueError("every b_j must hold N values")
+            arr[j] = _dev_ptr(b, "b[%d]" % j).value
+            dev = b.device
+        if out is None:
+            if dev is None:
+                raise ValueError("at least one b_j is needed")
+            out = torch.empty(self.N, dtype=torch.float64, device=dev)
+        _check(lib.phiq_plan_execute_combo(self._ptr, arr, _dev_ptr(out, "out"), _stream_ptr(stream)),
+               "phiq_plan_execute_combo")
+        return out
+
     def close(self):
         if self._ptr:
             L.load().phiq_plan_destroy(self._ptr)
@@ -318,21 +344,32 @@ class Handle:
         _check(lib.phiq_action_batched(self._h, nprob, arr, byref(o), _stream_ptr(stream)), "phiq_action_batched")
         return outs, [r.as_dict() for r in reps]
 
-    def etdrk4(self, mats, tau, nsteps, u, c1=1.0, c3=-1.0, tol=1e-8, graph=True, stream=None):
+    def etdrk4(self, mats, tau, nsteps, u, c1=1.0, c3=-1.0, tol=1e-8, graph=True, form="combo", stream=None):
         """ETD-RK4 steps of u' = -A u + c1 u + c3 u^3 in place on the device tensor u (phiq_etdrk4).
-        Returns the report dict."""
+        form: "combo" (one linear combination per stage) or "separate".  Returns the report dict."""
         lib = L.load()
+        if form not in ("separate", "combo"):
+            raise ValueError("form must be 'separate' or 'combo'")
         op = _Op(mats)
         if u.numel() != op.N:
             raise ValueError("u has %d entries, the operator needs %d" % (u.numel(), op.N))
         rep = L.EtdReport()
         _check(lib.phiq_etdrk4(self._h, byref(op.op), float(tau), int(nsteps), float(c1), float(c3), float(tol),
-                               int(bool(graph)), _dev_ptr(u, "u"), byref(rep), _stream_ptr(stream)), "phiq_etdrk4")
+                               int(bool(graph)), 1 if form == "combo" else 0, _dev_ptr(u, "u"), byref(rep),
+                               _stream_ptr(stream)), "phiq_etdrk4")
         return rep.as_dict()
 
-    def exprk(self, mats, method, nsteps, u, T=1.0, c2=None, tol=1e-8, stream=None, **opts):
-        """Section 5's exponential Euler (1), RK2 (2) or RK3 (3) on Problem 3, in place on u; report dict."""
+    def exprk(self, mats, method, nsteps, u, T=1.0, c2=None, tol=1e-8, form="auto", stream=None, **opts):
+        """Section 5's exponential Euler (1), RK2 (2) or RK3 (3) on Problem 3, in place on u; report dict.
+
+        form: "separate" (phi_0..p of every stage vector), "combo" (one linear
+        combination per stage) or "auto" (combo for Gauss FP64 options)."""
         lib = L.load()
+        if form == "auto":
+            combo = opts.get("rule", "gauss") == "gauss" and opts.get("precision", "fp64") == "fp64"
+            form = "combo" if combo else "separate"
+        if form not in ("separate", "combo"):
+            raise ValueError("form must be 'separate', 'combo' or 'auto'")
         op = _Op(mats)
         if u.numel() != op.N:
             raise ValueError("u has %d entries, the operator needs %d" % (u.numel(), op.N))
@@ -340,7 +377,8 @@ class Handle:
             c2 = 0.5 if method == 2 else 1.0 / 3.0
         rep = L.Report()
         _check(lib.phiq_exprk(self._h, byref(op.op), int(method), float(c2), int(nsteps), float(T), float(tol),
-                              byref(options(**opts)), _dev_ptr(u, "u"), byref(rep), _stream_ptr(stream)), "phiq_exprk")
+                              byref(options(**opts)), 1 if form == "combo" else 0, _dev_ptr(u, "u"), byref(rep),
+                              _stream_ptr(stream)), "phiq_exprk")
         return rep.as_dict()
 
     # ---- the learned selector's network (FP32) ----

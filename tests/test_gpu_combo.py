@@ -1,0 +1,188 @@
+"""phiq_plan_execute_combo: sum_j phi_j(-tA) b_j (the remark on linear
+combinations after Algorithm 2, with scaling and squaring) against the
+oracle, through the C ABI.
+
+Bars:
+* against the definition (dense augmented exponential, tiny grids) with plans
+  at tol 1e-12: relative max-norm error below 1e-10;
+* against the oracle's quadrature-and-squaring form with the same (l, m) on
+  grids spanning several tiles with ragged tails: below 1e-12 (the same
+  approximation, summed in another order);
+* at the 3D n = 128 size (p = 3): against the sum of phi_j(-tA) b_j from
+  separate plan executions (themselves parity-tested against the oracle at
+  that size), below 1e-12;
+* the exponential Runge-Kutta stages as combinations agree with the
+  per-vector form to 1e-12 and with the oracle's Table RK schemes to 1e-10.
+"""
+import numpy as np
+import pytest
+
+from oracle import exprk as R
+from oracle import phi_combo as C
+from paper_2211_00696_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def h():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2211_00696_amd import phiq
+
+    hd = phiq.Handle(0)
+    yield hd
+    hd.close()
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def ops(sizes, seed=7):
+    rng = np.random.default_rng(seed)
+    mats = []
+    for n in sizes:
+        a = float(np.exp(rng.uniform(np.log(0.1), np.log(10))))
+        b = float(rng.uniform(0, 50))
+        mats.append(I.adv_diff_1d(n, a, b))
+    return mats
+
+
+def draw(rng, p, N, none=()):
+    return [None if j in none else rng.standard_normal(N) for j in range(p + 1)]
+
+
+def run(h, mats, t, bs, tol=1e-12, **opts):
+    plan = h.plan(mats, t, len(bs) - 1, tol=tol, **opts)
+    dev = [None if b is None else torch.from_numpy(b).cuda() for b in bs]
+    out = plan.execute_combo(dev)
+    torch.cuda.synchronize()
+    rep = plan.report
+    plan.close()
+    return out.cpu().numpy(), rep
+
+
+@pytest.mark.parametrize("sizes", [[9, 11], [5, 6, 7]])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 6])
+@pytest.mark.parametrize("l", [None, 0, 1, 3])
+def test_combo_vs_definition(h, sizes, p, l):
+    mats = ops(sizes)
+    N = int(np.prod(sizes))
+    t = 0.02 if l is None else 4e-3
+    rng = np.random.default_rng(100 * p + (l or 0))
+    bs = draw(rng, p, N)
+    print("combo vs definition", sizes, p, l, flush=True)
+    kw = {} if l is None else dict(l=l, m=18)
+    got, rep = run(h, mats, t, bs, **kw)
+    ref = C.combo_exact(mats, t, bs)
+    e = rel(got, ref)
+    print(rep["l"], rep["m"], e, flush=True)
+    assert e < 1e-10, e
+
+
+@pytest.mark.parametrize("sizes,p,l,m", [([37, 50, 29], 3, 4, 10), ([130, 67], 4, 5, 11), ([70, 65, 33], 2, 2, 9),
+                                         ([200, 150], 3, 6, 12)])
+def test_combo_vs_oracle_quadrature(h, sizes, p, l, m):
+    mats = ops(sizes, seed=3)
+    N = int(np.prod(sizes))
+    rng = np.random.default_rng(5)
+    bs = draw(rng, p, N)
+    t = 1e-3
+    print("combo vs oracle quadrature", sizes, p, l, m, flush=True)
+    got, rep = run(h, mats, t, bs, l=l, m=m)
+    assert (rep["l"], rep["m"]) == (l, m)
+    ref = C.combo_quad(mats, t, bs, l=l, m=m)
+    e = rel(got, ref)
+    print(e, flush=True)
+    assert e < 1e-12, e
+
+
+@pytest.mark.parametrize("none", [(0,), (1,), (3,), (1, 2), (0, 1, 2), (1, 2, 3), (0, 2)])
+def test_combo_zero_entries(h, none):
+    sizes = [12, 17, 9]
+    mats = ops(sizes, seed=9)
+    N = int(np.prod(sizes))
+    rng = np.random.default_rng(len(none))
+    bs = draw(rng, 3, N, none=none)
+    print("combo with None at", none, flush=True)
+    got, rep = run(h, mats, 0.01, bs)
+    ref = C.combo_exact(mats, 0.01, bs)
+    e = rel(got, ref)
+    print(rep["l"], rep["m"], e, flush=True)
+    assert e < 1e-10, e
+
+
+def test_combo_single_vector_equals_execute(h):
+    sizes = [33, 40, 21]
+    mats = ops(sizes, seed=4)
+    N = int(np.prod(sizes))
+    v = torch.from_numpy(np.random.default_rng(8).standard_normal(N)).cuda()
+    plan = h.plan(mats, 0.003, 3, tol=1e-10)
+    full, _ = plan.execute(v)
+    for j in range(4):
+        bs = [None] * 4
+        bs[j] = v
+        got = plan.execute_combo(bs)
+        e = float((got - full[0, j]).abs().max() / full[0, j].abs().max())
+        print("slot", j, e, flush=True)
+        assert e < 1e-13, (j, e)
+    plan.close()
+
+
+def test_combo_errors(h):
+    from paper_2211_00696_amd import phiq
+
+    sizes = [8, 8]
+    mats = ops(sizes)
+    N = 64
+    b = torch.randn(N, dtype=torch.float64, device="cuda")
+    plan = h.plan(mats, 0.01, 2)
+    with pytest.raises(phiq.PhiqError, match="INVALID_ARG"):
+        plan.execute_combo([None, None, None], out=torch.empty_like(b))
+    with pytest.raises(phiq.PhiqError, match="INVALID_ARG"):
+        plan.execute_combo([b, b, None], out=b)
+    plan.close()
+    for kw in (dict(rule="cc"), dict(precision="fp32")):
+        plan = h.plan(mats, 0.01, 2, **kw)
+        with pytest.raises(phiq.PhiqError, match="UNSUPPORTED"):
+            plan.execute_combo([b, b, b])
+        plan.close()
+
+
+def test_combo_full_size_n128(h):
+    """3D n = 128, p = 3 at the advection-diffusion workload's plan."""
+    pr = I.problem("advdiff3d", seed=0, n=128)
+    mats, t = pr["mats"], pr["t"]
+    N = 128 ** 3
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1)
+    bs = [torch.randn(N, dtype=torch.float64, device="cuda", generator=g) for _ in range(4)]
+    plan = h.plan(mats, t, 3, tol=1e-8)
+    print("full size combo, plan", plan.report["l"], plan.report["m"], flush=True)
+    got = plan.execute_combo(bs)
+    ref = torch.zeros(N, dtype=torch.float64, device="cuda")
+    for j, b in enumerate(bs):
+        out, _ = plan.execute(b)
+        ref += out[0, j]
+    torch.cuda.synchronize()
+    e = float((got - ref).abs().max() / ref.abs().max())
+    print(e, flush=True)
+    plan.close()
+    assert e < 1e-12, e
+
+
+@pytest.mark.parametrize("method", [1, 2, 3])
+def test_exprk_forms_agree(h, method):
+    n = 127
+    mats = [I.fd_laplacian(n), I.fd_laplacian(n)]
+    u0 = torch.from_numpy(R.exact(n, 0.0)).cuda()
+    ua = u0.clone()
+    ub = u0.clone()
+    print("exprk forms", method, flush=True)
+    h.exprk(mats, method, 8, ua, tol=1e-12, form="separate")
+    h.exprk(mats, method, 8, ub, tol=1e-12, form="combo")
+    e = float((ua - ub).abs().max() / ua.abs().max())
+    print(e, flush=True)
+    assert e < 1e-12, e

@@ -42,7 +42,8 @@ def laplace(n, dim):
 
 @pytest.mark.parametrize("case", ["laplace2d_n10", "advdiff3d_n7"])
 @pytest.mark.parametrize("steps", [3, 6])
-def test_etd_vs_oracle_small(h, case, steps):
+@pytest.mark.parametrize("form", ["separate", "combo"])
+def test_etd_vs_oracle_small(h, case, steps, form):
     rng = np.random.default_rng(5)
     if case == "laplace2d_n10":
         mats = [0.1 * m for m in laplace(10, 2)]
@@ -52,25 +53,26 @@ def test_etd_vs_oracle_small(h, case, steps):
     N = int(np.prod([m.shape[0] for m in mats]))
     u0 = rng.uniform(-1.0, 1.0, N)
     tau = 0.02
-    print(case, steps, flush=True)
+    print(case, steps, form, flush=True)
     u = dev(u0)
-    rep = h.etdrk4(mats, tau, steps, u, tol=1e-12, graph=False)
+    rep = h.etdrk4(mats, tau, steps, u, tol=1e-12, graph=False, form=form)
     ref = E.etdrk4(mats, tau, u0, steps)
     e = rel(u.cpu().numpy(), ref)
     print(rep, e, flush=True)
     assert e < 1e-9, e
 
 
-def test_etd_graph_matches_direct(h):
+@pytest.mark.parametrize("form", ["separate", "combo"])
+def test_etd_graph_matches_direct(h, form):
     rng = np.random.default_rng(6)
     mats = laplace(16, 3)
     u0 = rng.uniform(-1.0, 1.0, 16 ** 3)
-    print("graph vs direct, 3D n=16", flush=True)
+    print("graph vs direct, 3D n=16", form, flush=True)
     ue = dev(u0)
-    rep_e = h.etdrk4(mats, 0.01, 6, ue, graph=False)
+    rep_e = h.etdrk4(mats, 0.01, 6, ue, graph=False, form=form)
     for trial in range(2):
         ug = dev(u0)
-        rep_g = h.etdrk4(mats, 0.01, 6, ug, graph=True)
+        rep_g = h.etdrk4(mats, 0.01, 6, ug, graph=True, form=form)
         assert rep_g["steps_graph"] == 5 and rep_g["steps_eager"] == 1 and rep_g["graph_nodes"] > 10
         assert torch.equal(ug, ue), trial
         # other work on the handle between the calls
@@ -79,14 +81,15 @@ def test_etd_graph_matches_direct(h):
     assert rep_e["steps_eager"] == 6
 
 
-def test_etd_one_step_n48_vs_oracle_quadrature(h):
+@pytest.mark.parametrize("form", ["separate", "combo"])
+def test_etd_one_step_n48_vs_oracle_quadrature(h, form):
     rng = np.random.default_rng(0)
     mats = laplace(48, 3)
     u0 = rng.uniform(-1.0, 1.0, 48 ** 3)
     tau = 0.01
-    print("3D n=48, one step vs oracle quadrature", flush=True)
+    print("3D n=48, one step vs oracle quadrature", form, flush=True)
     u = dev(u0)
-    h.etdrk4(mats, tau, 1, u, tol=1e-12, graph=False)
+    h.etdrk4(mats, tau, 1, u, tol=1e-12, graph=False, form=form)
     ref = E.etdrk4_step(mats, tau, u0, E.cubic,
                         phi=lambda m, t, v, p: Q.phiquadmv(m, t, v, p, eps=1e-14, beta=1.0))
     e = rel(u.cpu().numpy(), ref)
@@ -108,3 +111,21 @@ def test_etd_allen_cahn_3d_n128_graph(h):
     print(rep, flush=True)
     assert torch.equal(ug, ue)
     assert float(ug.abs().max()) <= 1.0 + 1e-12
+
+
+def test_etd_forms_agree_3d_n128(h):
+    """Ten full-size steps: the linear-combination form against the
+    per-vector form (the same scheme; tolerance 1e-8 plans, so the two differ
+    by the quadrature error only, far below 1e-9 relative)."""
+    rng = np.random.default_rng(0)
+    mats = laplace(128, 3)
+    u0 = rng.uniform(-1.0, 1.0, 128 ** 3)
+    print("3D n=128, 10 steps combo vs separate", flush=True)
+    ua = dev(u0)
+    ra = h.etdrk4(mats, 0.01, 10, ua, graph=True, form="separate")
+    ub = dev(u0)
+    rb = h.etdrk4(mats, 0.01, 10, ub, graph=True, form="combo")
+    e = float((ua - ub).abs().max() / ua.abs().max())
+    print(ra["ttm_chains_per_step"], rb["ttm_chains_per_step"], e, flush=True)
+    assert rb["ttm_chains_per_step"] < ra["ttm_chains_per_step"]
+    assert e < 1e-9, e

@@ -35,15 +35,15 @@ def lap2d(n):
 
 
 @pytest.mark.parametrize("method", [1, 2, 3])
-@pytest.mark.parametrize("rule", ["gauss", "cc"])
-def test_exprk_vs_oracle(h, method, rule):
+@pytest.mark.parametrize("rule,form", [("gauss", "separate"), ("gauss", "combo"), ("cc", "separate")])
+def test_exprk_vs_oracle(h, method, rule, form):
     n = 7
     mats = lap2d(n)
     c2 = 0.5 if method == 2 else 1.0 / 3.0
     u0 = R.exact(n, 0.0)
-    print("method", method, rule, flush=True)
+    print("method", method, rule, form, flush=True)
     u = torch.from_numpy(u0.copy()).cuda()
-    h.exprk(mats, method, 4, u, T=1.0, c2=c2, tol=1e-12, rule=rule)
+    h.exprk(mats, method, 4, u, T=1.0, c2=c2, tol=1e-12, rule=rule, form=form)
     ref = R.solve(mats, method, 1.0, 4, u0, R.g_ho(n), c2)
     e = float(np.max(np.abs(u.cpu().numpy() - ref)) / np.max(np.abs(ref)))
     print(e, flush=True)
