@@ -31,7 +31,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "φ_k(tA)v grid-pts/s + MFMA util: split-BF16 vs FP64 at rel err 1e-8"
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "int8": 5000.0}
 HBM_PEAK_GBS = 8000.0
 
 
@@ -97,7 +97,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--rule", default="gauss", choices=["gauss", "cc"])
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3", "int8"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
@@ -205,6 +205,11 @@ def main():
     avg_ms = st["ms"] / st["launches"]
     flops_per_launch = st["flops"] / st["launches"]
     achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
+    fp64_equivalent = achieved
+    if args.precision == "int8":
+        # executed int8 operations: every kept digit pair, S (S + 1) / 2 of them
+        digits = 5 if pr["tol"] >= 1e-6 else (6 if pr["tol"] >= 1e-9 else 7)
+        achieved *= digits * (digits + 1) / 2
     peak = PEAK_TFLOPS[args.precision]
     gbs = st["bytes"] / st["launches"] / (avg_ms * 1e-3) / 1e9
     # split bf16: three products at the 2.5 PF bf16 peak leave the kernel far from
@@ -228,7 +233,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}[args.precision],
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3", "int8": "i8"}[args.precision],
         "data": "synthetic",
         "config": {
             "workload": "3D advection-diffusion Kronecker sum, n=%d per axis (N=%d), a_d log-U[0.1,10], "
@@ -244,10 +249,11 @@ def main():
             "bound": bound,
             "achieved": achieved if bound == "mfma" else gbs,
             "peak": peak if bound == "mfma" else HBM_PEAK_GBS,
-            "unit": "TFLOP/s" if bound == "mfma" else "GB/s",
+            "unit": ("TOP/s" if args.precision == "int8" else "TFLOP/s") if bound == "mfma" else "GB/s",
             "frac": (achieved / peak) if bound == "mfma" else gbs / HBM_PEAK_GBS,
             "mfma_tflops": achieved,
             "mfma_peak_tflops": peak,
+            "fp64_equivalent_tflops": fp64_equivalent,
             "traffic": traffic,
             "avg_launch_ms": avg_ms,
             "launches": st["launches"],

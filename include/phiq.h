@@ -66,7 +66,13 @@ typedef enum { PHIQ_RULE_GAUSS = 1, PHIQ_RULE_CC = 2 } phiq_rule;
 typedef enum {
   PHIQ_PREC_FP64 = 0,    /* FP64 MFMA, FP64 intermediates                    */
   PHIQ_PREC_FP32 = 1,    /* FP32 MFMA with FP32 accumulation                 */
-  PHIQ_PREC_BF16X3 = 2   /* x = hi + lo in bf16, hi*hi + hi*lo + lo*hi, FP32 */
+  PHIQ_PREC_BF16X3 = 2,  /* x = hi + lo in bf16, hi*hi + hi*lo + lo*hi, FP32 */
+  PHIQ_PREC_INT8 = 3     /* FP64 split into S signed 7-bit digits (5 for tol  */
+                         /* >= 1e-6, 6 for >= 1e-9, else 7) with one exponent */
+                         /* per row of a 1D factor and per tensor; digit      */
+                         /* products exact on int8 MFMA, combined in FP64.    */
+                         /* Gauss rule, dim >= 2, every n_d in {32, 64, 96,  */
+                         /* 128} (else PHIQ_ERR_UNSUPPORTED).               */
 } phiq_precision;
 
 /* Choice of (l, m) for the Gauss rule. */

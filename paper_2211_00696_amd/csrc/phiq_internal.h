@@ -211,6 +211,40 @@ struct NodeSegs {
 int launch_node_sum(const NodeSegs& segs, long long N, const double* coef, int ldcoef, int np, double* Y,
                     void* stream);
 
+// ---- kernels_i8.hip: mode products on int8 digit slices -------------------
+enum I8Mode : int { kI8Slice = 0, kI8Store = 1, kI8Square = 2 };
+struct I8Args {
+  int S;                                // digits per value (5..7)
+  const int8_t* E;                      // factor digits: batch b at E + b es, slice s at + s esp
+  long long es, esp;                    // rows of K digits, M rows per factor
+  const int* ee;                        // row exponents: batch b at ee + b ees
+  long long ees;
+  int delta;                            // 2^delta bounds ||E_b||_inf (digit epilogue)
+  const int8_t* X;                      // input digits: batch b at X + b xs, slice s at + s xsp
+  long long xs, xsp;
+  const int* xe;                        // input tensor exponent of batch b: xe[b xes]
+  long long xes;
+  int M, K;
+  long long L;
+  int nbatch;
+  int8_t* O8;                           // kI8Slice: output digits O8 + b os8 + s osp8
+  long long os8, osp8;
+  int* oe;                              // kI8Slice: output exponents, oe[b] = xe + delta
+  double* O;                            // kI8Store / kI8Square: O + b os
+  long long os;
+  const double* Yprev;                  // kI8Square: y_j at Yprev + (j-1) yps; batch b is order b+1
+  long long yps;
+  double ifact[PHIQ_MAX_P + 1];
+};
+// digits of the rows of X (rows x K, contiguous) with one exponent per row
+int launch_i8_slice_rows(const double* X, long long rows, int K, int S, int8_t* planes, int* ex, void* stream);
+// digits of nt tensors X + r xs (N values each) with one exponent per
+// tensor (partial: nt x nbx doubles of scratch); planes + r bstride, ex[r]
+int launch_i8_slice_tensors(const double* X, long long xs, long long N, int nt, int S, double* partial, int nbx,
+                            int8_t* planes, long long bstride, int* ex, void* stream);
+// M = K in {32, 64, 96, 128}, L % 32 == 0
+int launch_i8_product(const I8Args& a, int mode, void* stream);
+
 // ---- batched.hip: batched stages, one launch per dependency depth --------
 // A batch is a list of stages (one GEMM, Taylor evaluation or mode product
 // over a whole operand, split into 64 x 64 tiles), stored by depth in the
