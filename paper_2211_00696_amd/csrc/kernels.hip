@@ -291,20 +291,29 @@ __global__ void absdiff_max_kernel(const double* __restrict__ y, const double* _
 }
 
 // Y[j*N + i] = sum_b coef[j * ldcoef + b] * V_b[i], b running through the segments
+// NP > 0: that many outputs, kept in registers; NP = 0: np outputs (any).
+template <int NP>
 __global__ void node_sum_kernel(NodeSegs segs, long long N, const double* __restrict__ coef, int ldcoef, int np,
                                 double* __restrict__ Y) {
+  constexpr int A = NP > 0 ? NP : PHIQ_MAX_P;
+  const int n = NP > 0 ? NP : np;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N; i += (long long)gridDim.x * blockDim.x) {
-    double acc[PHIQ_MAX_P];
-    for (int j = 0; j < np; ++j) acc[j] = 0.0;
+    double acc[A];
+#pragma unroll
+    for (int j = 0; j < A; ++j) acc[j] = 0.0;
     int b = 0;
     for (int sg = 0; sg < segs.nseg; ++sg) {
       const double* V = segs.V[sg];
       for (int c = 0; c < segs.count[sg]; ++c, ++b) {
         const double x = V[(long long)c * N + i];
-        for (int j = 0; j < np; ++j) acc[j] += coef[j * ldcoef + b] * x;
+#pragma unroll
+        for (int j = 0; j < A; ++j)
+          if (j < n) acc[j] += coef[j * ldcoef + b] * x;
       }
     }
-    for (int j = 0; j < np; ++j) Y[j * N + i] = acc[j];
+#pragma unroll
+    for (int j = 0; j < A; ++j)
+      if (j < n) Y[j * N + i] = acc[j];
   }
 }
 
@@ -512,7 +521,13 @@ int launch_absdiff_max(const double* y, const double* yold, int np, long long N,
 int launch_node_sum(const NodeSegs& segs, long long N, const double* coef, int ldcoef, int np, double* Y,
                     void* stream) {
   const int nb = std::max(1, std::min(4096, cdiv(N, 256)));
-  PHIQ_LAUNCH(node_sum_kernel, dim3(nb), dim3(256), 0, (hipStream_t)stream, segs, N, coef, ldcoef, np, Y);
+  switch (np) {
+    case 1: PHIQ_LAUNCH(node_sum_kernel<1>, dim3(nb), dim3(256), 0, (hipStream_t)stream, segs, N, coef, ldcoef, np, Y); break;
+    case 2: PHIQ_LAUNCH(node_sum_kernel<2>, dim3(nb), dim3(256), 0, (hipStream_t)stream, segs, N, coef, ldcoef, np, Y); break;
+    case 3: PHIQ_LAUNCH(node_sum_kernel<3>, dim3(nb), dim3(256), 0, (hipStream_t)stream, segs, N, coef, ldcoef, np, Y); break;
+    case 4: PHIQ_LAUNCH(node_sum_kernel<4>, dim3(nb), dim3(256), 0, (hipStream_t)stream, segs, N, coef, ldcoef, np, Y); break;
+    default: PHIQ_LAUNCH(node_sum_kernel<0>, dim3(nb), dim3(256), 0, (hipStream_t)stream, segs, N, coef, ldcoef, np, Y);
+  }
   return hipGetLastError();
 }
 

@@ -35,9 +35,11 @@ import sys
 from collections import defaultdict
 
 CLASS_RE = {
-    "ttm_store": re.compile(r"(^|::)ttm_(lp_)?store_kernel"),
+    # int8 digit products: modes 0 (digits out) and 1 (FP64 out) count as stores, 2 as squaring
+    "ttm_store": re.compile(r"(^|::)ttm_(lp_)?store_kernel|(^|::)i8_product_kernel<\d+, \d+, [01]>"),
     "ttm_accum": re.compile(r"(^|::)ttm_(lp_)?accum_kernel"),
-    "ttm_square": re.compile(r"(^|::)ttm_(lp_)?square(_all)?_kernel"),
+    "ttm_square": re.compile(r"(^|::)ttm_(lp_)?square(_all)?_kernel|(^|::)i8_product_kernel<\d+, \d+, 2>"),
+    "slice": re.compile(r"(^|::)i8_(slice_rows|absmax|slice_tensor)_kernel"),
     "gemm": re.compile(r"(^|::)gemm_jobs_kernel"),
     "taylor": re.compile(r"(^|::)taylor_jobs_kernel"),
     "scale": re.compile(r"(^|::)scale_jobs_kernel"),
