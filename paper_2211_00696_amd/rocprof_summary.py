@@ -3,6 +3,11 @@
   python -m paper_2211_00696_amd.rocprof_summary times   TRACE.csv BENCH.json
   python -m paper_2211_00696_amd.rocprof_summary traffic FETCH.csv WRITE.csv BENCH.json COPY_MIB
   python -m paper_2211_00696_amd.rocprof_summary mfma   COUNTERS.csv BENCH.json
+  python -m paper_2211_00696_amd.rocprof_summary timeline TRACE.csv INDEX
+
+`timeline` prints the kernels between the INDEX-th and the next plan upload
+(`fetch_kernel`, one per phiq_action call) in start order, with their queue
+(stream), and the busy and idle time of the GPU over that window.
 
 `times` reads a `--kernel-trace` CSV and prints a markdown table per kernel,
 plus the average duration of the dominant class's launches inside bench.py's
@@ -169,6 +174,37 @@ def mfma(csv_path, bench_json):
     print(json.dumps({dom: out}, indent=1))
 
 
+def timeline(trace_csv, index):
+    rows = sorted(_rows(trace_csv), key=lambda r: int(r["Start_Timestamp"]))
+    ups = [i for i, r in enumerate(rows) if re.search(r"(^|::)fetch_kernel", _name(r))]
+    k = int(index)
+    if k + 1 >= len(ups):
+        raise SystemExit("only %d plan uploads in the trace" % len(ups))
+    sel = rows[ups[k]:ups[k + 1] + 1]
+    t0 = int(sel[0]["Start_Timestamp"])
+    print("| start us | end us | us | queue | kernel |")
+    print("|---|---|---|---|---|")
+    spans = []
+    for r in sel:
+        s0, s1 = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+        spans.append((s0, s1))
+        print("| %.1f | %.1f | %.1f | %s | `%s` |" % ((s0 - t0) / 1e3, (s1 - t0) / 1e3, (s1 - s0) / 1e3,
+                                                  r.get("Queue_Id", "?"), _short(_name(r))))
+    spans.sort()
+    busy, cur = 0, None
+    for a, b in spans:
+        if cur is None or a > cur[1]:
+            if cur:
+                busy += cur[1] - cur[0]
+            cur = [a, b]
+        else:
+            cur[1] = max(cur[1], b)
+    busy += cur[1] - cur[0]
+    span = max(b for _, b in spans) - min(a for a, _ in spans)
+    print()
+    print("Window %.1f us: some kernel running %.1f us, idle %.1f us." % (span / 1e3, busy / 1e3, (span - busy) / 1e3))
+
+
 if __name__ == "__main__":
     if len(sys.argv) >= 4 and sys.argv[1] == "times":
         times(sys.argv[2], sys.argv[3])
@@ -176,6 +212,8 @@ if __name__ == "__main__":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
     elif len(sys.argv) >= 4 and sys.argv[1] == "mfma":
         mfma(sys.argv[2], sys.argv[3])
+    elif len(sys.argv) >= 4 and sys.argv[1] == "timeline":
+        timeline(sys.argv[2], sys.argv[3])
     else:
         print(__doc__)
         sys.exit(2)
