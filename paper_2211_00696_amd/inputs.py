@@ -11,6 +11,8 @@ Operators (1D, Dirichlet, n interior points, h = 1/(n+1)):
   * advection  U_n = tridiag(-1, 1, 0) / h      (first-order upwind, backward
     difference for a non-negative velocity)
   * A^d = a_d T_n + b_d U_n
+  * on a Shishkin mesh: -eps u'' + beta u' with non-uniform differences
+  * FE-P1 with the consistent mass matrix: the dense M^{-1} K
 
 Random draws use ``numpy.random.default_rng(seed)`` in a fixed order:
 a_1..a_d (log-uniform in [0.1, 10]), then b_1..b_d (uniform in [0, 50]),
@@ -47,6 +49,59 @@ def fd_upwind(n: int) -> np.ndarray:
 def adv_diff_1d(n: int, a: float, b: float) -> np.ndarray:
     """a * diffusion + b * upwind advection, both on n interior points."""
     return a * fd_laplacian(n) + b * fd_upwind(n)
+
+
+def shishkin_mesh(n: int, eps: float, beta: float = 1.0, sigma: float = 2.0) -> np.ndarray:
+    """The n interior nodes of a piecewise-uniform Shishkin mesh on (0, 1) for
+    a boundary layer at x = 1 (advection to the right): (n+1)/2 equal cells on
+    [0, 1 - tau] and (n+1)/2 on [1 - tau, 1], tau = min(1/2, sigma eps ln(n+1) / beta).
+    n must be odd."""
+    if n % 2 == 0:
+        raise ValueError("n must be odd")
+    cells = n + 1
+    tau = min(0.5, sigma * eps * math.log(cells) / beta)
+    left = np.linspace(0.0, 1.0 - tau, cells // 2 + 1)
+    right = np.linspace(1.0 - tau, 1.0, cells // 2 + 1)
+    x = np.concatenate([left, right[1:]])
+    return x[1:-1]
+
+
+def fd_adv_diff_nonuniform(x: np.ndarray, eps: float, beta: float) -> np.ndarray:
+    """-eps u'' + beta u' on the interior nodes x of (0, 1), Dirichlet: the
+    three-point second difference 2/(h_l + h_r) ((u_r - u)/h_r - (u - u_l)/h_l)
+    (exact on quadratics) and the upwind difference (u - u_l)/h_l."""
+    n = x.size
+    xs = np.concatenate([[0.0], x, [1.0]])
+    a = np.zeros((n, n))
+    for i in range(n):
+        hl = xs[i + 1] - xs[i]
+        hr = xs[i + 2] - xs[i + 1]
+        c = 2.0 / (hl + hr)
+        a[i, i] = eps * c * (1.0 / hl + 1.0 / hr) + beta / hl
+        if i > 0:
+            a[i, i - 1] = -eps * c / hl - beta / hl
+        if i < n - 1:
+            a[i, i + 1] = -eps * c / hr
+    return a
+
+
+def fem_p1_consistent(n: int) -> np.ndarray:
+    """Dense M^{-1} K of linear finite elements on n interior nodes of (0, 1)
+    (uniform, Dirichlet): K = tridiag(-1, 2, -1)/h, consistent mass
+    M = h tridiag(1/6, 2/3, 1/6); the product is a dense 1D operator."""
+    h = 1.0 / (n + 1)
+    idx = np.arange(n)
+    K = np.zeros((n, n))
+    K[idx, idx] = 2.0
+    K[idx[1:], idx[:-1]] = -1.0
+    K[idx[:-1], idx[1:]] = -1.0
+    K /= h
+    M = np.zeros((n, n))
+    M[idx, idx] = 2.0 / 3.0
+    M[idx[1:], idx[:-1]] = 1.0 / 6.0
+    M[idx[:-1], idx[1:]] = 1.0 / 6.0
+    M *= h
+    return np.linalg.solve(M, K)
 
 
 def draw_coefficients(rng: np.random.Generator, dim: int):
