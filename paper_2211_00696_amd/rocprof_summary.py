@@ -19,11 +19,12 @@ the same command, calibrates each counter with the plain device copy that
 another buffer: COPY_MIB MiB read, COPY_MIB MiB written), and prints the HBM
 bytes per launch of the dominant class as JSON for profiles/traffic.json.
 
-`mfma` reads a `--pmc SQ_INSTS_VALU_MFMA_MOPS_F64` and/or `--pmc MfmaUtil`
-CSV and prints, for the dominant class's timed-region launches, the FP64
-MFMA flops the hardware executed (MOPS x 512) next to the algorithmic flops,
-and rocprofv3's derived MFMA utilisation (busy cycles over active cycles x
-SIMDs, with the reductions the tool defines).
+`mfma` reads a `--pmc` counter CSV and prints, for the dominant class's
+timed-region launches, every counter's mean per launch; with
+SQ_INSTS_VALU_MFMA_MOPS_F64 the FP64 MFMA flops the hardware executed (MOPS x
+512) next to the algorithmic flops, with MfmaUtil rocprofv3's derived MFMA
+utilisation, and with the LDS / wait counters the bank-conflict cycles per
+LDS instruction and the wait fractions of the wave cycles.
 
 bench.py's step sequence after warm-up is: K timed actions, K untimed
 actions, one plan execution, K executions of the reused plan.  Every step
@@ -171,6 +172,16 @@ def mfma(csv_path, bench_json):
     if any("MfmaUtil" in c for _, c in sl):
         # rocprofv3's derived metric: MFMA busy cycles / (GPU active cycles x SIMDs), in percent
         out["mfma_util_percent_mean"] = sum(c["MfmaUtil"] for _, c in sl) / len(sl)
+    # every counter of the pass, mean per launch, and the LDS / wait ratios when present
+    keys = sorted({k for _, c in sl for k in c})
+    out["counters_per_launch"] = {k: sum(c.get(k, 0.0) for _, c in sl) / len(sl) for k in keys}
+    m = out["counters_per_launch"]
+    if m.get("SQ_INSTS_LDS"):
+        out["lds_bank_conflict_cycles_per_lds_instruction"] = m.get("SQ_LDS_BANK_CONFLICT", 0.0) / m["SQ_INSTS_LDS"]
+    if m.get("SQ_WAVE_CYCLES"):
+        for k in ("SQ_WAIT_INST_LDS", "SQ_WAIT_ANY"):
+            if k in m:
+                out[k.lower() + "_over_wave_cycles"] = m[k] / m["SQ_WAVE_CYCLES"]
     print(json.dumps({dom: out}, indent=1))
 
 
