@@ -109,6 +109,15 @@ BatchStage ttm(int type, const double* E, long long es, const double* X, long lo
   s.X = X;
   s.xs = xs;
   s.vec = (n % 2 == 0) && aligned16(E) && aligned16(X) && es % 2 == 0 && xs % 2 == 0;
+  // the single-problem kernels' fastest shapes at n >= 128: 64 x 128 stores,
+  // eight-wave node sums and squaring steps (the thresholds from batch timings)
+  if (type == kStageStore && n >= kBatchWideM) {
+    s.type = kStageStoreWide;
+    s.ntiles = (int)(cdiv(s.M, kBatchTile) * cdiv(s.L, kBatchWideN) * nb);
+    return s;
+  }
+  if (n >= kBatchWaves8M && type == kStageAccum) s.type = kStageAccumWide;
+  if (n >= kBatchWaves8M && type == kStageSquare) s.type = kStageSquareWide;
   const long long per = cdiv(s.M, kBatchTile) * cdiv(s.L, kBatchTile);
   s.ntiles = (int)(type == kStageStore ? per * nb : per);
   return s;
@@ -309,8 +318,10 @@ struct Built {
 // Kernel variant of a stage within its type: orders (Accum, Square) and
 // 16-byte staging.
 int key(const BatchStage& s) {
-  const int np = (s.type == kStageAccum || s.type == kStageSquare) ? s.np : 0;
-  const int vec = (s.type == kStageStore || s.type == kStageAccum || s.type == kStageSquare) ? s.vec : 0;
+  const bool acc_sq = s.type == kStageAccum || s.type == kStageSquare || s.type == kStageAccumWide ||
+                      s.type == kStageSquareWide;
+  const int np = acc_sq ? s.np : 0;
+  const int vec = (acc_sq || s.type == kStageStore || s.type == kStageStoreWide) ? s.vec : 0;
   return np * 2 + vec;
 }
 
@@ -522,16 +533,19 @@ struct Schedule {
           break;
         }
         case kStageStore:
+        case kStageStoreWide:
           for (int q = 0; q < s.nb && good; ++q)
             good = in(s.E + q * s.es, MK) && in(s.X + q * s.xs, LK) && in(s.O + q * s.os, ML);
           break;
         case kStageAccum:
+        case kStageAccumWide:
           if (s.np < 1 || s.np > 4) return PHIQ_ERR_INVALID_ARG;
           for (int q = 0; q < s.nb && good; ++q) good = in(s.E + q * s.es, MK) && in(s.X + q * s.xs, LK);
           for (int q = 0; q < s.np && good; ++q)
             good = in(s.Y + q * s.ys, ML) && in(s.coef + q * s.ldcoef, s.nb);
           break;
         case kStageSquare:
+        case kStageSquareWide:
           if (s.np < 1 || s.np > 4) return PHIQ_ERR_INVALID_ARG;
           good = in(s.E, MK);
           for (int q = 0; q < s.np && good; ++q)

@@ -16,6 +16,8 @@
 namespace phiq {
 
 using BT = Tile<kBatchTile, kBatchTile, 16, 2, 2>;  // 256 threads, 64 x 64 output tiles
+using BW = Tile<kBatchTile, kBatchWideN, 16, 2, 4, 1>;  // wide stores: 512 threads, 64 x 128 tiles
+using B8 = Tile<kBatchTile, kBatchTile, 16, 2, 4, 1>;   // wide node sums / squaring: 512 threads, 64 x 64
 constexpr int kXcdCount = 8;
 static_assert(BT::NT == 256, "batch worker size");
 
@@ -82,37 +84,50 @@ __device__ void run_store(const BatchStage& S, int tile, double* smem) {
   store_tile<BT>(S.O + b * S.os, S.M, S.L, m0, n0, acc);
 }
 
-template <int NP, bool VEC>
+template <bool VEC>
+__device__ void run_store_wide(const BatchStage& S, int tile, double* smem) {
+  const int mt = (S.M + BW::BM - 1) / BW::BM;
+  const int m0 = (tile % mt) * BW::BM;
+  const int r = tile / mt;
+  const int b = r % S.nb;
+  const int n0 = (r / S.nb) * BW::BN;
+  d4 acc[BW::TM][BW::TN];
+  zero_acc<BW>(acc);
+  tile_nt_db<BW, VEC>(S.E + b * S.es, S.X + b * S.xs, S.M, S.K, S.L, m0, n0, smem, acc);
+  store_tile<BW>(S.O + b * S.os, S.M, S.L, m0, n0, acc);
+}
+
+template <class C, int NP, bool VEC>
 __device__ void run_accum(const BatchStage& S, int tile, double* smem) {
-  const int mt = (S.M + BT::BM - 1) / BT::BM;
-  const int m0 = (tile % mt) * BT::BM, n0 = (tile / mt) * BT::BN;
-  d4 y[NP][BT::TM][BT::TN];
+  const int mt = (S.M + C::BM - 1) / C::BM;
+  const int m0 = (tile % mt) * C::BM, n0 = (tile / mt) * C::BN;
+  d4 y[NP][C::TM][C::TN];
 #pragma unroll
-  for (int q = 0; q < NP; ++q) zero_acc<BT>(y[q]);
+  for (int q = 0; q < NP; ++q) zero_acc<C>(y[q]);
   for (int b = 0; b < S.nb; ++b) {
-    d4 acc[BT::TM][BT::TN];
-    zero_acc<BT>(acc);
-    tile_nt_db<BT, VEC>(S.E + b * S.es, S.X + b * S.xs, S.M, S.K, S.L, m0, n0, smem, acc);
+    d4 acc[C::TM][C::TN];
+    zero_acc<C>(acc);
+    tile_nt_db<C, VEC>(S.E + b * S.es, S.X + b * S.xs, S.M, S.K, S.L, m0, n0, smem, acc);
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
       const double w = S.coef[q * S.ldcoef + b];
 #pragma unroll
-      for (int i = 0; i < BT::TM; ++i)
+      for (int i = 0; i < C::TM; ++i)
 #pragma unroll
-        for (int j = 0; j < BT::TN; ++j) y[q][i][j] += w * acc[i][j];
+        for (int j = 0; j < C::TN; ++j) y[q][i][j] += w * acc[i][j];
     }
   }
 #pragma unroll
   for (int q = 0; q < NP; ++q) {
     double* Y = S.Y + q * S.ys;
 #pragma unroll
-    for (int i = 0; i < BT::TM; ++i)
+    for (int i = 0; i < C::TM; ++i)
 #pragma unroll
-      for (int j = 0; j < BT::TN; ++j) {
-        const int col = n0 + acc_col<BT>(j);
+      for (int j = 0; j < C::TN; ++j) {
+        const int col = n0 + acc_col<C>(j);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int row = m0 + acc_row<BT>(i, e);
+          const int row = m0 + acc_row<C>(i, e);
           if (row < S.M && col < S.L) {
             const long long idx = (long long)row * S.L + col;
             Y[idx] = S.accumulate ? Y[idx] + y[q][i][j][e] : y[q][i][j][e];
@@ -126,39 +141,39 @@ __device__ void run_accum(const BatchStage& S, int tile, double* smem) {
 // block computes E y_i for i = 1..NP in turn; each y_i tile is loaded (into
 // registers, before its product's K loop so that the load overlaps it) once
 // and kept for the later orders.
-template <int NP, bool VEC>
+template <class C, int NP, bool VEC>
 __device__ void run_square(const BatchStage& S, int tile, double* smem) {
-  const int mt = (S.M + BT::BM - 1) / BT::BM;
-  const int m0 = (tile % mt) * BT::BM, n0 = (tile / mt) * BT::BN;
+  const int mt = (S.M + C::BM - 1) / C::BM;
+  const int m0 = (tile % mt) * C::BM, n0 = (tile / mt) * C::BN;
   const double ifact[4] = {1.0, 1.0, 0.5, 1.0 / 6.0};
-  d4 ys[NP][BT::TM][BT::TN];
+  d4 ys[NP][C::TM][C::TN];
 #pragma unroll
   for (int i = 0; i < NP; ++i) {
 #pragma unroll
-    for (int ti = 0; ti < BT::TM; ++ti)
+    for (int ti = 0; ti < C::TM; ++ti)
 #pragma unroll
-      for (int tj = 0; tj < BT::TN; ++tj) {
-        const int col = n0 + acc_col<BT>(tj);
+      for (int tj = 0; tj < C::TN; ++tj) {
+        const int col = n0 + acc_col<C>(tj);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int row = m0 + acc_row<BT>(ti, e);
+          const int row = m0 + acc_row<C>(ti, e);
           const int rc = row < S.M ? row : S.M - 1, cc = col < S.L ? col : S.L - 1;
           ys[i][ti][tj][e] = S.Y[i * S.ys + (long long)rc * S.L + cc];
         }
       }
-    d4 acc[BT::TM][BT::TN];
-    zero_acc<BT>(acc);
-    tile_nt_db<BT, VEC>(S.E, S.X + i * S.xs, S.M, S.K, S.L, m0, n0, smem, acc);
+    d4 acc[C::TM][C::TN];
+    zero_acc<C>(acc);
+    tile_nt_db<C, VEC>(S.E, S.X + i * S.xs, S.M, S.K, S.L, m0, n0, smem, acc);
     const double scale = ldexp(1.0, -(i + 1));
     double* O = S.O + i * S.os;
 #pragma unroll
-    for (int ti = 0; ti < BT::TM; ++ti)
+    for (int ti = 0; ti < C::TM; ++ti)
 #pragma unroll
-      for (int tj = 0; tj < BT::TN; ++tj) {
-        const int col = n0 + acc_col<BT>(tj);
+      for (int tj = 0; tj < C::TN; ++tj) {
+        const int col = n0 + acc_col<C>(tj);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int row = m0 + acc_row<BT>(ti, e);
+          const int row = m0 + acc_row<C>(ti, e);
           double s = acc[ti][tj][e];
 #pragma unroll
           for (int j = 0; j <= i; ++j) s += ys[j][ti][tj][e] * ifact[i - j];
@@ -200,11 +215,62 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs a) {
     } else if constexpr (TYPE == kStageStore) {
       run_store<VEC>(S, tile, smem);
     } else if constexpr (TYPE == kStageAccum) {
-      run_accum<NP, VEC>(S, tile, smem);
+      run_accum<BT, NP, VEC>(S, tile, smem);
     } else {
-      run_square<NP, VEC>(S, tile, smem);
+      run_square<BT, NP, VEC>(S, tile, smem);
     }
     __syncthreads();  // smem is reused by the next tile
+  }
+}
+
+// The wide stage types: the same tile walk with 512-thread workgroups.
+template <int TYPE, int NP, bool VEC>
+__global__ __launch_bounds__(512) void batch_wide_kernel(BatchArgs a) {
+  __shared__ double smem[TYPE == kStageStoreWide ? 2 * (BW::BM + BW::BN) * BW::LDK : 2 * (B8::BM + B8::BN) * B8::LDK];
+  const long long T = a.tile_end - a.tile_begin;
+  const long long per = (T + kXcdCount - 1) / kXcdCount;
+  const int xcd = blockIdx.x % kXcdCount;
+  const long long G = gridDim.x / kXcdCount;
+  int lo = a.stage_begin;
+  for (long long v = blockIdx.x / kXcdCount; v < per; v += G) {
+    const long long t = (long long)xcd * per + v;
+    if (t >= T) break;
+    const long long g = a.tile_begin + t;
+    int hi = a.stage_end - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (a.st[mid].tile0 <= g) lo = mid; else hi = mid - 1;
+    }
+    const BatchStage& S = a.st[lo];
+    const int tile = (int)(g - S.tile0);
+    if constexpr (TYPE == kStageStoreWide) {
+      run_store_wide<VEC>(S, tile, smem);
+    } else if constexpr (TYPE == kStageAccumWide) {
+      run_accum<B8, NP, VEC>(S, tile, smem);
+    } else {
+      run_square<B8, NP, VEC>(S, tile, smem);
+    }
+    __syncthreads();  // smem is reused by the next tile
+  }
+}
+
+template <int TYPE, int NP>
+hipError_t launch_wide(const BatchArgs& a, bool vec, dim3 grid, hipStream_t st) {
+  if (vec)
+    hipLaunchKernelGGL((batch_wide_kernel<TYPE, NP, true>), grid, dim3(512), 0, st, a);
+  else
+    hipLaunchKernelGGL((batch_wide_kernel<TYPE, NP, false>), grid, dim3(512), 0, st, a);
+  return hipGetLastError();
+}
+
+template <int TYPE>
+hipError_t launch_wide_type(const BatchArgs& a, int np, bool vec, dim3 grid, hipStream_t st) {
+  switch (np) {
+    case 1: return launch_wide<TYPE, 1>(a, vec, grid, st);
+    case 2: return launch_wide<TYPE, 2>(a, vec, grid, st);
+    case 3: return launch_wide<TYPE, 3>(a, vec, grid, st);
+    case 4: return launch_wide<TYPE, 4>(a, vec, grid, st);
+    default: return hipErrorInvalidValue;
   }
 }
 
@@ -241,6 +307,9 @@ int launch_batch(const BatchArgs& a, int type, int np, int vec, int blocks, void
       hipLaunchKernelGGL((batch_kernel<kStageTaylor, 0, false>), grid, dim3(256), 0, st, a);
       return hipGetLastError();
     case kStageStore: return launch_np<kStageStore, 0>(a, vec != 0, grid, st);
+    case kStageStoreWide: return launch_wide<kStageStoreWide, 0>(a, vec != 0, grid, st);
+    case kStageAccumWide: return launch_wide_type<kStageAccumWide>(a, np, vec != 0, grid, st);
+    case kStageSquareWide: return launch_wide_type<kStageSquareWide>(a, np, vec != 0, grid, st);
     case kStageAccum: return launch_type<kStageAccum>(a, np, vec != 0, grid, st);
     case kStageSquare: return launch_type<kStageSquare>(a, np, vec != 0, grid, st);
     default: return hipErrorInvalidValue;

@@ -258,6 +258,9 @@ enum BatchStageType : int {
   kStageStore = 2,   // O_b = rotated mode product of (E_b, X_b), b < nb
   kStageAccum = 3,   // Y_q (+)= sum_b coef[q * ldcoef + b] * (E_b X_b), q < np
   kStageSquare = 4,  // O_i = 2^{-i-1} (E X_i + sum_{j<=i} Y_j / (i-j)!), i < np
+  kStageStoreWide = 5,   // as kStageStore with 64 x 128 tiles and 512 threads (M >= kBatchWideM)
+  kStageAccumWide = 6,   // as kStageAccum, 512 threads (8 waves of 32 x 16) on the same 64 x 64 tiles (M >= kBatchWaves8M)
+  kStageSquareWide = 7,  // as kStageSquare, likewise
 };
 struct BatchStage {
   long long tile0;  // number of this stage's first tile
@@ -295,7 +298,10 @@ struct BatchTaylor {
   int nt;
   int pad_;
 };
-constexpr int kBatchTile = 64;          // output tile edge of every stage
+constexpr int kBatchTile = 64;          // output tile edge of every stage (rows of a wide store tile)
+constexpr int kBatchWideN = 128;        // columns of a wide store tile
+constexpr int kBatchWideM = 96;         // stores with at least this many rows use wide tiles
+constexpr int kBatchWaves8M = 64;       // node sums / squaring steps from this many rows use eight waves
 constexpr int kBatchTaylorChunk = 4096; // elements per Taylor tile
 struct BatchArgs {
   const BatchStage* st;

@@ -4,6 +4,11 @@
   python -m paper_2211_00696_amd.rocprof_summary traffic FETCH.csv WRITE.csv BENCH.json COPY_MIB
   python -m paper_2211_00696_amd.rocprof_summary mfma   COUNTERS.csv BENCH.json
   python -m paper_2211_00696_amd.rocprof_summary timeline TRACE.csv INDEX
+  python -m paper_2211_00696_amd.rocprof_summary batch  TRACE.csv
+
+`batch` takes the last run of consecutive batched-stage kernels
+(`batch_kernel`, `batch_wide_kernel`: one phiq_action_batched call) and sums
+their time per stage kind, order count and staging width.
 
 `timeline` prints the kernels between the INDEX-th and the next plan upload
 (`fetch_kernel`, one per phiq_action call) in start order, with their queue
@@ -216,6 +221,42 @@ def timeline(trace_csv, index):
     print("Window %.1f us: some kernel running %.1f us, idle %.1f us." % (span / 1e3, busy / 1e3, (span - busy) / 1e3))
 
 
+STAGE_KIND = {0: "GEMM (1D exponentials)", 1: "Taylor sums", 2: "mode product, store",
+              3: "last mode + node sum", 4: "last mode + squaring", 5: "mode product, store (64 x 128 tiles)",
+              6: "last mode + node sum (8 waves)", 7: "last mode + squaring (8 waves)"}
+BATCH_RE = re.compile(r"(^|::)batch(_wide)?_kernel<(\d+), (\d+), (true|false)>")
+
+
+def batch(trace_csv):
+    rows = sorted(_rows(trace_csv), key=lambda r: int(r["Start_Timestamp"]))
+    runs, cur = [], []
+    for r in rows:
+        if BATCH_RE.search(_name(r)):
+            cur.append(r)
+        elif cur:
+            runs.append(cur)
+            cur = []
+    if cur:
+        runs.append(cur)
+    if not runs:
+        raise SystemExit("no batched-stage kernels in the trace")
+    last = runs[-1]
+    agg = defaultdict(lambda: [0, 0.0])
+    for r in last:
+        m = BATCH_RE.search(_name(r))
+        key = (int(m.group(3)), int(m.group(4)), m.group(5))
+        agg[key][0] += 1
+        agg[key][1] += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
+    print("| stage kind | orders | 16-byte staging | launches | ms |")
+    print("|---|---|---|---|---|")
+    for (t, np_, vec), (n, ms) in sorted(agg.items()):
+        print("| %s | %d | %s | %d | %.1f |" % (STAGE_KIND.get(t, str(t)), np_, vec, n, ms))
+    total = sum(ms for _, ms in agg.values())
+    span = (int(last[-1]["End_Timestamp"]) - int(last[0]["Start_Timestamp"])) / 1e6
+    print()
+    print("Sum of the last call: %.1f ms over %d launches, span %.1f ms." % (total, len(last), span))
+
+
 if __name__ == "__main__":
     if len(sys.argv) >= 4 and sys.argv[1] == "times":
         times(sys.argv[2], sys.argv[3])
@@ -225,6 +266,8 @@ if __name__ == "__main__":
         mfma(sys.argv[2], sys.argv[3])
     elif len(sys.argv) >= 4 and sys.argv[1] == "timeline":
         timeline(sys.argv[2], sys.argv[3])
+    elif len(sys.argv) >= 3 and sys.argv[1] == "batch":
+        batch(sys.argv[2])
     else:
         print(__doc__)
         sys.exit(2)

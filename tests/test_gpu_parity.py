@@ -240,6 +240,21 @@ def test_advdiff3d_n128_full_size(h, rule):
     assert max(res) < 1e-9, res
 
 
+def test_advdiff3d_n256_full_size(h):
+    """3D n = 256 (N = 16.8M): properties that hold at any size.  phi_0
+    against the separable 1D exponentials, and the recurrence
+    phi_{k-1} = M phi_k + v/(k-1)! for phi_1..phi_3, whose residual for a
+    result within tol is at most about alpha tol (M = -tA, alpha = ||tA||_inf)."""
+    pr = I.problem("advdiff3d", seed=0, n=256)
+    print("advdiff3d n=256", flush=True)
+    out, rep = h.action(pr["mats"], pr["t"], 3, dev(pr["v"]), tol=1e-8)
+    o = host(out)
+    assert rel(o[0], X.phi0_separable(pr["mats"], pr["t"], pr["v"])) < 1e-12
+    res = X.recurrence_residual(pr["mats"], pr["t"], pr["v"], o)
+    print(rep["l"], rep["m"], rep["alpha"], res, flush=True)
+    assert max(res) < rep["alpha"] * 1e-8, res
+
+
 # --------------------------------------------------------------------------
 # graph replay of repeated calls (phiq_action, Gauss rule)
 # --------------------------------------------------------------------------
