@@ -395,6 +395,19 @@ int tuned_cfg(phiq_handle h, int kind, const TtmArgs& a) {
   return -1;
 }
 
+// Without a tuned entry: the shapes the autotuner picks at n = 128 (stores:
+// 64 x 128 eight-wave tiles when they fill the GPU, 64 x 64 tiles with
+// 32-deep chunks when they would not; squaring: all orders per block, eight
+// waves), else the kernels' own defaults.
+int fallback_cfg(int kind, const TtmArgs& a) {
+  if (kind == 0 && a.M >= 128) {
+    const long long tiles = (long long)((a.M + 63) / 64) * ((a.L + 127) / 128) * a.nbatch;
+    return tiles < 768 ? 6 : 11;
+  }
+  if (kind == 2 && a.M >= 128 && a.nbatch <= 4 && a.es == 0) return 11;
+  return -1;
+}
+
 int launch_kind(int kind, const TtmArgs& a, phiq_precision prec, hipStream_t st, int cfg) {
   if (kind == 1) return launch_ttm_accum(a, prec, st, cfg);
   if (kind == 2) return launch_ttm_square(a, prec, st, cfg);
@@ -419,7 +432,8 @@ phiq_status L_ttm(phiq_handle h, int cls, const TtmArgs& a0, phiq_precision prec
   }
   ttm_work(a, cls, &fl, &by);
   const int kind = kind_of(cls);
-  const int cfg = (prec != PHIQ_PREC_FP64) ? -1 : (h->force_cfg[kind] >= 0 ? h->force_cfg[kind] : tuned_cfg(h, kind, a));
+  int cfg = (prec != PHIQ_PREC_FP64) ? -1 : (h->force_cfg[kind] >= 0 ? h->force_cfg[kind] : tuned_cfg(h, kind, a));
+  if (prec == PHIQ_PREC_FP64 && cfg < 0) cfg = fallback_cfg(kind, a);
   return prof_launch(h, st, cls, fl, by, [&] { return launch_kind(kind, a, prec, st, cfg); });
 }
 
