@@ -397,13 +397,14 @@ int tuned_cfg(phiq_handle h, int kind, const TtmArgs& a) {
 
 // Without a tuned entry: the shapes the autotuner picks at n = 128 (stores:
 // 64 x 128 eight-wave tiles when they fill the GPU, 64 x 64 tiles with
-// 32-deep chunks when they would not; squaring: all orders per block, eight
-// waves), else the kernels' own defaults.
+// 32-deep chunks when they would not; node sums: 64 x 64, eight waves;
+// squaring: all orders per block, eight waves), else the kernels' defaults.
 int fallback_cfg(int kind, const TtmArgs& a) {
   if (kind == 0 && a.M >= 128) {
     const long long tiles = (long long)((a.M + 63) / 64) * ((a.L + 127) / 128) * a.nbatch;
     return tiles < 768 ? 6 : 11;
   }
+  if (kind == 1 && a.M >= 128) return 6;  // node sum: 64 x 64 tiles, eight waves
   if (kind == 2 && a.M >= 128 && a.nbatch <= 4 && a.es == 0) return 11;
   return -1;
 }
