@@ -1093,20 +1093,18 @@ phiq_status execute_gauss(phiq_plan P, const double* v, double* out, hipStream_t
   const int nb = std::max(P->m + 1, p);
   const size_t tbytes = (P->D > 1 ? (size_t)nb * N * tensor_elem(P) : 0);
   const size_t ybytes = (size_t)p * N * sizeof(double);
-  const size_t t1bytes = (P->D > 1 ? (size_t)N * tensor_elem(P) : 0);
-  const size_t need = 2 * align_up(tbytes) + 2 * align_up(ybytes) + 2 * align_up(t1bytes);
+  const size_t need = 2 * align_up(tbytes) + 2 * align_up(ybytes);
   PHIQ_TRY(ensure(h, h->ws, std::max<size_t>(need, kAlign)));
   char* wb = (char*)h->ws.p;
   void* T0 = wb;
   void* T1 = wb + align_up(tbytes);
   double* Ya = (double*)(wb + 2 * align_up(tbytes));
   double* Yb = (double*)(wb + 2 * align_up(tbytes) + align_up(ybytes));
-  void* T2 = wb + 2 * align_up(tbytes) + 2 * align_up(ybytes);
-  void* T3 = (char*)T2 + align_up(t1bytes);
 
+  // phi_0 runs last, on this stream: on the side stream beside the node
+  // chains it saved no time (both fill the GPU; within 1% at n = 128 and
+  // 256) and slowed every launch it overlapped.
   if (p == 0) return phi0_chain(P, v, out, T0, T1, st);
-  const bool side = P->has_join;  // phi_0 overlaps the quadrature and squaring
-  if (side) PHIQ_TRY(phi0_start(P, v, out, T2, T3, st));
 
   // quadrature: the m node chains as one batch per mode product
   double* E[PHIQ_MAX_DIM];
@@ -1129,7 +1127,6 @@ phiq_status execute_gauss(phiq_plan P, const double* v, double* out, hipStream_t
   }
   if (P->l > 0) PHIQ_TRY(squaring(P, Ya, Yb, out + N, T0, T1, st));
   // phi_0 = (exp(-tA^0) (x) exp(-tA^1) ...) v
-  if (side) return phi0_finish(P, st);
   return phi0_chain(P, v, out, T0, T1, st);
 }
 
