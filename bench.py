@@ -102,10 +102,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--workload", default="advdiff3d",
-                    choices=["advdiff3d", "batch512", "etdrk4", "precision256", "problem1", "problem3"],
+                    choices=["advdiff3d", "batch512", "etdrk4", "precision256", "problem1", "problem3", "seeds"],
                     help="advdiff3d: one 3D problem (default); batch512: 512 mixed 2D/3D problems in one "
                          "batched call (phiq_action_batched); etdrk4: 100 ETD-RK4 steps of Allen-Cahn on 3D n=128")
-    ap.add_argument("--count", type=int, default=512, help="batch512: number of problems")
+    ap.add_argument("--count", type=int, default=None,
+                    help="batch512: number of problems (default 512); seeds: number of coefficient draws (default 16)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the steps, negate a buffer of this many MiB into another once (a plain device copy "
                          "of known size that calibrates hardware byte counters taken over the same run)")
@@ -129,6 +130,8 @@ def main():
         return bench_problem1(args, rank)
     if args.workload == "problem3":
         return bench_problem3(args, rank)
+    if args.workload == "seeds":
+        return bench_seeds(args, rank)
 
     from paper_2211_00696_amd import inputs, phiq
 
@@ -300,7 +303,7 @@ def bench_batch(args, rank):
 
     from paper_2211_00696_amd import inputs, phiq
 
-    probs = inputs.batch_mix(seed=args.seed, count=args.count)
+    probs = inputs.batch_mix(seed=args.seed, count=args.count or 512)
     Ns = [p["v"].size for p in probs]
     Ntot = int(sum(Ns))
     vbuf = torch.empty(Ntot, dtype=torch.float64, device="cuda")
@@ -540,6 +543,42 @@ def bench_problem3(args, rank):
         print(json.dumps({"metric": "Problem 3 (Section 5) total time of an exponential Runge-Kutta run, T = 1",
                           "unit": "s", "note": "paper: serial MATLAB on one thread of an Intel i5-8279U "
                           "(context, another machine); tol 1e-14 as in the paper", "rows": rows}), flush=True)
+
+
+def bench_seeds(args, rank):
+    """The 3D n=128 benchmark over the coefficient draws of seeds 0..count-1 (--count, default 16):
+    per seed the plan and the time of a full phiq_action (Gauss and Clenshaw-Curtis), and the medians."""
+    import torch
+
+    from paper_2211_00696_amd import inputs, phiq
+
+    count = args.count or 16
+    h = phiq.Handle(0)
+    rows = []
+    for seed in range(count):
+        pr = inputs.problem("advdiff3d", seed=seed, n=args.n)
+        N = pr["v"].size
+        v = torch.from_numpy(pr["v"]).cuda()
+        out = torch.empty((pr["p"] + 1, N), dtype=torch.float64, device="cuda")
+        row = dict(seed=seed, coefficients=pr["coef"])
+        for rule in ("gauss", "cc"):
+            for _ in range(2):
+                _, rep = h.action(pr["mats"], pr["t"], pr["p"], v, tol=pr["tol"], out=out, rule=rule)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                h.action(pr["mats"], pr["t"], pr["p"], v, tol=pr["tol"], out=out, rule=rule)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / args.steps
+            row[rule] = dict(ms=ms, grid_pts_per_s=N / (ms * 1e-3), l=rep["l"], m=rep["m"], alpha=rep["alpha"])
+        rows.append(row)
+        print(json.dumps(row), file=sys.stderr, flush=True)
+    h.close()
+    med = {r: float(np.median([row[r]["grid_pts_per_s"] for row in rows])) for r in ("gauss", "cc")}
+    if rank == 0:
+        print(json.dumps({"metric": "phi_k(tA)v grid-pts/s over coefficient draws, 3D n=%d" % args.n,
+                          "unit": "grid-pts/s", "seeds": count, "steps": args.steps, "median": med,
+                          "rows": rows}), flush=True)
 
 
 def bench_etd(args, rank):
