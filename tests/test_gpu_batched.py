@@ -114,6 +114,21 @@ def test_batched_mixed_sizes_sampled_oracle(h):
     run_and_check(h, probs, oracle_idx=set(small))
 
 
+def test_batched_wide_tiles(h):
+    """Problems with n >= 96 (64 x 128 store tiles) and n >= 64 (eight-wave
+    node sums and squaring) next to small ones, ragged n included."""
+    rng = np.random.default_rng(23)
+    cases = [(2, 96, 3, 1e-3), (2, 130, 2, 5e-4), (2, 160, 4, 2e-3), (3, 100, 3, 1e-3), (3, 128, 1, 1e-3),
+             (3, 64, 4, 1e-2), (2, 70, 2, 1e-2), (3, 12, 3, 1e-2)]
+    probs = []
+    for dim, n, p, t in cases:
+        a, b = I.draw_coefficients(rng, dim)
+        mats = [I.adv_diff_1d(n, float(a[d]), float(b[d])) for d in range(dim)]
+        probs.append(dict(mats=mats, t=t, p=p, tol=1e-8, vh=rng.standard_normal((1, n ** dim)),
+                          name=f"dim{dim} n{n} p{p}"))
+    run_and_check(h, probs, oracle_idx={0, 1, 2, 6, 7})
+
+
 def test_batched_arena_reuse_smaller_second_call(h):
     probs = small_mix()
     run_and_check(h, probs[:6], oracle_idx={0})
