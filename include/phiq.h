@@ -53,7 +53,7 @@ typedef enum {
   PHIQ_ERR_NOT_CONVERGED = -3, /* adaptive Clenshaw-Curtis hit its cap        */
   PHIQ_ERR_OOM = -4,           /* device allocation failed or over the cap    */
   PHIQ_ERR_HIP = -5,           /* a HIP runtime call failed                   */
-  PHIQ_ERR_UNSUPPORTED = -6    /* valid request this build does not implement */
+  PHIQ_ERR_UNSUPPORTED = -6    /* valid request the library does not implement */
 } phiq_status;
 
 /* Quadrature rule of the integral form (the `type` input of phiquadmv):
