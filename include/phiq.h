@@ -104,6 +104,13 @@ typedef struct {
                             /* or PHIQ_SEL_MLP (the handle's network, see           */
                             /* phiq_selector_set; the bound judges its choice and   */
                             /* Algorithm setup_quadrature is the fallback)          */
+  int slab_products;        /* FP64, three axes with n_1 = n_2 = 128: the products  */
+                            /* along axes 2 and 1 in one pass per 128 x 128 slab    */
+                            /* (the same sums, the k-loops associated otherwise)    */
+                            /* for 1 chains of one vector (phi_0, single terms of a */
+                            /* combination), 2 every chain, 0 none (default: on     */
+                            /* gfx950 at n = 128 it saved no time in a phi-action   */
+                            /* and cost 3% in ETD-RK4)                              */
 } phiq_options;
 
 /* What a plan / call did.  Times are filled by phiq_action only. */

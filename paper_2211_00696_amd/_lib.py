@@ -20,7 +20,8 @@ STATUS = {
     -6: "PHIQ_ERR_UNSUPPORTED",
 }
 RULE = {"gauss": 1, "cc": 2}
-PROFILE_CLASSES = ["ttm_store", "ttm_accum", "ttm_square", "gemm", "taylor", "scale", "node_sum", "absdiff"]
+PROFILE_CLASSES = ["ttm_store", "ttm_accum", "ttm_square", "gemm", "taylor", "scale", "node_sum", "absdiff", "slice",
+                   "ttm_slab"]
 PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2, "int8": 3}
 SELECTOR = {"paper": 0, "mlp": 1}
 
@@ -74,6 +75,7 @@ class Options(ctypes.Structure):
         ("workspace_cap", c_size_t),
         ("use_graphs", c_int),
         ("selector", c_int),
+        ("slab_products", c_int),
     ]
 
 

@@ -4,13 +4,14 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libphiq.so")
 
-SOURCES = ["kernels.hip", "kernels_lowp.hip", "kernels_i8.hip", "batched.hip", "etd.hip", "exprk.hip", "mlp.hip", "planner.cpp", "api.cpp", "batched.cpp",
+SOURCES = ["kernels.hip", "kernels_slab.hip", "kernels_lowp.hip", "kernels_i8.hip", "batched.hip", "etd.hip", "exprk.hip", "mlp.hip", "planner.cpp", "api.cpp", "batched.cpp",
            "etd.cpp", "exprk.cpp", "mlp.cpp"]
 
 HIPCC_FLAGS = [
@@ -34,16 +35,31 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, *srcs, "-o", tmp]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
+    return res.returncode
+
+
+def build(verbose: bool = False, jobs: int = 8) -> str:
+    """Compile every source to an object in _build/ (in parallel), then link."""
+    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    objdir = os.path.join(ROOT, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    compile_flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    objs = [os.path.join(objdir, s.replace(".", "_") + ".o") for s in srcs]
+    cmds = [[hipcc(), *compile_flags, *inc, "-c", os.path.join(CSRC, s), "-o", o] for s, o in zip(srcs, objs)]
+    with ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
+        codes = list(ex.map(lambda c: _run(c, verbose), cmds))
+    if any(codes):
         raise RuntimeError("hipcc failed building libphiq.so")
+    tmp = LIB + ".tmp"
+    if _run([hipcc(), "--offload-arch=gfx950", "-fPIC", "-shared", *objs, "-o", tmp], verbose):
+        raise RuntimeError("hipcc failed linking libphiq.so")
     os.replace(tmp, LIB)
     return LIB
 

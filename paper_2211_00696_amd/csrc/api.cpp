@@ -178,8 +178,8 @@ struct Profiler {
   size_t next = 0;
 };
 
-static const char* const kProfClass[] = {"ttm_store", "ttm_accum", "ttm_square", "gemm", "taylor",
-                                         "scale",     "node_sum",  "absdiff",    "slice"};
+static const char* const kProfClass[] = {"ttm_store", "ttm_accum", "ttm_square", "gemm",  "taylor",
+                                         "scale",     "node_sum",  "absdiff",    "slice", "ttm_slab"};
 enum ProfClass {
   K_TTM_STORE = 0,
   K_TTM_ACCUM,
@@ -189,7 +189,8 @@ enum ProfClass {
   K_SCALE,
   K_NODE_SUM,
   K_ABSDIFF,
-  K_SLICE,  // int8 digit slicing of factors and tensors
+  K_SLICE,     // int8 digit slicing of factors and tensors
+  K_TTM_SLAB,  // products along axes 2 and 1 in one pass (kernels_slab.hip)
   K_NCLASS
 };
 
@@ -969,6 +970,7 @@ struct Front {
   const void* X;
   long long xs;
   int f32;  // X holds FP32 values
+  int nn;   // X is in the natural layout (after the slab product)
 };
 
 inline bool lowp(const phiq_plan_s* P) { return twin_prec(P->opt.precision); }
@@ -981,7 +983,39 @@ inline const void* elem_offset(const void* X, long long elems, int f32) {
 // input of the final product over axis 0.  X is FP64; the intermediates T0
 // and T1 are FP32 when a lower precision is selected.
 phiq_status chain_front(const phiq_plan_s* P, const double* X, long long xs, double* const* Ebase, long long const* es,
-                        int nb, void* T0, void* T1, hipStream_t st, Front* f) {
+                        int nb, void* T0, void* T1, hipStream_t st, Front* f, bool beside = false) {
+  // 1: single-vector chains only (with a batch the per-axis kernels keep more
+  // waves per CU busy and were faster at n = 128), and not beside other work
+  // on a side stream, where a block that takes a whole CU's LDS waits for a
+  // free CU
+  const int sp = P->opt.slab_products;
+  if (P->D == 3 && P->n[1] == kSlabN && P->n[2] == kSlabN && P->opt.precision == PHIQ_PREC_FP64 &&
+      (sp == 2 || (sp == 1 && nb == 1 && !beside))) {
+    SlabArgs s{};
+    s.X = X;
+    s.xs = xs;
+    s.E1 = Ebase[1];
+    s.es1 = es[1];
+    s.E2 = Ebase[2];
+    s.es2 = es[2];
+    s.O = (double*)T0;
+    s.os = P->N;
+    s.n0 = P->n[0];
+    s.nbatch = nb;
+    if (slab2_supported(s)) {
+      const double slabs = (double)s.n0 * nb;
+      const double S3 = (double)kSlabN * kSlabN * kSlabN;
+      // two 128-deep contractions per element; X read (once when shared), O written, the factors read
+      const double bytes = 8.0 * ((xs == 0 ? (double)P->N : slabs * kSlabN * kSlabN) + slabs * kSlabN * kSlabN +
+                                  (double)kSlabN * kSlabN * ((es[1] ? nb : 1) + (es[2] ? nb : 1)));
+      PHIQ_TRY(prof_launch(P->h, st, K_TTM_SLAB, 4.0 * S3 * slabs, bytes, [&] { return launch_slab2(s, st); }));
+      f->X = T0;
+      f->xs = P->N;
+      f->f32 = 0;
+      f->nn = 1;
+      return PHIQ_OK;
+    }
+  }
   const void* cur = X;
   long long cxs = xs;
   int cur_f32 = 0;
@@ -1007,6 +1041,7 @@ phiq_status chain_front(const phiq_plan_s* P, const double* X, long long xs, dou
   f->X = cur;
   f->xs = cxs;
   f->f32 = cur_f32;
+  f->nn = 0;
   return PHIQ_OK;
 }
 
@@ -1017,6 +1052,7 @@ TtmArgs final_args(const phiq_plan_s* P, const double* E, long long es, const Fr
   a.X = f.X;
   a.xs = f.xs;
   a.x_f32 = f.f32;
+  a.nn = f.nn;
   a.o_f32 = 0;
   a.M = a.K = P->n[0];
   a.L = (int)(P->N / P->n[0]);
@@ -1034,7 +1070,7 @@ phiq_status phi0_chain(const phiq_plan_s* P, const double* v, double* out0, void
     es[d] = 0;
   }
   Front f;
-  PHIQ_TRY(chain_front(P, v, 0, E, es, 1, T0, T1, st, &f));
+  PHIQ_TRY(chain_front(P, v, 0, E, es, 1, T0, T1, st, &f, side));
   TtmArgs a = final_args(P, P->Ephi0[0], 0, f, 1);
   a.O = out0;
   a.os = 0;
@@ -1723,6 +1759,7 @@ phiq_status phiq_options_default(phiq_options* o) {
   o->workspace_cap = 0;
   o->use_graphs = 0;
   o->selector = PHIQ_SEL_PAPER;
+  o->slab_products = 0;
   return PHIQ_OK;
 }
 

@@ -56,14 +56,14 @@ __device__ __forceinline__ bool tile_of_block(int M, int L, int nb, int& m0, int
   return true;
 }
 
-template <class C, bool VEC>
+template <class C, bool VEC, bool NN = false>
 __global__ __launch_bounds__(C::NT, C::MINW) void ttm_store_kernel(TtmArgs a) {
   __shared__ double smem[2 * (C::BM + C::BN) * C::LDK];
   int m0, n0, b;
   if (!tile_of_block<C>(a.M, a.L, a.nbatch, m0, n0, b)) return;
   d4 acc[C::TM][C::TN];
   zero_acc<C>(acc);
-  tile_nt_db<C, VEC>(a.E + b * a.es, (const double*)a.X + b * a.xs, a.M, a.K, a.L, m0, n0, smem, acc);
+  tile_nt_db<C, VEC, NN>(a.E + b * a.es, (const double*)a.X + b * a.xs, a.M, a.K, a.L, m0, n0, smem, acc);
   double* O = (double*)a.O + b * a.os;
 #pragma unroll
   for (int i = 0; i < C::TM; ++i)
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(C::NT, C::MINW) void ttm_store_kernel(TtmArgs a) {
 
 // Node sum fused into the last mode product: every block loops over all
 // nodes b and keeps the NP running sums in registers.
-template <class C, int NP, bool VEC>
+template <class C, int NP, bool VEC, bool NN = false>
 __global__ __launch_bounds__(C::NT, C::MINW) void ttm_accum_kernel(TtmArgs a) {
   __shared__ double smem[2 * (C::BM + C::BN) * C::LDK];
   int m0, n0, bb;
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(C::NT, C::MINW) void ttm_accum_kernel(TtmArgs a) {
   for (int b = 0; b < a.nbatch; ++b) {
     d4 acc[C::TM][C::TN];
     zero_acc<C>(acc);
-    tile_nt_db<C, VEC>(a.E + b * a.es, (const double*)a.X + b * a.xs, a.M, a.K, a.L, m0, n0, smem, acc);
+    tile_nt_db<C, VEC, NN>(a.E + b * a.es, (const double*)a.X + b * a.xs, a.M, a.K, a.L, m0, n0, smem, acc);
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
       const double w = ldexp(a.coef[q * a.ldcoef + b], a.cexp);
@@ -124,14 +124,14 @@ __global__ __launch_bounds__(C::NT, C::MINW) void ttm_accum_kernel(TtmArgs a) {
 // Modified squaring fused into the last mode product (eq. squaring):
 // batch b is order i = b+1+order0, out = 2^{-i} (E y_i + sum_{j=1}^{i} y_j/(i-j)!),
 // added to out when yacc is set.
-template <class C, bool VEC>
+template <class C, bool VEC, bool NN = false>
 __global__ __launch_bounds__(C::NT, C::MINW) void ttm_square_kernel(TtmArgs a) {
   __shared__ double smem[2 * (C::BM + C::BN) * C::LDK];
   int m0, n0, b;
   if (!tile_of_block<C>(a.M, a.L, a.nbatch, m0, n0, b)) return;
   d4 acc[C::TM][C::TN];
   zero_acc<C>(acc);
-  tile_nt_db<C, VEC>(a.E + b * a.es, (const double*)a.X + b * a.xs, a.M, a.K, a.L, m0, n0, smem, acc);
+  tile_nt_db<C, VEC, NN>(a.E + b * a.es, (const double*)a.X + b * a.xs, a.M, a.K, a.L, m0, n0, smem, acc);
   const int order = b + 1 + a.order0;
   const double scale = ldexp(1.0, -order);
   double* O = (double*)a.O + b * a.os;
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(C::NT, C::MINW) void ttm_square_kernel(TtmArgs a) {
 // All p orders of one modified-squaring step in one block (p <= 4): the
 // block computes E y_i for i = 1..p in turn and reads every y_j tile once,
 // keeping it in registers for the later orders.  Same factor E for all i.
-template <class C, int NP, bool VEC>
+template <class C, int NP, bool VEC, bool NN = false>
 __global__ __launch_bounds__(C::NT, C::MINW) void ttm_square_all_kernel(TtmArgs a) {
   __shared__ double smem[2 * (C::BM + C::BN) * C::LDK];
   int m0, n0, bb;
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(C::NT, C::MINW) void ttm_square_all_kernel(TtmArgs 
       }
     d4 acc[C::TM][C::TN];
     zero_acc<C>(acc);
-    tile_nt_db<C, VEC>(a.E, (const double*)a.X + i * a.xs, a.M, a.K, a.L, m0, n0, smem, acc);
+    tile_nt_db<C, VEC, NN>(a.E, (const double*)a.X + i * a.xs, a.M, a.K, a.L, m0, n0, smem, acc);
     const double scale = ldexp(1.0, -(i + 1));
     double* O = (double*)a.O + i * a.os;
 #pragma unroll
@@ -375,8 +375,10 @@ dim3 ttm_grid(const TtmArgs& a, int nb) {
 }
 
 // 16-byte vector loads need even row lengths and 16-byte aligned operands
+// (natural layout: X rows have L elements)
 bool vec_ok(const TtmArgs& a) {
-  return (a.K % 2 == 0) && (((uintptr_t)a.E | (uintptr_t)a.X) % 16 == 0) && (a.es % 2 == 0) && (a.xs % 2 == 0);
+  return (a.K % 2 == 0) && (!a.nn || a.L % 2 == 0) && (((uintptr_t)a.E | (uintptr_t)a.X) % 16 == 0) &&
+         (a.es % 2 == 0) && (a.xs % 2 == 0);
 }
 
 template <class C>
@@ -411,6 +413,60 @@ int accum_cfg(const TtmArgs& a, hipStream_t st) {
   return vec_ok(a) ? accum_np<C, true>(a, st) : accum_np<C, false>(a, st);
 }
 
+// Last product after the slab product (X in its natural layout): fixed
+// shapes, those the autotuner picks for the rotated kernels at n = 128.
+template <class C>
+int store_nn(const TtmArgs& a, hipStream_t st) {
+  if (vec_ok(a))
+    PHIQ_LAUNCH((ttm_store_kernel<C, true, true>), ttm_grid<C>(a, a.nbatch), dim3(C::NT), 0, st, a);
+  else
+    PHIQ_LAUNCH((ttm_store_kernel<C, false, true>), ttm_grid<C>(a, a.nbatch), dim3(C::NT), 0, st, a);
+  return hipGetLastError();
+}
+template <class C, bool VEC>
+int accum_nn_v(const TtmArgs& a, hipStream_t st) {
+  static_assert(C::BM == Tile64p1w8::BM && C::BN == Tile64p1w8::BN && C::NT == Tile64p1w8::NT, "same grid");
+  const dim3 g = ttm_grid<C>(a, 1);
+  switch (a.np) {
+    case 1: PHIQ_LAUNCH((ttm_accum_kernel<C, 1, VEC, true>), g, dim3(C::NT), 0, st, a); break;
+    case 2: PHIQ_LAUNCH((ttm_accum_kernel<C, 2, VEC, true>), g, dim3(C::NT), 0, st, a); break;
+    case 3: PHIQ_LAUNCH((ttm_accum_kernel<C, 3, VEC, true>), g, dim3(C::NT), 0, st, a); break;
+    // four running sums do not fit in 128 registers
+    default: PHIQ_LAUNCH((ttm_accum_kernel<Tile64p1w8, 4, VEC, true>), g, dim3(C::NT), 0, st, a); break;
+  }
+  return hipGetLastError();
+}
+template <class C>
+int square_nn(const TtmArgs& a, hipStream_t st) {
+  if (vec_ok(a))
+    PHIQ_LAUNCH((ttm_square_kernel<C, true, true>), ttm_grid<C>(a, a.nbatch), dim3(C::NT), 0, st, a);
+  else
+    PHIQ_LAUNCH((ttm_square_kernel<C, false, true>), ttm_grid<C>(a, a.nbatch), dim3(C::NT), 0, st, a);
+  return hipGetLastError();
+}
+template <class C, bool VEC>
+int square_all_nn_v(const TtmArgs& a, hipStream_t st) {
+  const dim3 g = ttm_grid<C>(a, 1);
+  switch (a.nbatch) {
+    case 1: PHIQ_LAUNCH((ttm_square_all_kernel<C, 1, VEC, true>), g, dim3(C::NT), 0, st, a); break;
+    case 2: PHIQ_LAUNCH((ttm_square_all_kernel<C, 2, VEC, true>), g, dim3(C::NT), 0, st, a); break;
+    case 3: PHIQ_LAUNCH((ttm_square_all_kernel<C, 3, VEC, true>), g, dim3(C::NT), 0, st, a); break;
+    default: PHIQ_LAUNCH((ttm_square_all_kernel<Tile64p1w8, 4, VEC, true>), g, dim3(C::NT), 0, st, a); break;
+  }
+  return hipGetLastError();
+}
+int launch_nn(int kind, const TtmArgs& a, hipStream_t st) {
+  const bool v = vec_ok(a);
+  if (kind == 1) return v ? accum_nn_v<Tile64p1w8m2, true>(a, st) : accum_nn_v<Tile64p1w8m2, false>(a, st);
+  if (kind == 2) {
+    if (a.order0 != 0 || a.yacc || a.nbatch > 4 || a.es != 0) return square_nn<Tile64x128>(a, st);
+    return v ? square_all_nn_v<Tile64p1w8m2, true>(a, st) : square_all_nn_v<Tile64p1w8m2, false>(a, st);
+  }
+  // too few 64 x 128 tiles to fill the GPU three blocks per CU: 64 x 64, 32-deep chunks
+  return ttm_tiles<Tile64x128p1w8>(a.M, a.L, a.nbatch) < 768 ? store_nn<Tile64k32>(a, st)
+                                                              : store_nn<Tile64x128p1w8>(a, st);
+}
+
 // default tile choice when no tuned entry exists (from sweeps on gfx950 at
 // n = 32, 128, 256: 64 x 128 tiles for the stores, 64 x 64 with 32-deep K
 // chunks for small n, for the node sum and, with all orders per block, for
@@ -425,8 +481,9 @@ int default_cfg(int kind, int M, int nb) {
 int ttm_num_configs(int kind) { return kind == 1 ? 7 : (kind == 2 ? 12 : 14); }
 
 int launch_ttm_store(const TtmArgs& a, phiq_precision prec, void* stream, int cfg) {
-  if (prec != PHIQ_PREC_FP64) return launch_ttm_store_lowp(a, prec, stream);
+  if (prec != PHIQ_PREC_FP64) return a.nn ? hipErrorInvalidValue : launch_ttm_store_lowp(a, prec, stream);
   hipStream_t st = (hipStream_t)stream;
+  if (a.nn) return launch_nn(0, a, st);
   if (cfg < 0) cfg = default_cfg(0, a.M, a.nbatch);
   switch (cfg) {
     case 0: return store_cfg<Tile64>(a, st);
@@ -449,8 +506,9 @@ int launch_ttm_store(const TtmArgs& a, phiq_precision prec, void* stream, int cf
 
 int launch_ttm_accum(const TtmArgs& a, phiq_precision prec, void* stream, int cfg) {
   if (a.np > 4 || a.np < 1) return hipErrorInvalidValue;
-  if (prec != PHIQ_PREC_FP64) return launch_ttm_accum_lowp(a, prec, stream);
+  if (prec != PHIQ_PREC_FP64) return a.nn ? hipErrorInvalidValue : launch_ttm_accum_lowp(a, prec, stream);
   hipStream_t st = (hipStream_t)stream;
+  if (a.nn) return launch_nn(1, a, st);
   if (cfg < 0) cfg = default_cfg(1, a.M, a.nbatch);
   switch (cfg) {
     case 0: return accum_cfg<Tile64>(a, st);
@@ -483,8 +541,9 @@ int square_all_cfg(const TtmArgs& a, hipStream_t st) {
 }  // namespace
 
 int launch_ttm_square(const TtmArgs& a, phiq_precision prec, void* stream, int cfg) {
-  if (prec != PHIQ_PREC_FP64) return launch_ttm_square_lowp(a, prec, stream);
+  if (prec != PHIQ_PREC_FP64) return a.nn ? hipErrorInvalidValue : launch_ttm_square_lowp(a, prec, stream);
   hipStream_t st = (hipStream_t)stream;
+  if (a.nn) return launch_nn(2, a, st);
   // an order offset or an accumulating store needs the per-order kernel
   if ((a.order0 != 0 || a.yacc) && (cfg < 0 || cfg >= 7)) cfg = a.M >= 128 ? 5 : 6;
   if (cfg < 0) cfg = default_cfg(2, a.M, a.nbatch);

@@ -145,7 +145,9 @@ struct TaylorJob {
 // original layout after D steps.  Batch b uses E + b*es, X + b*xs, O + b*os.
 // X and O are FP64 for the FP64 path; with a lower precision the
 // intermediate tensors between mode products are FP32 (x_f32 / o_f32 say
-// which side is FP32; strides are in elements).
+// which side is FP32; strides are in elements).  With nn set (FP64 only)
+// X is read in its natural layout instead, X[k * L + j]: the last product
+// after the two-axis slab product, which leaves the layout unchanged.
 struct TtmArgs {
   const double* E;
   long long es;
@@ -158,6 +160,7 @@ struct TtmArgs {
   void* O;
   long long os;
   int x_f32, o_f32;
+  int nn;
   int M, K, L, nbatch;
   // node-sum epilogue: Y + j*ys = sum_b 2^cexp coef[j * ldcoef + b] * C_b, j < np
   const double* coef;
@@ -188,6 +191,26 @@ int ttm_num_configs(int kind);
 int launch_ttm_store(const TtmArgs& a, phiq_precision prec, void* stream, int cfg);
 int launch_ttm_accum(const TtmArgs& a, phiq_precision prec, void* stream, int cfg);
 int launch_ttm_square(const TtmArgs& a, phiq_precision prec, void* stream, int cfg);
+
+// Products along axes 2 and 1 of nbatch tensors n0 x kSlabN x kSlabN in one
+// pass (kernels_slab.hip), layout unchanged:
+//   O_b[i0][j1][j2] = sum_{k1,k2} E1_b[j1][k1] E2_b[j2][k2] X_b[i0][k1][k2],
+// batch b at X + b*xs, E1 + b*es1, E2 + b*es2, O + b*os (FP64; X, E1, E2
+// 16-byte aligned, strides even).
+constexpr int kSlabN = 128;
+struct SlabArgs {
+  const double* X;
+  long long xs;
+  const double* E1;
+  long long es1;
+  const double* E2;
+  long long es2;
+  double* O;
+  long long os;
+  int n0, nbatch;
+};
+bool slab2_supported(const SlabArgs& a);
+int launch_slab2(const SlabArgs& a, void* stream);
 // FP32-MFMA and split-bf16 (3-product) versions (kernels_lowp.hip)
 // dst = src converted to FP32 (a) or split into bf16 hi (a) and lo (b)
 int launch_convert(const double* src, long long count, phiq_precision prec, void* a, void* b, void* stream);

@@ -51,6 +51,7 @@ using Tile64x128p1w8 = Tile<64, 128, 16, 2, 4, 1>;
 using Tile128p1w8 = Tile<128, 64, 16, 4, 2, 1>;
 using Tile128x128p1 = Tile<128, 128, 16, 2, 2, 1, 2>;
 using Tile64p1w8 = Tile<64, 64, 16, 2, 4, 1>;
+using Tile64p1w8m2 = Tile<64, 64, 16, 2, 4, 1, 4>;  // the same within 128 registers: two blocks per CU
 
 // ---------------------------------------------------------------------------
 // Staging of rows [r0, r0+ROWS) x k-chunk [k0, k0+BK) of a row-major matrix
@@ -130,6 +131,32 @@ __device__ __forceinline__ void load_nmajor(const double* __restrict__ g, long l
     reg[i] = ok ? v : 0.0;
   }
 }
+// The same with pairs of columns per lane (ld and c0 even, 16-byte aligned
+// base; cols_valid even, so a pair is valid or invalid as a whole).
+template <int COLS, int BK, int NT, int PER>
+__device__ __forceinline__ void load_nmajor_v(const double* __restrict__ g, long long ld, int c0, int cols_valid,
+                                              int k0, int k_valid, double (&reg)[PER]) {
+#pragma unroll
+  for (int i = 0; i < PER / 2; ++i) {
+    const int e = threadIdx.x + i * NT;
+    const int kk = e / (COLS / 2), c = 2 * (e % (COLS / 2));
+    const int k = k0 + kk, col = c0 + c;
+    const bool ok = col < cols_valid && k < k_valid;
+    const d2 v = *(const d2*)(g + (long long)(ok ? k : 0) * ld + (ok ? col : 0));
+    reg[2 * i] = ok ? v.x : 0.0;
+    reg[2 * i + 1] = ok ? v.y : 0.0;
+  }
+}
+template <int COLS, int NT, int PER, int LDK>
+__device__ __forceinline__ void store_nmajor_v(double* s, const double (&reg)[PER]) {
+#pragma unroll
+  for (int i = 0; i < PER / 2; ++i) {
+    const int e = threadIdx.x + i * NT;
+    const int kk = e / (COLS / 2), c = 2 * (e % (COLS / 2));
+    s[c * LDK + kk] = reg[2 * i];
+    s[(c + 1) * LDK + kk] = reg[2 * i + 1];
+  }
+}
 template <int COLS, int NT, int PER, int LDK>
 __device__ __forceinline__ void store_nmajor(double* s, const double (&reg)[PER]) {
 #pragma unroll
@@ -199,24 +226,41 @@ __device__ __forceinline__ int acc_col(int j) {
   return (wave % C::WAVES_N) * C::WN + 16 * j + (lane & 15);
 }
 
-// acc += E[m0:m0+BM, :] X[n0:n0+BN, :]^T (E: M x K, X: L x K, row-major):
-// register prefetch two chunks ahead and a double-buffered LDS tile, one
-// barrier per K-chunk.  smem holds 2 (BM + BN) LDK doubles and is free when
-// the call returns.
+// acc += E[m0:m0+BM, :] X[n0:n0+BN, :]^T (E: M x K, X: L x K, row-major;
+// with NN, X is K x L instead, element (j, k) at X[k * L + j]): register
+// prefetch two chunks ahead and a double-buffered LDS tile, one barrier per
+// K-chunk.  smem holds 2 (BM + BN) LDK doubles and is free when the call
+// returns.
 
-template <class C, bool VEC>
+template <class C, bool VEC, bool NN = false>
 __device__ __forceinline__ void tile_nt_db(const double* __restrict__ E, const double* __restrict__ X, int M, int K,
                                            int L, int m0, int n0, double* smem, d4 (&acc)[C::TM][C::TN]) {
   constexpr int STAGE = (C::BM + C::BN) * C::LDK;
   double ra[C::A_PER], rb[C::B_PER];
   const int nch = (K + C::BK - 1) / C::BK;
+  auto load_b = [&](int k0) {
+    if constexpr (NN && VEC)
+      load_nmajor_v<C::BN, C::BK, C::NT, C::B_PER>(X, L, n0, L, k0, K, rb);
+    else if constexpr (NN)
+      load_nmajor<C::BN, C::BK, C::NT, C::B_PER>(X, L, n0, L, k0, K, rb);
+    else
+      load_kmajor<C::BN, C::BK, C::NT, C::B_PER, VEC>(X, K, n0, L, k0, K, rb);
+  };
+  auto store_b = [&](double* s, int k0) {
+    if constexpr (NN && VEC)
+      store_nmajor_v<C::BN, C::NT, C::B_PER, C::LDK>(s, rb);
+    else if constexpr (NN)
+      store_nmajor<C::BN, C::NT, C::B_PER, C::LDK>(s, rb);
+    else
+      store_kmajor<C::BK, C::NT, C::B_PER, C::LDK, VEC, false>(s, rb, k0, K);
+  };
   load_kmajor<C::BM, C::BK, C::NT, C::A_PER, VEC>(E, K, m0, M, 0, K, ra);
-  load_kmajor<C::BN, C::BK, C::NT, C::B_PER, VEC>(X, K, n0, L, 0, K, rb);
+  load_b(0);
   store_kmajor<C::BK, C::NT, C::A_PER, C::LDK, VEC, true>(smem, ra, 0, K);
-  store_kmajor<C::BK, C::NT, C::B_PER, C::LDK, VEC, false>(smem + C::BM * C::LDK, rb, 0, K);
+  store_b(smem + C::BM * C::LDK, 0);
   if (nch > 1) {
     load_kmajor<C::BM, C::BK, C::NT, C::A_PER, VEC>(E, K, m0, M, C::BK, K, ra);
-    load_kmajor<C::BN, C::BK, C::NT, C::B_PER, VEC>(X, K, n0, L, C::BK, K, rb);
+    load_b(C::BK);
   }
   __syncthreads();
   for (int c = 0; c < nch; ++c) {
@@ -225,10 +269,10 @@ __device__ __forceinline__ void tile_nt_db(const double* __restrict__ E, const d
     if (c + 1 < nch) {
       // readers of nxt (chunk c-1) passed the barrier at the end of c-1
       store_kmajor<C::BK, C::NT, C::A_PER, C::LDK, VEC, true>(nxt, ra, (c + 1) * C::BK, K);
-      store_kmajor<C::BK, C::NT, C::B_PER, C::LDK, VEC, false>(nxt + C::BM * C::LDK, rb, (c + 1) * C::BK, K);
+      store_b(nxt + C::BM * C::LDK, (c + 1) * C::BK);
       if (c + 2 < nch) {
         load_kmajor<C::BM, C::BK, C::NT, C::A_PER, VEC>(E, K, m0, M, (c + 2) * C::BK, K, ra);
-        load_kmajor<C::BN, C::BK, C::NT, C::B_PER, VEC>(X, K, n0, L, (c + 2) * C::BK, K, rb);
+        load_b((c + 2) * C::BK);
       }
     }
     mma_chunk<C>(cur, cur + C::BM * C::LDK, acc);

@@ -72,7 +72,7 @@ class _Op:
 
 
 def options(rule="gauss", precision="fp64", l=None, m=None, alpha=None, c1=None, c2=None,
-            cc_max_doublings=None, workspace_cap=None, use_graphs=None, selector=None):
+            cc_max_doublings=None, workspace_cap=None, use_graphs=None, selector=None, slab_products=None):
     lib = L.load()
     o = L.Options()
     _check(lib.phiq_options_default(byref(o)), "phiq_options_default")
@@ -96,6 +96,8 @@ def options(rule="gauss", precision="fp64", l=None, m=None, alpha=None, c1=None,
         o.use_graphs = int(bool(use_graphs))
     if selector is not None:
         o.selector = L.SELECTOR[selector]
+    if slab_products is not None:
+        o.slab_products = int(slab_products)
     return o
 
 
