@@ -101,6 +101,9 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--slab-products", type=int, default=0, choices=[0, 1, 2],
+                    help="phiq_options.slab_products: 0 one axis per pass (default), "
+                         "1 two-axis slab products for single-vector chains, 2 for every chain")
     ap.add_argument("--workload", default="advdiff3d",
                     choices=["advdiff3d", "batch512", "etdrk4", "precision256", "problem1", "problem3", "seeds"],
                     help="advdiff3d: one 3D problem (default); batch512: 512 mixed 2D/3D problems in one "
@@ -144,7 +147,7 @@ def main():
     out = torch.empty((p + 1, N), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
     h = phiq.Handle(0)
-    opts = dict(rule=args.rule, precision=args.precision)
+    opts = dict(rule=args.rule, precision=args.precision, slab_products=args.slab_products)
     if args.copy_probe_mib > 0:
         src = torch.ones(args.copy_probe_mib << 17, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
@@ -244,7 +247,7 @@ def main():
                         % (args.n, N, args.seed, "Gauss-Legendre" if args.rule == "gauss" else "adaptive Clenshaw-Curtis",
                            args.precision.upper()),
             "n": args.n, "N": N, "p": p, "t": pr["t"], "tol": pr["tol"], "rule": args.rule,
-            "precision": args.precision, "seed": args.seed,
+            "precision": args.precision, "seed": args.seed, "slab_products": args.slab_products,
             "coefficients": pr["coef"],
         },
         "roofline": {
