@@ -72,8 +72,10 @@ def _name(r):
 
 
 def _short(n):
-    n = re.sub(r"^void ", "", n)
-    return n.split("(")[0] if "(" in n and not n.startswith("(") else n
+    """The kernel's name without the return type and the argument list."""
+    n = re.sub(r"^void ", "", n).replace("(anonymous namespace)", "{anonymous}")
+    n = n.split("(")[0] if "(" in n and not n.startswith("(") else n
+    return n.replace("{anonymous}", "(anonymous namespace)")
 
 
 def _timed_slice(items, bench):
