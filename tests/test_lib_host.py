@@ -135,3 +135,19 @@ def test_host_validation_errors():
     bad[1, 1] = np.nan
     with pytest.raises(phiq.PhiqError, match="NONFINITE"):
         phiq.norm_bound([bad, np.eye(3)], 1.0)
+
+
+def test_options_struct_matches_the_header():
+    """The ctypes mirror of phiq_options has the C layout: phiq_options_default
+    writes exactly sizeof(Options) bytes and every field reads its documented
+    default (a field missing on either side shifts or leaves one unwritten)."""
+    lib = L.load()
+    size = ctypes.sizeof(L.Options)
+    buf = (ctypes.c_ubyte * (size + 64))(*([0xAB] * (size + 64)))
+    assert lib.phiq_options_default(ctypes.cast(buf, ctypes.POINTER(L.Options))) == 0
+    assert bytes(buf[size:]) == b"\xab" * 64
+    o = L.Options.from_buffer(buf)
+    assert (o.rule, o.precision, o.l, o.m) == (L.RULE["gauss"], L.PRECISION["fp64"], -1, -1)
+    assert (o.alpha, o.c1, o.c2, o.cc_max_doublings, o.workspace_cap) == (-1.0, 0.0, 1.0, 6, 0)
+    assert (o.use_graphs, o.selector, o.slab_products) == (0, 0, 0)
+    assert phiq.options(slab_products=2).slab_products == 2
