@@ -212,12 +212,18 @@ phiq_status phiq_plan_execute(phiq_plan plan, const double* v, int nrhs, double*
  *        as for phiq_action); NULL entries are zero vectors, at least one
  *        entry must be non-NULL.  out DEVICE N doubles, must not overlap any
  *        b[j].
+ *   With a Clenshaw-Curtis plan, Algorithm 2's doubling runs on the p scaled
+ *   intermediates: every level's node vectors of every b_j are kept, and the
+ *   doubling stops when the largest relative change of the intermediates is
+ *   below the tolerance (one stream synchronisation per doubling, as in
+ *   phiq_plan_execute; PHIQ_ERR_NOT_CONVERGED at the plan's doubling cap).
  *   Errors: PHIQ_ERR_INVALID_ARG (NULL plan/b/out, all b[j] NULL, overlap),
- *   PHIQ_ERR_UNSUPPORTED (Clenshaw-Curtis or lower-precision plans, or
- *   l (p-1) > 900, which would overflow the 2^{l (p-j)} factors).
- * Accuracy: the plan's bound holds for each term, so the error is at most
- * tol * sum_j ||b_j||_inf plus rounding.  Asynchronous on `stream`; uses the
- * handle's workspace like phiq_plan_execute. */
+ *   PHIQ_ERR_UNSUPPORTED (lower-precision plans, or l (p-1) > 900, which
+ *   would overflow the 2^{l (p-j)} factors), PHIQ_ERR_NOT_CONVERGED.
+ * Accuracy (Gauss): the plan's bound holds for each term, so the error is at
+ * most tol * sum_j ||b_j||_inf plus rounding.  Gauss plans run
+ * asynchronously on `stream`; both use the handle's workspace like
+ * phiq_plan_execute. */
 phiq_status phiq_plan_execute_combo(phiq_plan plan, const double* const* b, double* out,
                                     hipStream_t stream);
 
@@ -320,7 +326,7 @@ phiq_status phiq_etdrk4(phiq_handle h, const phiq_kron_op* op, double tau, int n
  * entry).  phi-actions with tolerance tol and options opt (rule etc.).
  * form 0: the vectors of one stage go through one plan execution (phi_0..p
  * of each, then combined); allocates 13 n^2 doubles.  form 1: every stage
- * is one phiq_plan_execute_combo (Gauss rule and FP64 only, else
+ * is one phiq_plan_execute_combo (FP64 plans only, else
  * PHIQ_ERR_UNSUPPORTED), about half the mode products; allocates 6 n^2
  * doubles.  Returns when the steps have finished.  rep (nullable): the
  * full-step plan.  PHIQ_ERR_UNSUPPORTED for other dimensions. */

@@ -12,7 +12,13 @@ Bars:
   separate plan executions (themselves parity-tested against the oracle at
   that size), below 1e-12;
 * the exponential Runge-Kutta stages as combinations agree with the
-  per-vector form to 1e-12 and with the oracle's Table RK schemes to 1e-10.
+  per-vector form to 1e-12 and with the oracle's Table RK schemes to 1e-10;
+* with the adaptive Clenshaw-Curtis rule (Algorithm 2's doubling test on
+  the base sums y_1..y_pe): against the definition (tiny grids, plan tol
+  1e-12, also with scaling exponent l = 0 and with empty slots) below 1e-10,
+  against the oracle's Gauss form with 24 nodes on grids spanning several
+  tiles below 1e-9 (plan tol 1e-10), and a single vector in slot j against
+  the plain adaptive execution to 1e-10.
 """
 import numpy as np
 import pytest
@@ -144,11 +150,15 @@ def test_combo_errors(h):
     with pytest.raises(phiq.PhiqError, match="INVALID_ARG"):
         plan.execute_combo([b, b, None], out=b)
     plan.close()
-    for kw in (dict(rule="cc"), dict(precision="fp32")):
-        plan = h.plan(mats, 0.01, 2, **kw)
-        with pytest.raises(phiq.PhiqError, match="UNSUPPORTED"):
-            plan.execute_combo([b, b, b])
-        plan.close()
+    plan = h.plan(mats, 0.01, 2, precision="fp32")
+    with pytest.raises(phiq.PhiqError, match="UNSUPPORTED"):
+        plan.execute_combo([b, b, b])
+    plan.close()
+    # the adaptive rule's doubling cap reached before the tolerance
+    plan = h.plan(mats, 0.01, 2, tol=1e-14, rule="cc", cc_max_doublings=1)
+    with pytest.raises(phiq.PhiqError, match="NOT_CONVERGED"):
+        plan.execute_combo([b, b, b])
+    plan.close()
 
 
 def test_combo_full_size_n128(h):
@@ -186,3 +196,67 @@ def test_exprk_forms_agree(h, method):
     e = float((ua - ub).abs().max() / ua.abs().max())
     print(e, flush=True)
     assert e < 1e-12, e
+
+
+@pytest.mark.parametrize("sizes", [[9, 11], [5, 6, 7]])
+@pytest.mark.parametrize("p,t,none", [(1, 0.02, ()), (3, 0.02, ()), (4, 4e-3, (2,)), (3, 1e-5, ()), (2, 1e-5, (0,))])
+def test_combo_cc_vs_definition(h, sizes, p, t, none):
+    mats = ops(sizes, seed=11)
+    N = int(np.prod(sizes))
+    rng = np.random.default_rng(7 * p)
+    bs = draw(rng, p, N, none=none)
+    print("cc combo vs definition", sizes, p, t, none, flush=True)
+    got, rep = run(h, mats, t, bs, rule="cc")
+    ref = C.combo_exact(mats, t, bs)
+    e = rel(got, ref)
+    print(rep["l"], e, flush=True)
+    assert e < 1e-10, e
+    if t == 1e-5:
+        assert rep["l"] == 0
+
+
+@pytest.mark.parametrize("sizes,p", [([37, 50, 29], 3), ([130, 67], 2), ([70, 65, 33], 4)])
+def test_combo_cc_vs_oracle_gauss(h, sizes, p):
+    mats = ops(sizes, seed=12)
+    N = int(np.prod(sizes))
+    rng = np.random.default_rng(13)
+    bs = draw(rng, p, N)
+    t = 1e-3
+    print("cc combo vs oracle Gauss form", sizes, p, flush=True)
+    got, rep = run(h, mats, t, bs, tol=1e-10, rule="cc")
+    ref = C.combo_quad(mats, t, bs, l=rep["l"], m=24)
+    e = rel(got, ref)
+    print(rep["l"], e, flush=True)
+    assert e < 1e-9, e
+
+
+def test_combo_cc_single_vector_equals_execute(h):
+    sizes = [33, 40, 21]
+    mats = ops(sizes, seed=14)
+    N = int(np.prod(sizes))
+    v = torch.from_numpy(np.random.default_rng(15).standard_normal(N)).cuda()
+    plan = h.plan(mats, 0.003, 3, tol=1e-12, rule="cc")
+    full, _ = plan.execute(v)
+    for j in range(4):
+        bs = [None] * 4
+        bs[j] = v
+        got = plan.execute_combo(bs)
+        e = float((got - full[0, j]).abs().max() / full[0, j].abs().max())
+        print("cc slot", j, e, flush=True)
+        assert e < 1e-10, (j, e)
+    plan.close()
+
+
+@pytest.mark.parametrize("method", [1, 3])
+def test_exprk_forms_agree_clenshaw_curtis(h, method):
+    n = 63
+    mats = [I.fd_laplacian(n), I.fd_laplacian(n)]
+    u0 = torch.from_numpy(R.exact(n, 0.0)).cuda()
+    ua = u0.clone()
+    ub = u0.clone()
+    print("exprk forms, cc", method, flush=True)
+    h.exprk(mats, method, 4, ua, tol=1e-12, form="separate", rule="cc")
+    h.exprk(mats, method, 4, ub, tol=1e-12, form="combo", rule="cc")
+    e = float((ua - ub).abs().max() / ua.abs().max())
+    print(e, flush=True)
+    assert e < 1e-10, e
