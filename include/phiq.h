@@ -218,8 +218,10 @@ phiq_status phiq_plan_execute(phiq_plan plan, const double* v, int nrhs, double*
  *   below the tolerance (one stream synchronisation per doubling, as in
  *   phiq_plan_execute; PHIQ_ERR_NOT_CONVERGED at the plan's doubling cap).
  *   Errors: PHIQ_ERR_INVALID_ARG (NULL plan/b/out, all b[j] NULL, overlap),
- *   PHIQ_ERR_UNSUPPORTED (lower-precision plans, or l (p-1) > 900, which
- *   would overflow the 2^{l (p-j)} factors), PHIQ_ERR_NOT_CONVERGED.
+ *   PHIQ_ERR_UNSUPPORTED (int8-digit plans, or l (p-1) > 900, which would
+ *   overflow the 2^{l (p-j)} factors), PHIQ_ERR_NOT_CONVERGED.  FP32 and
+ *   split-bf16 plans run their mode products in that form, the node sums and
+ *   squaring in FP64, as phiq_plan_execute does.
  * Accuracy (Gauss): the plan's bound holds for each term, so the error is at
  * most tol * sum_j ||b_j||_inf plus rounding.  Gauss plans run
  * asynchronously on `stream`; both use the handle's workspace like
@@ -326,7 +328,7 @@ phiq_status phiq_etdrk4(phiq_handle h, const phiq_kron_op* op, double tau, int n
  * entry).  phi-actions with tolerance tol and options opt (rule etc.).
  * form 0: the vectors of one stage go through one plan execution (phi_0..p
  * of each, then combined); allocates 13 n^2 doubles.  form 1: every stage
- * is one phiq_plan_execute_combo (FP64 plans only, else
+ * is one phiq_plan_execute_combo (not with int8-digit plans:
  * PHIQ_ERR_UNSUPPORTED), about half the mode products; allocates 6 n^2
  * doubles.  Returns when the steps have finished.  rep (nullable): the
  * full-step plan.  PHIQ_ERR_UNSUPPORTED for other dimensions. */

@@ -2048,7 +2048,7 @@ phiq_status phiq_plan_execute(phiq_plan plan, const double* v, int nrhs, double*
 
 phiq_status phiq_plan_execute_combo(phiq_plan plan, const double* const* b, double* out, hipStream_t stream) {
   if (!plan || !b || !out) return PHIQ_ERR_INVALID_ARG;
-  if (plan->opt.precision != PHIQ_PREC_FP64) return PHIQ_ERR_UNSUPPORTED;
+  if (plan->opt.precision == PHIQ_PREC_INT8) return PHIQ_ERR_UNSUPPORTED;
   // (Clenshaw-Curtis: a plan's doubling cap is at most 10, so the node sums
   // take at most 11 levels plus the running sums: the 12 segments of NodeSegs)
   const long long N = plan->N;

@@ -131,8 +131,8 @@ extern "C" phiq_status phiq_exprk(phiq_handle h, const phiq_kron_op* op, int met
   if (op->dim != 2 || op->n[0] != op->n[1]) return PHIQ_ERR_UNSUPPORTED;  // the source lives on the unit square
   if (!std::isfinite(c2) || !std::isfinite(T) || !std::isfinite(tol)) return PHIQ_ERR_NONFINITE;
   if (!(T > 0) || !(tol > 0) || (method > 1 && !(c2 > 0 && c2 <= 1))) return PHIQ_ERR_INVALID_ARG;
-  if (form == 1 && opt && opt->precision != PHIQ_PREC_FP64)
-    return PHIQ_ERR_UNSUPPORTED;  // linear combinations: FP64 plans
+  if (form == 1 && opt && opt->precision == PHIQ_PREC_INT8)
+    return PHIQ_ERR_UNSUPPORTED;  // linear combinations: not with the int8-digit form
   const int n = op->n[0];
   const long long N = (long long)n * n;
   const double tau = T / nsteps, c3 = 2.0 / 3.0;

@@ -387,7 +387,7 @@ __global__ __launch_bounds__(256) void ttm_lp_accum_kernel(TtmArgs a) {
                                 a.K, a.L, m0, n0, sm, acc);
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
-      const double w = a.coef[q * a.ldcoef + b];
+      const double w = ldexp(a.coef[q * a.ldcoef + b], a.cexp);
 #pragma unroll
       for (int i = 0; i < C::TM; ++i)
 #pragma unroll
@@ -407,7 +407,10 @@ __global__ __launch_bounds__(256) void ttm_lp_accum_kernel(TtmArgs a) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int row = m0 + lp_row<C>(i, e);
-          if (row < a.M && col < a.L) Y[(long long)row * a.L + col] = y[q][i][j][e];
+          if (row < a.M && col < a.L) {
+            const long long idx = (long long)row * a.L + col;
+            Y[idx] = a.yacc ? Y[idx] + y[q][i][j][e] : y[q][i][j][e];
+          }
         }
       }
   }
@@ -422,7 +425,7 @@ __global__ __launch_bounds__(256) void ttm_lp_square_kernel(TtmArgs a) {
   f4 acc[C::TM][C::TN];
   lp_tile<MODE, BM, TIn, VEC>(e_ptr<MODE>(a, a.Ea, b), e_ptr<MODE>(a, a.Eb, b), (const TIn*)a.X + b * a.xs, a.M, a.K,
                               a.L, m0, n0, sm, acc);
-  const int order = b + 1;
+  const int order = b + 1 + a.order0;
   const double scale = ldexp(1.0, -order);
   double* O = (double*)a.O + b * a.os;
 #pragma unroll
@@ -437,7 +440,7 @@ __global__ __launch_bounds__(256) void ttm_lp_square_kernel(TtmArgs a) {
           const long long idx = (long long)row * a.L + col;
           double s = (double)acc[i][j][e];
           for (int jj = 1; jj <= order; ++jj) s += a.Yprev[(jj - 1) * a.yps + idx] * a.ifact[order - jj];
-          O[idx] = scale * s;
+          O[idx] = a.yacc ? O[idx] + scale * s : scale * s;
         }
       }
     }
@@ -569,7 +572,8 @@ int square_all_go(const TtmArgs& a, hipStream_t st) {
 
 template <int MODE>
 int square_mode(const TtmArgs& a, hipStream_t st) {
-  if (a.nbatch <= 4 && a.es == 0) {
+  // an order offset or an accumulating store needs the per-order kernel
+  if (a.nbatch <= 4 && a.es == 0 && a.order0 == 0 && !a.yacc) {
     const bool v = lp_vec(a);
     if (a.x_f32) return v ? square_all_go<MODE, float, true>(a, st) : square_all_go<MODE, float, false>(a, st);
     return v ? square_all_go<MODE, double, true>(a, st) : square_all_go<MODE, double, false>(a, st);

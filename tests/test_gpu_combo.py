@@ -18,7 +18,11 @@ Bars:
   1e-12, also with scaling exponent l = 0 and with empty slots) below 1e-10,
   against the oracle's Gauss form with 24 nodes on grids spanning several
   tiles below 1e-9 (plan tol 1e-10), and a single vector in slot j against
-  the plain adaptive execution to 1e-10.
+  the plain adaptive execution to 1e-10;
+* FP32 and split-bf16 plans (mode products in that form, node sums and
+  squaring in FP64): against the FP64 combination with the same (l, m)
+  below 3e-6 and 3e-5, the forms' error floors (8e-7 and 9e-6 per
+  phi-action, measured) with room for the p terms.
 """
 import numpy as np
 import pytest
@@ -150,9 +154,10 @@ def test_combo_errors(h):
     with pytest.raises(phiq.PhiqError, match="INVALID_ARG"):
         plan.execute_combo([b, b, None], out=b)
     plan.close()
-    plan = h.plan(mats, 0.01, 2, precision="fp32")
+    b32 = torch.randn(32 * 32, dtype=torch.float64, device="cuda")
+    plan = h.plan(ops([32, 32]), 0.01, 2, precision="int8")
     with pytest.raises(phiq.PhiqError, match="UNSUPPORTED"):
-        plan.execute_combo([b, b, b])
+        plan.execute_combo([b32, b32, b32])
     plan.close()
     # the adaptive rule's doubling cap reached before the tolerance
     plan = h.plan(mats, 0.01, 2, tol=1e-14, rule="cc", cc_max_doublings=1)
@@ -260,3 +265,20 @@ def test_exprk_forms_agree_clenshaw_curtis(h, method):
     e = float((ua - ub).abs().max() / ua.abs().max())
     print(e, flush=True)
     assert e < 1e-10, e
+
+
+@pytest.mark.parametrize("precision,bar", [("fp32", 3e-6), ("bf16x3", 3e-5)])
+@pytest.mark.parametrize("rule", ["gauss", "cc"])
+def test_combo_lower_precision_vs_fp64(h, precision, bar, rule):
+    sizes = [37, 50, 29]
+    mats = ops(sizes, seed=16)
+    N = int(np.prod(sizes))
+    rng = np.random.default_rng(17)
+    bs = draw(rng, 3, N)
+    print("combo", precision, rule, flush=True)
+    ref, rep = run(h, mats, 1e-3, bs, tol=1e-8, rule=rule)
+    kw = dict(l=rep["l"], m=rep["m"]) if rule == "gauss" else {}
+    got, _ = run(h, mats, 1e-3, bs, tol=1e-8, rule=rule, precision=precision, **kw)
+    e = rel(got, ref)
+    print(rep["l"], rep["m"], e, flush=True)
+    assert e < bar, e
