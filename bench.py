@@ -109,7 +109,8 @@ def main():
                     help="phiq_options.slab_products: 0 one axis per pass (default), "
                          "1 two-axis slab products for single-vector chains, 2 for every chain")
     ap.add_argument("--workload", default="advdiff3d",
-                    choices=["advdiff3d", "batch512", "etdrk4", "precision256", "problem1", "problem3", "seeds"],
+                    choices=["advdiff3d", "batch512", "combo", "etdrk4", "precision256", "problem1", "problem3",
+                             "seeds"],
                     help="advdiff3d: one 3D problem (default); batch512: 512 mixed 2D/3D problems in one "
                          "batched call (phiq_action_batched); etdrk4: 100 ETD-RK4 steps of Allen-Cahn on 3D n=128")
     ap.add_argument("--count", type=int, default=None,
@@ -139,6 +140,8 @@ def main():
         return bench_problem3(args, rank)
     if args.workload == "seeds":
         return bench_seeds(args, rank)
+    if args.workload == "combo":
+        return bench_combo(args, rank)
 
     from paper_2211_00696_amd import inputs, phiq
 
@@ -550,6 +553,62 @@ def bench_problem3(args, rank):
         print(json.dumps({"metric": "Problem 3 (Section 5) total time of an exponential Runge-Kutta run, T = 1",
                           "unit": "s", "note": "paper: serial MATLAB on one thread of an Intel i5-8279U "
                           "(context, another machine); tol 1e-14 as in the paper", "rows": rows}), flush=True)
+
+
+def bench_combo(args, rank):
+    """Linear combinations sum_j phi_j(-tA) b_j, j = 0..3, on the 3D n=128 advection-diffusion operator
+    (four seeded N(0,1) vectors): one phiq_plan_execute_combo against the four phi_j b_j from separate
+    executions of the same plan (summed on the device), per rule and precision; plans reused, times per
+    combination after warm-up."""
+    import torch
+
+    from paper_2211_00696_amd import inputs, phiq
+
+    pr = inputs.problem("advdiff3d", seed=args.seed, n=args.n)
+    N = pr["v"].size
+    p = pr["p"]
+    g = torch.Generator(device="cuda")
+    g.manual_seed(args.seed)
+    bs = [torch.randn(N, dtype=torch.float64, device="cuda", generator=g) for _ in range(p + 1)]
+    h = phiq.Handle(0)
+    rows = []
+    steps = max(3, args.steps // 3)
+    for rule in ("gauss", "cc"):
+        for precision in ("fp64", "fp32", "bf16x3"):
+            plan = h.plan(pr["mats"], pr["t"], p, tol=pr["tol"], rule=rule, precision=precision)
+            out = torch.empty((1, p + 1, N), dtype=torch.float64, device="cuda")
+
+            def separate():
+                acc = torch.zeros(N, dtype=torch.float64, device="cuda")
+                for j, b in enumerate(bs):
+                    plan.execute(b, out=out)
+                    acc += out[0, j]
+                return acc
+
+            def timed(fn):
+                fn()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(steps):
+                    r = fn()
+                torch.cuda.synchronize()
+                return (time.perf_counter() - t0) * 1e3 / steps, r
+
+            ms_c, rc = timed(lambda: plan.execute_combo(bs))
+            ms_s, rs = timed(separate)
+            rep = plan.report
+            rows.append(dict(rule=rule, precision=precision, l=rep["l"], m=rep["m"], ms_combo=ms_c,
+                             ms_separate=ms_s, speedup=ms_s / ms_c,
+                             rel_diff=float((rc - rs).abs().max() / rs.abs().max())))
+            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+            plan.close()
+    h.close()
+    if rank == 0:
+        print(json.dumps({"metric": "linear combination sum_j phi_j(-tA) b_j (j = 0..3), 3D n=128 advection-diffusion",
+                          "unit": "ms per combination", "higher_is_better": False,
+                          "config": {"workload": "3D advection-diffusion n=%d (N=%d), t=1e-3, tol 1e-8, seed %d, "
+                                     "b_j ~ N(0,1)" % (args.n, N, args.seed)},
+                          "rows": rows}), flush=True)
 
 
 def bench_seeds(args, rank):
