@@ -361,6 +361,12 @@ phiq_status phiq_mlp_train(phiq_handle h, int B, const float* X, const float* T,
                            float lr, float* loss_history);
 /* The handle's selector network (HOST w copied; NULL clears it). */
 phiq_status phiq_selector_set(phiq_handle h, const float* w);
+/* The same from a file: exactly PHIQ_MLP_NPARAM little-endian IEEE float32
+ * values, in the order of the parameter vector above (weights_path HOST,
+ * NUL-terminated).  PHIQ_ERR_INVALID_ARG if the file cannot be opened or
+ * holds another number of bytes, PHIQ_ERR_NONFINITE for a NaN or infinite
+ * weight; the handle's network is unchanged on error. */
+phiq_status phiq_selector_load(phiq_handle h, const char* weights_path);
 
 /* Building blocks (also used by the tests).
  *

@@ -49,6 +49,7 @@ EXPORTS = [
     "phiq_mlp_grad",
     "phiq_mlp_train",
     "phiq_selector_set",
+    "phiq_selector_load",
     "phiq_expm",
     "phiq_kron_apply",
     "phiq_profile_start",
@@ -165,6 +166,7 @@ def load():
         "phiq_mlp_train": (c_int, [c_void_p, c_int, P(ctypes.c_float), P(ctypes.c_float), P(ctypes.c_float), c_int,
                                    ctypes.c_float, P(ctypes.c_float)]),
         "phiq_selector_set": (c_int, [c_void_p, P(ctypes.c_float)]),
+        "phiq_selector_load": (c_int, [c_void_p, ctypes.c_char_p]),
         "phiq_expm": (c_int, [c_void_p, c_int, c_int, c_void_p, P(c_double), c_void_p, c_void_p]),
         "phiq_kron_apply": (c_int, [c_void_p, c_int, P(c_int), P(c_void_p), c_void_p, c_void_p, c_int, c_int,
                                     c_void_p]),

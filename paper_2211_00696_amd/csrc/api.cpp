@@ -12,6 +12,7 @@
 //            sum fused into the last product; then l modified-squaring steps
 //            (eq. squaring), each D mode products on the p vectors with the
 //            combination fused into the last one; phi_0 from exp(-t A^d).
+#include <cstdio>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -2526,6 +2527,17 @@ extern "C" phiq_status phiq_selector_set(phiq_handle h, const float* w) {
     if (!std::isfinite(w[i])) return PHIQ_ERR_NONFINITE;
   h->mlp.assign(w, w + kMlpParams);
   return PHIQ_OK;
+}
+
+extern "C" phiq_status phiq_selector_load(phiq_handle h, const char* weights_path) {
+  if (!h || !weights_path) return PHIQ_ERR_INVALID_ARG;
+  FILE* f = std::fopen(weights_path, "rb");
+  if (!f) return PHIQ_ERR_INVALID_ARG;
+  std::vector<float> w(kMlpParams + 1);
+  const size_t got = std::fread(w.data(), sizeof(float), w.size(), f);
+  std::fclose(f);
+  if (got != (size_t)kMlpParams) return PHIQ_ERR_INVALID_ARG;  // shorter or longer than one weight vector
+  return phiq_selector_set(h, w.data());
 }
 
 namespace phiq {

@@ -7,6 +7,7 @@ the library's HIP kernels; nothing here computes.
 from __future__ import annotations
 
 import ctypes
+import os
 from ctypes import POINTER, byref, c_double, c_int, c_void_p
 
 import numpy as np
@@ -435,6 +436,11 @@ class Handle:
             return
         w = np.ascontiguousarray(w, dtype=np.float32)
         _check(lib.phiq_selector_set(self._h, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float))), "phiq_selector_set")
+
+    def selector_load(self, path):
+        """Install the selector network from a file of PHIQ_MLP_NPARAM float32 values
+        (phiq_selector_load; `selector.save_weights_bin` writes one)."""
+        _check(L.load().phiq_selector_load(self._h, os.fsencode(path)), "phiq_selector_load")
 
     def plan(self, mats, t, p, tol=1e-8, stream=None, **opts):
         lib = L.load()

@@ -239,6 +239,11 @@ def load_weights(path=WEIGHTS):
     return np.array(json.load(open(path))["weights"], dtype=np.float32)
 
 
+def save_weights_bin(w, path):
+    """The weight vector as raw little-endian float32, the file phiq_selector_load reads."""
+    np.asarray(w, dtype="<f4").tofile(path)
+
+
 def main(argv):
     if len(argv) >= 1 and argv[0] == "train":
         out = argv[1] if len(argv) > 1 else WEIGHTS

@@ -141,3 +141,40 @@ def test_trained_selector_gain(h):
         assert t_mlp <= 1.05 * t_pap
     finally:
         h.selector_set(None)
+
+
+@pytest.mark.skipif(not os.path.exists(S.WEIGHTS), reason="no trained selector weights in the package")
+def test_selector_load_from_file_matches_set(h, tmp_path):
+    """phiq_selector_load installs the same network as phiq_selector_set: the
+    same (l, m) and the same bits on a set of problems; bad files are errors
+    that leave the installed network in place."""
+    from paper_2211_00696_amd import phiq
+
+    w = S.load_weights()
+    path = tmp_path / "w.bin"
+    S.save_weights_bin(w, str(path))
+    probs = [I.problem("advdiff", seed=s, n=12, dim=3, t=t) for s, t in ((1, 1e-3), (2, 1e-2), (3, 5e-2))]
+    try:
+        h.selector_set(w)
+        ref = [h.action(pr["mats"], pr["t"], 3, dev(pr["v"]), tol=1e-8, selector="mlp") for pr in probs]
+        h.selector_set(None)
+        h.selector_load(str(path))
+        got = [h.action(pr["mats"], pr["t"], 3, dev(pr["v"]), tol=1e-8, selector="mlp") for pr in probs]
+        for (o1, r1), (o2, r2) in zip(ref, got):
+            assert (r1["l"], r1["m"], r1["selector"]) == (r2["l"], r2["m"], r2["selector"])
+            assert r2["selector"] != 0
+            assert torch.equal(o1, o2)
+        short = tmp_path / "short.bin"
+        S.save_weights_bin(w[:-1], str(short))
+        bad = w.copy()
+        bad[7] = np.nan
+        nan = tmp_path / "nan.bin"
+        S.save_weights_bin(bad, str(nan))
+        for p, code in ((tmp_path / "missing.bin", "INVALID_ARG"), (short, "INVALID_ARG"), (nan, "NONFINITE")):
+            with pytest.raises(phiq.PhiqError, match=code):
+                h.selector_load(str(p))
+        # still the loaded network
+        _, r3 = h.action(probs[0]["mats"], probs[0]["t"], 3, dev(probs[0]["v"]), tol=1e-8, selector="mlp")
+        assert (r3["l"], r3["m"]) == (got[0][1]["l"], got[0][1]["m"])
+    finally:
+        h.selector_set(None)
