@@ -74,24 +74,37 @@ def cpu_baseline(pr, out_gpu, min_seconds=10.0, max_runs=8):
     from oracle import phiquad
 
     threads = blas_threads()
-    runs, dt = 0, 0.0
-    while runs < max_runs and (runs == 0 or dt < min_seconds):
+    secs = []
+    while len(secs) < max_runs and (not secs or sum(secs) < min_seconds):
         t0 = time.perf_counter()
         ref = phiquad.phiquadmv(pr["mats"], pr["t"], pr["v"], pr["p"], eps=pr["tol"], beta=1.0)
-        dt += time.perf_counter() - t0
-        runs += 1
+        secs.append(time.perf_counter() - t0)
     N = pr["v"].size
+    med = float(np.median(secs))
     errs = [float(np.max(np.abs(out_gpu[k] - ref[k])) / np.max(np.abs(ref[k]))) for k in range(pr["p"] + 1)]
     return {
-        "value": N * runs / dt,
+        "value": N / med,
         "unit": "grid-pts/s",
         "cores": int(threads),
         "kind": "oracle",
         "sample": "%d full phi-actions (all N = %d points, phi_0..phi_%d each) of the same workload by the oracle's "
-                  "numpy quadrature + modified squaring (FP64, BLAS threads = %d), %.2f s in total"
-                  % (runs, N, pr["p"], threads, dt),
-        "seconds": dt,
+                  "numpy quadrature + modified squaring (FP64, BLAS threads = %d), %.2f s in total; value from "
+                  "the median run" % (len(secs), N, pr["p"], threads, sum(secs)),
+        "seconds": float(sum(secs)),
+        "run_seconds": secs,
+        "affinity_cores": len(os.sched_getaffinity(0)),
+        "cpu_model": cpu_model(),
     }, errs
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def main():
