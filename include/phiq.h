@@ -426,7 +426,8 @@ phiq_status phiq_tile_config(phiq_handle h, int kind, int cfg, int* count);
  *
  * Times every tile shape of the FP64 mode-product kernels on the launch
  * shapes a phi-action with these sizes makes (dim axes of sizes n[d], p
- * orders, m quadrature nodes: node products with m batches, phi_0 with 1,
+ * orders, m quadrature nodes: node products with m + 1 batches (the Gauss
+ * nodes and phi_0's chain), phi_0's last product with 1,
  * squaring products with p batches, the fused node sum and the fused
  * squaring step)
  * and keeps the fastest shape per launch shape in the handle; later calls

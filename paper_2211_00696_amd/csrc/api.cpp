@@ -1139,20 +1139,23 @@ phiq_status execute_gauss(phiq_plan P, const double* v, double* out, hipStream_t
   double* Ya = (double*)(wb + 2 * align_up(tbytes));
   double* Yb = (double*)(wb + 2 * align_up(tbytes) + align_up(ybytes));
 
-  // phi_0 runs last, on this stream: on the side stream beside the node
-  // chains it saved no time (both fill the GPU; within 1% at n = 128 and
-  // 256) and slowed every launch it overlapped.
   if (p == 0) return phi0_chain(P, v, out, T0, T1, st);
 
-  // quadrature: the m node chains as one batch per mode product
+  // quadrature: the m node chains and the phi_0 chain as one batch per mode
+  // product.  phi_0's factor exp(-tA^d) is slot m of the node tables (the
+  // end of the scaling chain, joined here), so its first products ride in
+  // the node batch instead of two launches on one vector (on a side stream
+  // beside the node chains, phi_0 saved no time and slowed the launches it
+  // overlapped).
   double* E[PHIQ_MAX_DIM];
   long long es[PHIQ_MAX_DIM];
   for (int d = 0; d < P->D; ++d) {
     E[d] = P->Enode[d];
     es[d] = (long long)P->n[d] * P->n[d];
   }
+  PHIQ_TRY(wait_join(P, st));
   Front f;
-  PHIQ_TRY(chain_front(P, v, 0, E, es, P->m, T0, T1, st, &f));
+  PHIQ_TRY(chain_front(P, v, 0, E, es, P->m + 1, T0, T1, st, &f));
   double* Y = (P->l == 0) ? out + N : Ya;
   for (int j0 = 0; j0 < p; j0 += 4) {
     TtmArgs a = final_args(P, P->Enode[0], es[0], f, P->m);
@@ -1163,9 +1166,17 @@ phiq_status execute_gauss(phiq_plan P, const double* v, double* out, hipStream_t
     a.ys = N;
     PHIQ_TRY(L_ttm(P->h, K_TTM_ACCUM, a, P->opt.precision, st, &P->twins));
   }
+  {  // phi_0 = (exp(-tA^0) (x) exp(-tA^1) ...) v: the last product of slot m,
+     // before the squaring reuses the front's buffers
+    Front f0 = f;
+    f0.X = elem_offset(f.X, (long long)P->m * f.xs, f.f32);
+    TtmArgs a = final_args(P, P->Ephi0[0], 0, f0, 1);
+    a.O = out;
+    a.os = 0;
+    PHIQ_TRY(L_ttm(P->h, K_TTM_STORE, a, P->opt.precision, st, &P->twins));
+  }
   if (P->l > 0) PHIQ_TRY(squaring(P, Ya, Yb, out + N, T0, T1, st));
-  // phi_0 = (exp(-tA^0) (x) exp(-tA^1) ...) v
-  return phi0_chain(P, v, out, T0, T1, st);
+  return PHIQ_OK;
 }
 
 // ---- int8 digit products (PHIQ_PREC_INT8) -----------------------------------
@@ -2420,7 +2431,7 @@ phiq_status phiq_autotune(phiq_handle h, int dim, const int* n, int p, int m, do
   std::vector<Shape> shapes;
   for (int d = 0; d < dim; ++d) {
     const int L = (int)(N / n[d]);
-    shapes.push_back({0, n[d], L, m});  // node chains
+    shapes.push_back({0, n[d], L, m + 1});  // node chains with phi_0's (Gauss)
     shapes.push_back({0, n[d], L, 1});  // phi_0
     if (p > 0 && p != m && p != 1) shapes.push_back({0, n[d], L, p});  // squaring orders
     if (d == 0 && p > 0) {
