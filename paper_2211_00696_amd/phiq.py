@@ -366,11 +366,11 @@ class Handle:
         """Section 5's exponential Euler (1), RK2 (2) or RK3 (3) on Problem 3, in place on u; report dict.
 
         form: "separate" (phi_0..p of every stage vector), "combo" (one linear
-        combination per stage) or "auto" (combo for Gauss FP64 options)."""
+        combination per stage) or "auto" (combo for every precision but the int8 digits, which have
+        no combination form)."""
         lib = L.load()
         if form == "auto":
-            combo = opts.get("rule", "gauss") == "gauss" and opts.get("precision", "fp64") == "fp64"
-            form = "combo" if combo else "separate"
+            form = "separate" if opts.get("precision", "fp64") == "int8" else "combo"
         if form not in ("separate", "combo"):
             raise ValueError("form must be 'separate', 'combo' or 'auto'")
         op = _Op(mats)
