@@ -35,7 +35,7 @@ def lap2d(n):
 
 
 @pytest.mark.parametrize("method", [1, 2, 3])
-@pytest.mark.parametrize("rule,form", [("gauss", "separate"), ("gauss", "combo"), ("cc", "separate")])
+@pytest.mark.parametrize("rule,form", [("gauss", "separate"), ("gauss", "combo"), ("cc", "separate"), ("cc", "combo")])
 def test_exprk_vs_oracle(h, method, rule, form):
     n = 7
     mats = lap2d(n)
