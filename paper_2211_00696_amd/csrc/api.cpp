@@ -243,6 +243,9 @@ struct phiq_handle_s {
   // transient plans alternate between two buffers so the upload of the next
   // call overlaps the execution of the current one
   DevBuf tr_buf[2];
+  // adaptive Clenshaw-Curtis node tables of transient plans, per slot and
+  // level (kept like tr_buf, so that a call neither allocates nor frees them)
+  std::vector<DevBuf> tr_cc[2];
   hipEvent_t tr_free[2] = {nullptr, nullptr};  // buffer no longer read
   hipEvent_t tr_up[2] = {nullptr, nullptr};    // upload into buffer done
   bool tr_used[2] = {false, false};
@@ -270,6 +273,8 @@ struct phiq_handle_s {
   size_t held() const {
     size_t s = ws.cap + scratch.cap + partial.cap + combo_coef.cap + tr_buf[0].cap + tr_buf[1].cap + batch.cap;
     for (const auto& b : cc_levels) s += b.cap;
+    for (int k = 0; k < 2; ++k)
+      for (const auto& b : tr_cc[k]) s += b.cap;
     return s;
   }
 };
@@ -314,8 +319,10 @@ struct phiq_plan_s {
   void* ej = nullptr;  // the plan's device job groups (ExpmJobs), enqueued by plan_enqueue
   void (*ej_free)(void*) = nullptr;
   // adaptive Clenshaw-Curtis: per level, node exponentials [axis][count]
+  // (owned by the plan, or by the handle's transient slot when cc_pooled)
   std::vector<DevBuf> cc_E;
   std::vector<int> cc_count;
+  bool cc_pooled = false;
   ~phiq_plan_s() {
     if (ej && ej_free) ej_free(ej);
     if (own_events) {
@@ -324,8 +331,9 @@ struct phiq_plan_s {
       if (fork2) (void)hipEventDestroy(fork2);
       if (phi0) (void)hipEventDestroy(phi0);
     }
-    for (auto& b : cc_E)
-      if (b.p) (void)hipFree(b.p);
+    if (!cc_pooled)
+      for (auto& b : cc_E)
+        if (b.p) (void)hipFree(b.p);
     if (!transient && mem) (void)hipFree(mem);
   }
 };
@@ -1574,12 +1582,22 @@ phiq_status cc_ensure_level(phiq_plan P, int level, hipStream_t st) {
     const bool lp = twin_prec(P->opt.precision);
     if (lp) bytes += twin_bytes(fp64_bytes / sizeof(double));
     DevBuf b;
-    if (h->cap_bytes && h->held() + bytes > h->cap_bytes) return PHIQ_ERR_OOM;
-    if (hipMalloc(&b.p, bytes) != hipSuccess) {
-      (void)hipGetLastError();
-      return PHIQ_ERR_OOM;
+    if (P->tr_slot >= 0) {
+      // transient plan (phiq_action): the slot's table, reused call after call
+      // (the slot's previous user finished before this call's upload)
+      auto& pool = h->tr_cc[P->tr_slot];
+      if ((int)pool.size() <= lv) pool.resize(lv + 1);
+      PHIQ_TRY(ensure(h, pool[lv], bytes));
+      b = pool[lv];
+      P->cc_pooled = true;
+    } else {
+      if (h->cap_bytes && h->held() + bytes > h->cap_bytes) return PHIQ_ERR_OOM;
+      if (hipMalloc(&b.p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return PHIQ_ERR_OOM;
+      }
+      b.cap = bytes;
     }
-    b.cap = bytes;
     P->cc_E.push_back(b);
     P->cc_count.push_back(cnt);
     std::vector<ExpTarget> tg;
@@ -2004,6 +2022,8 @@ phiq_status phiq_destroy(phiq_handle h) {
   if (h->tr_phi0) (void)hipEventDestroy(h->tr_phi0);
   for (int k = 0; k < 2; ++k) {
     if (h->tr_buf[k].p) (void)hipFree(h->tr_buf[k].p);
+    for (auto& b : h->tr_cc[k])
+      if (b.p) (void)hipFree(b.p);
     if (h->tr_free[k]) (void)hipEventDestroy(h->tr_free[k]);
     if (h->tr_up[k]) (void)hipEventDestroy(h->tr_up[k]);
   }
@@ -2089,7 +2109,7 @@ phiq_status phiq_plan_destroy(phiq_plan plan) {
     // plan memory may still be read by queued work
     (void)hipDeviceSynchronize();
   }
-  if (!plan->cc_E.empty()) (void)hipDeviceSynchronize();
+  if (!plan->cc_E.empty() && !plan->cc_pooled) (void)hipDeviceSynchronize();
   delete plan;
   return PHIQ_OK;
 }
@@ -2201,7 +2221,7 @@ phiq_status phiq_action(phiq_handle h, const phiq_kron_op* op, double t, int p, 
     if (hipEventRecord(h->tr_free[P->tr_slot], stream) == hipSuccess) h->tr_used[P->tr_slot] = true;
   }
   if (rep) *rep = r;
-  if (!P->cc_E.empty()) (void)hipStreamSynchronize(stream);
+  if (!P->cc_E.empty() && !P->cc_pooled) (void)hipStreamSynchronize(stream);
   delete P;  // transient: memory stays in the handle
   return s;
 }
