@@ -225,6 +225,52 @@ __global__ __launch_bounds__(C::NT) void gemm_jobs_kernel(const GemmJob* __restr
     }
 }
 
+// The same for n <= kPanelK: a block loads its whole 32-row panel of A and
+// 32-column panel of B in one pass (every load in flight at once, one
+// barrier), then four waves take a 16 x 16 quarter of the 32 x 32 output
+// each.  The k order of the MFMA chain is the one above, so the two kernels
+// give the same bits; this one pays one load latency per block instead of
+// one per 16-deep chunk.
+constexpr int kPanelK = 128;
+__global__ __launch_bounds__(256) void gemm_panel_kernel(const GemmJob* __restrict__ jobs) {
+  constexpr int BM = 32, BN = 32, LDK = kPanelK + 2, NT = 256, PER = BM * kPanelK / NT;
+  __shared__ double As[BM * LDK];
+  __shared__ double Bs[BN * LDK];
+  const GemmJob jb = jobs[blockIdx.z];
+  const int n = jb.n;
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  if (m0 >= n || n0 >= n) return;  // uniform per block
+  double ra[PER], rb[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + i * NT;
+    const int r = m0 + e / kPanelK, k = e % kPanelK;  // A: k fastest
+    ra[i] = (r < n && k < n) ? jb.A[(long long)r * n + k] : 0.0;
+    const int kb = e / BN, c = n0 + e % BN;  // B: columns fastest
+    rb[i] = (kb < n && c < n) ? jb.B[(long long)kb * n + c] : 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + i * NT;
+    As[(e / kPanelK) * LDK + e % kPanelK] = ra[i];
+    Bs[(e % BN) * LDK + e / BN] = rb[i];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const double* a = As + (16 * wm + (lane & 15)) * LDK + (lane >> 4);
+  const double* b = Bs + (16 * wn + (lane & 15)) * LDK + (lane >> 4);
+  d4 acc = {0.0, 0.0, 0.0, 0.0};
+  const int ksteps = (n + 3) / 4;
+  for (int k4 = 0; k4 < ksteps; ++k4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[4 * k4], b[4 * k4], acc, 0, 0, 0);
+  const int col = n0 + 16 * wn + (lane & 15);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int row = m0 + 16 * wm + (lane >> 4) + 4 * e;
+    if (row < n && col < n) jb.C[(long long)row * n + col] = acc[e];
+  }
+}
+
 __global__ void scale_jobs_kernel(const ScaleJob* __restrict__ jobs) {
   const ScaleJob jb = jobs[blockIdx.y];
   const long long nn = (long long)jb.n * jb.n;
@@ -340,6 +386,11 @@ int launch_fetch(void* dst, const void* src, size_t bytes, void* stream) {
 
 int launch_gemm_jobs(const GemmJob* jobs, int njobs, int nmax, void* stream) {
   if (njobs <= 0) return hipSuccess;
+  if (nmax <= kPanelK) {
+    dim3 grid(cdiv(nmax, 32), cdiv(nmax, 32), njobs);
+    PHIQ_LAUNCH(gemm_panel_kernel, grid, dim3(256), 0, (hipStream_t)stream, jobs);
+    return hipGetLastError();
+  }
   // few large-tile blocks would leave most CUs idle: use one-wave 32x32 tiles
   if ((long long)njobs * cdiv(nmax, 64) * cdiv(nmax, 64) < 512) {
     using C = Tile32;
