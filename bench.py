@@ -128,6 +128,9 @@ def main():
                          "batched call (phiq_action_batched); etdrk4: 100 ETD-RK4 steps of Allen-Cahn on 3D n=128")
     ap.add_argument("--count", type=int, default=None,
                     help="batch512: number of problems (default 512); seeds: number of coefficient draws (default 16)")
+    ap.add_argument("--event-every", type=int, default=10,
+                    help="advdiff3d: in the timed region, the dominant kernel class's launches of every this-many-th "
+                         "step (the first, the 1+S-th, ...) carry HIP events; 1 = every step")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the steps, negate a buffer of this many MiB into another once (a plain device copy "
                          "of known size that calibrates hardware byte counters taken over the same run)")
@@ -192,8 +195,11 @@ def main():
     all_stats = h.profile_stop()
     dom = max(all_stats.items(), key=lambda kv: kv[1]["ms"])[0]
 
-    # timed region: K full phi-actions; the dominant kernel's launches are
-    # bracketed by HIP events on its launch stream
+    # timed region: K full phi-actions; the dominant kernel's launches in every
+    # S-th step are bracketed by HIP events on its launch stream (a bracketed
+    # launch leaves the GPU idle for some microseconds, so bracketing every
+    # one would slow the steps being timed)
+    every = max(1, args.event_every)
     h.profile_start([dom])
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -201,7 +207,9 @@ def main():
     t0 = time.perf_counter()
     ev0.record(stream)
     rep = None
-    for _ in range(args.steps):
+    for i in range(args.steps):
+        if every > 1:
+            h.profile_enable(i % every == 0)
         _, rep = h.action(pr["mats"], pr["t"], p, v, tol=pr["tol"], out=out, **opts)
     ev1.record(stream)
     torch.cuda.synchronize()
@@ -288,6 +296,8 @@ def main():
         },
         "plan": {"l": rep["l"], "m": rep["m"], "alpha": rep["alpha"], "ttm_chains": rep["ttm_chains"],
                  "log10_bound": rep["log10_bound"]},
+        "event_every": every,
+        "event_steps": len(range(0, args.steps, every)),
         "ms_per_step_events": ms_events,
         "ms_per_step_unprofiled": ms_unprofiled,
         "ms_per_execute_reused_plan": ms_execute,

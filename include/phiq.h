@@ -414,6 +414,14 @@ typedef struct {
 phiq_status phiq_profile_start(phiq_handle h, unsigned class_mask);
 phiq_status phiq_profile_stop(phiq_handle h, phiq_kernel_stat* stats, int max_stats, int* n_stats);
 
+/* Pause (on = 0) or resume (on != 0) the bracketing that phiq_profile_start
+ * began, keeping the launches recorded so far and the class mask; no device
+ * work, no synchronisation.  A bracketed launch leaves the GPU idle for a
+ * few microseconds around it, so timing a sample of a long run's launches
+ * disturbs its throughput less than timing every one.  INVALID_ARG if h is
+ * NULL or no profile is open (before phiq_profile_start or after stop). */
+phiq_status phiq_profile_enable(phiq_handle h, int on);
+
 /* Tile shape of the FP64 mode products for every later launch of one kind:
  * kind 0 (plain mode product), 1 (with the node sum), 2 (with the squaring
  * combination); cfg -1 restores the autotuned or default choice, 0..count-1

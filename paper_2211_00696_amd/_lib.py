@@ -54,6 +54,7 @@ EXPORTS = [
     "phiq_kron_apply",
     "phiq_profile_start",
     "phiq_profile_stop",
+    "phiq_profile_enable",
     "phiq_tile_config",
     "phiq_autotune",
 ]
@@ -172,6 +173,7 @@ def load():
                                     c_void_p]),
         "phiq_profile_start": (c_int, [c_void_p, ctypes.c_uint]),
         "phiq_profile_stop": (c_int, [c_void_p, P(KernelStat), c_int, P(c_int)]),
+        "phiq_profile_enable": (c_int, [c_void_p, c_int]),
         "phiq_tile_config": (c_int, [c_void_p, c_int, c_int, P(c_int)]),
         "phiq_autotune": (c_int, [c_void_p, c_int, P(c_int), c_int, c_int, P(c_double), c_void_p]),
     }

@@ -172,7 +172,8 @@ struct ProfRec {
 };
 
 struct Profiler {
-  bool on = false;
+  bool on = false;    // launches are being bracketed
+  bool open = false;  // between phiq_profile_start and phiq_profile_stop
   unsigned mask = ~0u;
   std::vector<ProfRec> recs;
   std::vector<hipEvent_t> pool;
@@ -2376,6 +2377,13 @@ phiq_status phiq_profile_start(phiq_handle h, unsigned class_mask) {
   h->prof.recs.clear();
   h->prof.next = 0;
   h->prof.on = true;
+  h->prof.open = true;
+  return PHIQ_OK;
+}
+
+phiq_status phiq_profile_enable(phiq_handle h, int on) {
+  if (!h || !h->prof.open) return PHIQ_ERR_INVALID_ARG;
+  h->prof.on = on != 0;
   return PHIQ_OK;
 }
 
@@ -2383,6 +2391,7 @@ phiq_status phiq_profile_stop(phiq_handle h, phiq_kernel_stat* stats, int max_st
   if (!h || (max_stats > 0 && !stats) || max_stats < 0) return PHIQ_ERR_INVALID_ARG;
   DeviceGuard g(h->device);
   h->prof.on = false;
+  h->prof.open = false;
   PHIQ_HIP(hipDeviceSynchronize());
   phiq_kernel_stat agg[K_NCLASS];
   std::memset(agg, 0, sizeof(agg));

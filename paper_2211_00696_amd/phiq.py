@@ -270,6 +270,10 @@ class Handle:
             mask |= 1 << L.PROFILE_CLASSES.index(c)
         _check(L.load().phiq_profile_start(self._h, mask), "phiq_profile_start")
 
+    def profile_enable(self, on=True):
+        """Pause (False) or resume (True) the bracketing, keeping what was recorded."""
+        _check(L.load().phiq_profile_enable(self._h, int(bool(on))), "phiq_profile_enable")
+
     def profile_stop(self):
         """Synchronise and return {kernel class: dict(launches, ms, flops, bytes)}."""
         arr = (L.KernelStat * 16)()

@@ -116,6 +116,13 @@ def times(trace_csv, bench_json):
           % (dom, len(sl), avg, bench["roofline"]["avg_launch_ms"] * 1e3, bench["roofline"]["launches"]))
     names = sorted(set(n for n, _ in sl))
     print("Kernels of the class in the timed region: " + ", ".join("`%s`" % n for n in names))
+    every = int(bench.get("event_every", 1))
+    if every > 1:
+        # the launches bench.py bracketed: those of steps 0, S, 2S, ...
+        L = int(bench["kernels_one_step"][dom]["launches"])
+        ev = [d for i, (_, d) in enumerate(sl) if (i // L) % every == 0]
+        print("Launches of the bracketed steps (every %d-th): %d, average %.2f us (rocprofv3)."
+              % (every, len(ev), sum(ev) / len(ev)))
 
 
 def _counter(path, counter):

@@ -1,0 +1,94 @@
+"""Live kernel timing (phiq_profile_start / _enable / _stop) on a 3D problem:
+the classes asked for and no others are recorded, the recorded work is what
+the launches compute, and pausing the bracketing keeps exactly the launches
+made while it was on."""
+import numpy as np
+import pytest
+
+from paper_2211_00696_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def h():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2211_00696_amd import phiq
+
+    hd = phiq.Handle(0)
+    yield hd
+    hd.close()
+
+
+@pytest.fixture(scope="module")
+def prob():
+    pr = I.problem("advdiff3d", seed=3, n=48)
+    return pr, torch.from_numpy(pr["v"]).cuda()
+
+
+def step(h, prob):
+    pr, v = prob
+    _, rep = h.action(pr["mats"], pr["t"], 3, v, tol=1e-8)
+    return rep
+
+
+def test_only_requested_classes(h, prob):
+    h.profile_start(["ttm_store"])
+    rep = step(h, prob)
+    st = h.profile_stop()
+    print(rep["l"], rep["m"], st, flush=True)
+    assert set(st) == {"ttm_store"}
+    s = st["ttm_store"]
+    assert s["launches"] > 0 and s["ms"] > 0
+    # every launch is a mode product of whole N-vectors: 2 n N flops per
+    # vector, so the total is a positive multiple of 2 n N
+    n, N = 48, 48 ** 3
+    k = s["flops"] / (2.0 * n * N)
+    assert k >= s["launches"] and abs(k - round(k)) < 1e-9
+    # at least the input and the output of each vector: 16 N bytes
+    assert s["bytes"] >= 16.0 * N * s["launches"] - 1e-6
+
+
+def test_all_classes(h, prob):
+    h.profile_start()
+    rep = step(h, prob)
+    st = h.profile_stop()
+    want = {"ttm_store", "ttm_accum", "gemm"} | ({"ttm_square"} if rep["l"] > 0 else set())
+    assert want <= set(st), (rep["l"], set(st))
+
+
+def test_pause_keeps_only_enabled_launches(h, prob):
+    h.profile_start(["ttm_store"])
+    step(h, prob)
+    one = h.profile_stop()["ttm_store"]
+
+    h.profile_start(["ttm_store"])
+    h.profile_enable(False)
+    step(h, prob)
+    h.profile_enable(True)
+    step(h, prob)
+    h.profile_enable(False)
+    step(h, prob)
+    got = h.profile_stop()["ttm_store"]
+    assert got["launches"] == one["launches"]
+    assert got["flops"] == one["flops"] and got["bytes"] == one["bytes"]
+
+    h.profile_start(["ttm_store"])
+    for _ in range(3):
+        step(h, prob)
+    three = h.profile_stop()["ttm_store"]
+    assert three["launches"] == 3 * one["launches"]
+    assert np.isclose(three["flops"], 3 * one["flops"])
+
+
+def test_enable_needs_an_open_profile(h):
+    from paper_2211_00696_amd.phiq import PhiqError
+
+    with pytest.raises(PhiqError):
+        h.profile_enable(True)
+    h.profile_start(["gemm"])
+    h.profile_stop()
+    with pytest.raises(PhiqError):
+        h.profile_enable(False)
