@@ -228,9 +228,10 @@ __global__ __launch_bounds__(C::NT) void gemm_jobs_kernel(const GemmJob* __restr
 // The same for n <= kPanelK: a block loads its whole 32-row panel of A and
 // 32-column panel of B in one pass (every load in flight at once, one
 // barrier), then four waves take a 16 x 16 quarter of the 32 x 32 output
-// each.  The k order of the MFMA chain is the one above, so the two kernels
-// give the same bits; this one pays one load latency per block instead of
-// one per 16-deep chunk.
+// each.  The k order of the MFMA chain is the one above (which only adds
+// zero products past n), so the two kernels agree up to the sign of exact
+// zeros; this one pays one load latency per block instead of one per
+// 16-deep chunk.
 constexpr int kPanelK = 128;
 __global__ __launch_bounds__(256) void gemm_panel_kernel(const GemmJob* __restrict__ jobs) {
   constexpr int BM = 32, BN = 32, LDK = kPanelK + 2, NT = 256, PER = BM * kPanelK / NT;
