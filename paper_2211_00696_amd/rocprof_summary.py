@@ -52,7 +52,7 @@ CLASS_RE = {
     "ttm_accum": re.compile(r"(^|::)ttm_(lp_)?accum_kernel"),
     "ttm_square": re.compile(r"(^|::)ttm_(lp_)?square(_all)?_kernel|(^|::)i8_product_kernel<\d+, \d+, 2>"),
     "slice": re.compile(r"(^|::)i8_(slice_rows|absmax|slice_tensor)_kernel"),
-    "gemm": re.compile(r"(^|::)gemm_jobs_kernel"),
+    "gemm": re.compile(r"(^|::)gemm_(jobs|panel)_kernel"),
     "taylor": re.compile(r"(^|::)taylor_jobs_kernel"),
     "scale": re.compile(r"(^|::)scale_jobs_kernel"),
     "node_sum": re.compile(r"(^|::)node_sum_kernel"),
