@@ -111,7 +111,21 @@ typedef struct {
                             /* combination), 2 every chain, 0 none (default: on     */
                             /* gfx950 at n = 128 it saved no time in a phi-action   */
                             /* and cost 3% in ETD-RK4)                              */
+  int accept_floor;         /* FP32 / BF16X3: 0 (default) = a tol below the form's  */
+                            /* rounding floor (PHIQ_FLOOR_FP32 / _BF16X3) is        */
+                            /* refused with PHIQ_ERR_UNSUPPORTED; 1 = run anyway:   */
+                            /* the result then carries the floor, not tol, and the  */
+                            /* report says so (precision_floor, tol_met = 0)        */
 } phiq_options;
+
+/* Rounding floors of the lower-precision mode products: an upper level of
+ * the relative error per phi_k (inf-norm, against the exact action) that
+ * the FP32-accumulated products leave whatever the quadrature and squaring
+ * do, measured on the 3D advection-diffusion workloads up to n_d = 256
+ * (FP32 ~8e-7, split bf16 ~9e-6) with a margin.  The method's own
+ * truncation error (log10_bound) comes on top of it. */
+#define PHIQ_FLOOR_FP32 2e-6
+#define PHIQ_FLOOR_BF16X3 3e-5
 
 /* What a plan / call did.  Times are filled by phiq_action only. */
 typedef struct {
@@ -126,6 +140,12 @@ typedef struct {
   int selector;        /* how (l, m) was chosen: 0 Algorithm setup_quadrature   */
                        /* (or forced), 1 network, 2 network with m raised to    */
                        /* what the bound needs, 3 network rejected (fallback)   */
+  double precision_floor; /* rounding floor of the mode products' precision     */
+                       /* (PHIQ_FLOOR_FP32 / _BF16X3; 0 for FP64 and int8       */
+                       /* digits, whose digit count follows tol)                */
+  int tol_met;         /* 1 if tol >= precision_floor, i.e. the requested       */
+                       /* tolerance is within what the precision form reaches;  */
+                       /* 0 only when accept_floor let a smaller tol through    */
 } phiq_report;
 
 typedef struct phiq_handle_s* phiq_handle;
@@ -422,11 +442,14 @@ phiq_status phiq_profile_stop(phiq_handle h, phiq_kernel_stat* stats, int max_st
  * NULL or no profile is open (before phiq_profile_start or after stop). */
 phiq_status phiq_profile_enable(phiq_handle h, int on);
 
-/* Tile shape of the FP64 mode products for every later launch of one kind:
- * kind 0 (plain mode product), 1 (with the node sum), 2 (with the squaring
- * combination); cfg -1 restores the autotuned or default choice, 0..count-1
- * forces that shape (tuning, testing; squaring shapes 7.. need p <= 4).
- * *count (nullable) = number of shapes of the kind. */
+/* Tile shape of the mode products for every later launch of one kind:
+ * FP64 kind 0 (plain mode product), 1 (with the node sum), 2 (with the
+ * squaring combination); split bf16 kind 3 (plain) and 4 (squaring), where
+ * cfg 0 is the general tile kernel and cfg >= 1 the kernels that keep the
+ * 1D factor resident in LDS (n_d in {64, 128, 256}; other shapes always take
+ * the general kernel).  cfg -1 restores the autotuned or default choice,
+ * 0..count-1 forces that shape (tuning, testing; FP64 squaring shapes 7..
+ * need p <= 4).  *count (nullable) = number of shapes of the kind. */
 phiq_status phiq_tile_config(phiq_handle h, int kind, int cfg, int* count);
 
 /* ---------------------------------------------------------------------------

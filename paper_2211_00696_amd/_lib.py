@@ -78,6 +78,7 @@ class Options(ctypes.Structure):
         ("use_graphs", c_int),
         ("selector", c_int),
         ("slab_products", c_int),
+        ("accept_floor", c_int),
     ]
 
 
@@ -92,6 +93,8 @@ class Report(ctypes.Structure):
         ("cc_err", c_double),
         ("workspace_bytes", c_size_t),
         ("selector", c_int),
+        ("precision_floor", c_double),
+        ("tol_met", c_int),
     ]
 
     def as_dict(self):

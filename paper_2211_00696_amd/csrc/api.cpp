@@ -260,7 +260,7 @@ struct phiq_handle_s {
   std::vector<GraphEntry> graphs;
   std::vector<std::vector<long long>> seen;  // keys run once eagerly
   std::vector<TuneEntry> tune;  // fastest tile shape per launch shape (autotuner)
-  int force_cfg[3] = {-1, -1, -1};  // phiq_tile_config: one shape for every launch of a kind
+  int force_cfg[5] = {-1, -1, -1, -1, -1};  // phiq_tile_config: one shape for every launch of a kind
   DevBuf ws;                     // execute workspace (T0, T1, Ya, Yb)
   DevBuf scratch;                // transient plans (phiq_action) and phiq_expm
   std::vector<DevBuf> cc_levels; // node vectors of the adaptive rule, per level
@@ -445,7 +445,11 @@ phiq_status L_ttm(phiq_handle h, int cls, const TtmArgs& a0, phiq_precision prec
   }
   ttm_work(a, cls, &fl, &by);
   const int kind = kind_of(cls);
-  int cfg = (prec != PHIQ_PREC_FP64) ? -1 : (h->force_cfg[kind] >= 0 ? h->force_cfg[kind] : tuned_cfg(h, kind, a));
+  // split bf16: kinds 3 / 4 force the resident-factor shapes of the plain
+  // and the squaring products (0 = the general tile kernel)
+  int cfg = (prec == PHIQ_PREC_BF16X3 && kind != 1) ? h->force_cfg[kind == 0 ? 3 : 4]
+            : (prec != PHIQ_PREC_FP64) ? -1
+                                       : (h->force_cfg[kind] >= 0 ? h->force_cfg[kind] : tuned_cfg(h, kind, a));
   if (prec == PHIQ_PREC_FP64 && cfg < 0) cfg = fallback_cfg(kind, a);
   return prof_launch(h, st, cls, fl, by, [&] { return launch_kind(kind, a, prec, st, cfg); });
 }
@@ -737,6 +741,9 @@ phiq_status plan_build(phiq_handle h, const phiq_kron_op* op, double t, int p, d
     for (int d = 0; d < op->dim; ++d)
       if (op->n[d] % 32 != 0 || op->n[d] > 128) return PHIQ_ERR_UNSUPPORTED;
   }
+  // a tolerance below the lower-precision products' rounding floor cannot be
+  // met; refused unless the caller accepts the floor
+  if (tol < precision_floor(opt.precision) && !opt.accept_floor) return PHIQ_ERR_UNSUPPORTED;
   if (!std::isfinite(opt.c1) || !std::isfinite(opt.c2) || !std::isfinite(opt.alpha)) return PHIQ_ERR_NONFINITE;
   if (opt.c1 < 0 || opt.c2 < 0 || opt.l < -1 || opt.l > 60 || opt.m < -1 || opt.m == 0 || opt.m > 4096 ||
       opt.cc_max_doublings < 1 || opt.cc_max_doublings > 10)
@@ -969,6 +976,8 @@ phiq_status plan_build(phiq_handle h, const phiq_kron_op* op, double t, int p, d
     rep->log10_bound = P->log10_bound;
     rep->selector = P->selector;
     rep->workspace_bytes = h->held();
+    rep->precision_floor = precision_floor(P->opt.precision);
+    rep->tol_met = P->tol >= rep->precision_floor;
   }
   *out = P;
   return PHIQ_OK;
@@ -2075,6 +2084,8 @@ phiq_status phiq_plan_execute(phiq_plan plan, const double* v, int nrhs, double*
     const int chains_per = (plan->p > 0 ? rep->m + plan->l * plan->p : 0) + 1;
     rep->ttm_chains = chains_per * nrhs;
     rep->workspace_bytes = plan->h->held();
+    rep->precision_floor = precision_floor(plan->opt.precision);
+    rep->tol_met = plan->tol >= rep->precision_floor;
   }
   return PHIQ_OK;
 }
@@ -2417,8 +2428,8 @@ phiq_status phiq_profile_stop(phiq_handle h, phiq_kernel_stat* stats, int max_st
 }
 
 phiq_status phiq_tile_config(phiq_handle h, int kind, int cfg, int* count) {
-  if (!h || kind < 0 || kind > 2) return PHIQ_ERR_INVALID_ARG;
-  const int nc = ttm_num_configs(kind);
+  if (!h || kind < 0 || kind > 4) return PHIQ_ERR_INVALID_ARG;
+  const int nc = kind <= 2 ? ttm_num_configs(kind) : (kind == 3 ? bf16r_num_configs() : 2);
   if (count) *count = nc;
   if (cfg < -1 || cfg >= nc) return PHIQ_ERR_INVALID_ARG;
   h->force_cfg[kind] = cfg;

@@ -653,6 +653,8 @@ extern "C" phiq_status phiq_action_batched(phiq_handle h, int nprob, const phiq_
       rep->selector = P.pp.selector;
       rep->ttm_chains = P.pr->nrhs * ((P.pr->p > 0 ? P.pp.m + P.pp.l * P.pr->p : 0) + 1);
       rep->workspace_bytes = S.total;
+      rep->precision_floor = 0.0;  // the one-launch path is FP64
+      rep->tol_met = 1;
     }
   }
 

@@ -533,6 +533,10 @@ int default_cfg(int kind, int M, int nb) {
 int ttm_num_configs(int kind) { return kind == 1 ? 7 : (kind == 2 ? 12 : 14); }
 
 int launch_ttm_store(const TtmArgs& a, phiq_precision prec, void* stream, int cfg) {
+  if (prec == PHIQ_PREC_BF16X3 && !a.nn) {
+    const int r = launch_ttm_store_bf16r(a, stream, cfg);
+    if (r != hipErrorNotSupported) return r;
+  }
   if (prec != PHIQ_PREC_FP64) return a.nn ? hipErrorInvalidValue : launch_ttm_store_lowp(a, prec, stream);
   hipStream_t st = (hipStream_t)stream;
   if (a.nn) return launch_nn(0, a, st);
@@ -593,6 +597,10 @@ int square_all_cfg(const TtmArgs& a, hipStream_t st) {
 }  // namespace
 
 int launch_ttm_square(const TtmArgs& a, phiq_precision prec, void* stream, int cfg) {
+  if (prec == PHIQ_PREC_BF16X3 && !a.nn) {
+    const int r = launch_ttm_square_bf16r(a, stream, cfg);
+    if (r != hipErrorNotSupported) return r;
+  }
   if (prec != PHIQ_PREC_FP64) return a.nn ? hipErrorInvalidValue : launch_ttm_square_lowp(a, prec, stream);
   hipStream_t st = (hipStream_t)stream;
   if (a.nn) return launch_nn(2, a, st);

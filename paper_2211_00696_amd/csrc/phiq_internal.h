@@ -26,6 +26,11 @@ void clenshaw_curtis(int m, double* theta, double* w);
 
 // ---- api.cpp --------------------------------------------------------------
 phiq_status validate_op(const phiq_kron_op* op);
+// Rounding floor of a precision form's mode products (0 where the digit
+// count or FP64 follows tol).
+inline double precision_floor(phiq_precision prec) {
+  return prec == PHIQ_PREC_FP32 ? PHIQ_FLOOR_FP32 : prec == PHIQ_PREC_BF16X3 ? PHIQ_FLOOR_BF16X3 : 0.0;
+}
 double sum_infnorms(const phiq_kron_op* op);
 
 // Host-chosen parameters of one phi-action (Algorithm 5 with beta = 1).
@@ -191,6 +196,13 @@ int ttm_num_configs(int kind);
 int launch_ttm_store(const TtmArgs& a, phiq_precision prec, void* stream, int cfg);
 int launch_ttm_accum(const TtmArgs& a, phiq_precision prec, void* stream, int cfg);
 int launch_ttm_square(const TtmArgs& a, phiq_precision prec, void* stream, int cfg);
+// Split-bf16 products with the factor resident in LDS (kernels_bf16r.hip),
+// n in {64, 128, 256}: hipErrorNotSupported for other shapes or cfg 0 (the
+// caller then runs the general kernel).  Store cfg 1..3 pick the wave and
+// column-block shape, -1 the default.
+int bf16r_num_configs();
+int launch_ttm_store_bf16r(const TtmArgs& a, void* stream, int cfg);
+int launch_ttm_square_bf16r(const TtmArgs& a, void* stream, int cfg);
 
 // Products along axes 2 and 1 of nbatch tensors n0 x kSlabN x kSlabN in one
 // pass (kernels_slab.hip), layout unchanged:

@@ -73,7 +73,8 @@ class _Op:
 
 
 def options(rule="gauss", precision="fp64", l=None, m=None, alpha=None, c1=None, c2=None,
-            cc_max_doublings=None, workspace_cap=None, use_graphs=None, selector=None, slab_products=None):
+            cc_max_doublings=None, workspace_cap=None, use_graphs=None, selector=None, slab_products=None,
+            accept_floor=None):
     lib = L.load()
     o = L.Options()
     _check(lib.phiq_options_default(byref(o)), "phiq_options_default")
@@ -99,6 +100,8 @@ def options(rule="gauss", precision="fp64", l=None, m=None, alpha=None, c1=None,
         o.selector = L.SELECTOR[selector]
     if slab_products is not None:
         o.slab_products = int(slab_products)
+    if accept_floor is not None:
+        o.accept_floor = int(bool(accept_floor))
     return o
 
 
@@ -425,8 +428,10 @@ class Handle:
         return w, hist[:steps]
 
     def tile_config(self, kind, cfg=-1):
-        """Force tile shape cfg for every FP64 launch of kind 0 (store), 1 (node sum), 2 (squaring);
-        -1 restores the tuned/default choice.  Returns the number of shapes of the kind."""
+        """Force tile shape cfg for every launch of a kind: FP64 0 (store), 1 (node sum), 2 (squaring);
+        split bf16 3 (store) and 4 (squaring), where 0 is the general tile kernel and 1.. keep the
+        1D factor resident in LDS.  -1 restores the tuned/default choice.  Returns the number of
+        shapes of the kind."""
         lib = L.load()
         n = c_int()
         _check(lib.phiq_tile_config(self._h, int(kind), int(cfg), byref(n)), "phiq_tile_config")
