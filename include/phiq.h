@@ -251,6 +251,30 @@ phiq_status phiq_plan_execute_combo(phiq_plan plan, const double* const* b, doub
 
 phiq_status phiq_plan_destroy(phiq_plan plan);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Runs
+ * phiq_plan_execute for one vector (nrhs = 1) of a Gauss-rule plan with
+ * FP64, FP32 or split-bf16 mode products, keeping its intermediate tensors in
+ * a fixed device array of the library instead of the handle's workspace.  It
+ * allocates and frees nothing; the plan (phiq_plan_create) and v, out are
+ * the caller's.
+ *   v     DEVICE, N doubles; out DEVICE, (p+1) x N doubles; no overlap.
+ *   need  HOST, nullable: set to the bytes of the array the plan needs,
+ *         2 max(m+1, p) N e + 2 p N 8 (e = 8 for FP64, 4 otherwise; each
+ *         term rounded up to 256), also when that exceeds the array.
+ * The array holds PHIQ_NOALLOC_SCRATCH_BYTES (64 MiB) per GPU, from the
+ * library's load until the process ends.  Errors: PHIQ_ERR_OOM when the plan
+ * needs more than that (e.g. 3D n = 64 with m <= 12 fits, n = 128 does not);
+ * PHIQ_ERR_UNSUPPORTED for the Clenshaw-Curtis rule, int8 digits, or while
+ * live timing (phiq_profile_start) is on.  No element of the array needs to
+ * start at zero: the call reads only what it wrote first.  Every call on one
+ * GPU shares that GPU's array and leaves its contents behind: calls that
+ * overlap on one GPU (other streams, threads or handles) race and must be
+ * ordered by the caller. */
+#define PHIQ_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+phiq_status phiq_plan_execute_noalloc(phiq_plan plan, const double* v, double* out, size_t* need,
+                                      hipStream_t stream);
+
 /* One call: plan_create + plan_execute + plan_destroy.  v DEVICE N,
  * out DEVICE (p+1) x N.  The whole call is on `stream`; the host returns
  * after enqueueing (Gauss) or after the last error check (CC). */

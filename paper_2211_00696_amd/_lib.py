@@ -40,6 +40,7 @@ EXPORTS = [
     "phiq_plan_execute",
     "phiq_plan_execute_combo",
     "phiq_plan_destroy",
+    "phiq_plan_execute_noalloc",
     "phiq_action",
     "phiq_action_batched",
     "phiq_batch_info",
@@ -157,6 +158,7 @@ def load():
         "phiq_plan_execute": (c_int, [c_void_p, c_void_p, c_int, c_void_p, P(Report), c_void_p]),
         "phiq_plan_execute_combo": (c_int, [c_void_p, P(c_void_p), c_void_p, c_void_p]),
         "phiq_plan_destroy": (c_int, [c_void_p]),
+        "phiq_plan_execute_noalloc": (c_int, [c_void_p, c_void_p, c_void_p, P(c_size_t), c_void_p]),
         "phiq_action": (c_int, [c_void_p, P(KronOp), c_double, c_int, c_void_p, c_double, P(Options), c_void_p,
                                 P(Report), c_void_p]),
         "phiq_action_batched": (c_int, [c_void_p, c_int, P(Problem), P(Options), c_void_p]),

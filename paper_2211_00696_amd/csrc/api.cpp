@@ -1142,16 +1142,36 @@ phiq_status squaring(const phiq_plan_s* P, double* Ycur, double* Yother, double*
   return PHIQ_OK;
 }
 
-phiq_status execute_gauss(phiq_plan P, const double* v, double* out, hipStream_t st) {
+// Device bytes of the intermediate tensors of one Gauss-rule execution:
+// two node batches (max(m + 1, p) tensors each) and two p-vector squaring
+// iterates.
+size_t gauss_ws_bytes(const phiq_plan_s* P) {
+  const long long N = P->N;
+  const int nb = std::max(P->m + 1, P->p);
+  const size_t tbytes = (P->D > 1 ? (size_t)nb * N * tensor_elem(P) : 0);
+  const size_t ybytes = (size_t)P->p * N * sizeof(double);
+  return 2 * align_up(tbytes) + 2 * align_up(ybytes);
+}
+
+// ws (nullable): a caller-provided workspace of ws_cap bytes used instead of
+// the handle's (no allocation; PHIQ_ERR_OOM when it is too small).
+phiq_status execute_gauss(phiq_plan P, const double* v, double* out, hipStream_t st, void* ws = nullptr,
+                          size_t ws_cap = 0) {
   phiq_handle h = P->h;
   const long long N = P->N;
   const int p = P->p;
   const int nb = std::max(P->m + 1, p);
   const size_t tbytes = (P->D > 1 ? (size_t)nb * N * tensor_elem(P) : 0);
   const size_t ybytes = (size_t)p * N * sizeof(double);
-  const size_t need = 2 * align_up(tbytes) + 2 * align_up(ybytes);
-  PHIQ_TRY(ensure(h, h->ws, std::max<size_t>(need, kAlign)));
-  char* wb = (char*)h->ws.p;
+  const size_t need = gauss_ws_bytes(P);
+  char* wb;
+  if (ws) {
+    if (need > ws_cap) return PHIQ_ERR_OOM;
+    wb = (char*)ws;
+  } else {
+    PHIQ_TRY(ensure(h, h->ws, std::max<size_t>(need, kAlign)));
+    wb = (char*)h->ws.p;
+  }
   void* T0 = wb;
   void* T1 = wb + align_up(tbytes);
   double* Ya = (double*)(wb + 2 * align_up(tbytes));
@@ -2001,6 +2021,11 @@ phiq_status phiq_create(phiq_handle* out, int device) {
     return PHIQ_ERR_HIP;
   }
   if (device < 0 || device >= count) return PHIQ_ERR_INVALID_ARG;
+  {
+    // the fixed array of phiq_plan_execute_noalloc: its address on this device
+    DeviceGuard g(device);
+    PHIQ_TRY(noalloc_scratch_init(device));
+  }
   phiq_handle h = new (std::nothrow) phiq_handle_s;
   if (!h) return PHIQ_ERR_OOM;
   h->device = device;
@@ -2566,6 +2591,28 @@ bool plan_profiling(phiq_plan P) { return P && P->h->prof.on; }
 
 const float* handle_mlp(phiq_handle h) { return (h && !h->mlp.empty()) ? h->mlp.data() : nullptr; }
 
+}  // namespace phiq
+
+namespace phiq {
+phiq_status plan_execute_in(phiq_plan P, const double* v, double* out, void* ws, size_t ws_cap, hipStream_t st,
+                            size_t* need) {
+  if (!P || !v || !out || !ws) return PHIQ_ERR_INVALID_ARG;
+  if (P->opt.rule != PHIQ_RULE_GAUSS || P->opt.precision == PHIQ_PREC_INT8) return PHIQ_ERR_UNSUPPORTED;
+  // live timing creates and records events per launch
+  if (P->h->prof.on) return PHIQ_ERR_UNSUPPORTED;
+  const long long N = P->N;
+  const char* vb = (const char*)v;
+  const char* ve = vb + (size_t)N * sizeof(double);
+  const char* ob = (const char*)out;
+  const char* oe = ob + (size_t)(P->p + 1) * N * sizeof(double);
+  if (vb < oe && ob < ve) return PHIQ_ERR_INVALID_ARG;
+  const size_t nd = gauss_ws_bytes(P);
+  if (need) *need = nd;
+  if (nd > ws_cap) return PHIQ_ERR_OOM;
+  DeviceGuard g(P->h->device);
+  return execute_gauss(P, v, out, st, ws, ws_cap);
+}
+int plan_device(phiq_plan P) { return P ? P->h->device : -1; }
 }  // namespace phiq
 
 extern "C" phiq_status phiq_selector_set(phiq_handle h, const float* w) {

@@ -26,6 +26,12 @@ void clenshaw_curtis(int m, double* theta, double* w);
 
 // ---- api.cpp --------------------------------------------------------------
 phiq_status validate_op(const phiq_kron_op* op);
+// noalloc.hip: resolve the fixed scratch array's address on `device` (which
+// must be current); api.cpp: one Gauss execution with a caller workspace.
+phiq_status noalloc_scratch_init(int device);
+phiq_status plan_execute_in(phiq_plan P, const double* v, double* out, void* ws, size_t ws_cap, hipStream_t st,
+                            size_t* need);
+int plan_device(phiq_plan P);
 // Rounding floor of a precision form's mode products (0 where the digit
 // count or FP64 follows tol).
 inline double precision_floor(phiq_precision prec) {

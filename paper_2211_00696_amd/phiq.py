@@ -8,7 +8,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from ctypes import POINTER, byref, c_double, c_int, c_void_p
+from ctypes import POINTER, byref, c_double, c_int, c_size_t, c_void_p
 
 import numpy as np
 
@@ -200,6 +200,18 @@ class Plan:
         _check(lib.phiq_plan_execute(self._ptr, _dev_ptr(v, "v"), nrhs, _dev_ptr(out, "out"), byref(rep),
                                      _stream_ptr(stream)), "phiq_plan_execute")
         return out, rep.as_dict()
+
+    def execute_noalloc(self, v, out, stream=None):
+        """One vector through phiq_plan_execute_noalloc: the plan's intermediates in the library's
+        fixed device array (nothing allocated).  out (p+1, N) float64 CUDA tensor, caller-owned.
+        Returns the bytes of the array the plan needs."""
+        lib = L.load()
+        if v.numel() != self.N or out.numel() != (self.p + 1) * self.N:
+            raise ValueError("v must hold N values and out (p+1) x N")
+        need = c_size_t()
+        _check(lib.phiq_plan_execute_noalloc(self._ptr, _dev_ptr(v, "v"), _dev_ptr(out, "out"), byref(need),
+                                             _stream_ptr(stream)), "phiq_plan_execute_noalloc")
+        return need.value
 
     def execute_combo(self, bs, out=None, stream=None):
         """out = sum_j phi_j(-tA) bs[j], j = 0..p; bs holds p+1 entries, each a
