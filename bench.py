@@ -116,7 +116,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--n", type=int, default=None,
+                    help="grid points per axis (default: 256 for advdiff3d and precision256, 128 for seeds and combo)")
     ap.add_argument("--rule", default="gauss", choices=["gauss", "cc"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3", "int8"])
     ap.add_argument("--seed", type=int, default=0)
@@ -142,6 +143,8 @@ def main():
                          "of known size that calibrates hardware byte counters taken over the same run)")
     args = ap.parse_args()
 
+    if args.n is None:
+        args.n = 256 if args.workload in ("advdiff3d", "precision256") else 128
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus %d is not supported "
                                    "(the phi-action of one problem is not split across GPUs here)" % args.gpus}))
@@ -546,7 +549,7 @@ def bench_precision(args, rank):
     from oracle import phiquad
     from paper_2211_00696_amd import inputs, phiq, selector
 
-    n = args.n if args.n != 128 else 256
+    n = args.n
     pr = inputs.problem("advdiff3d", seed=args.seed, n=n)
     N, p = pr["v"].size, pr["p"]
     v = torch.from_numpy(pr["v"]).cuda()

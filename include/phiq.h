@@ -116,6 +116,13 @@ typedef struct {
                             /* refused with PHIQ_ERR_UNSUPPORTED; 1 = run anyway:   */
                             /* the result then carries the floor, not tol, and the  */
                             /* report says so (precision_floor, tol_met = 0)        */
+  double selector_slack;    /* PHIQ_SEL_MLP: decades by which the a priori bound at */
+                            /* the network's (l, m) may exceed tol (0..12).  0, the */
+                            /* default, is the certified mode: the bound must meet  */
+                            /* tol, as in Algorithm setup_quadrature.  A network    */
+                            /* trained on measured errors (empirical mode) is used  */
+                            /* with the slack calibrated on its own sweep: the      */
+                            /* largest bound excess its training labels needed      */
 } phiq_options;
 
 /* Rounding floors of the lower-precision mode products: an upper level of

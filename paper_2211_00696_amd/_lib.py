@@ -80,6 +80,7 @@ class Options(ctypes.Structure):
         ("selector", c_int),
         ("slab_products", c_int),
         ("accept_floor", c_int),
+        ("selector_slack", c_double),
     ]
 
 

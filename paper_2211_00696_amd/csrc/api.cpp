@@ -134,7 +134,8 @@ phiq_status select_params(const phiq_kron_op* op, double t, int p, double tol, c
       if (opt.selector == PHIQ_SEL_MLP && mlp && opt.rule == PHIQ_RULE_GAUSS && opt.m <= 0 && alpha > 1e-12 &&
           l >= 0 && nq >= 0) {
         int lm = l, nm = nq, used = 0;
-        if (mlp_choose(mlp, op, norms, t, p, tol, alpha, l, nq, &lm, &nm, &used)) {
+        if (mlp_choose(mlp, op, norms, t, p, tol, std::pow(10.0, opt.selector_slack), alpha, l, nq, &lm, &nm,
+                       &used)) {
           l = lm;
           nq = nm;
         }
@@ -261,6 +262,13 @@ struct phiq_handle_s {
   std::vector<std::vector<long long>> seen;  // keys run once eagerly
   std::vector<TuneEntry> tune;  // fastest tile shape per launch shape (autotuner)
   int force_cfg[5] = {-1, -1, -1, -1, -1};  // phiq_tile_config: one shape for every launch of a kind
+  // adaptive Clenshaw-Curtis: the device decisions per level, their pinned
+  // host copies and events, and the flag that guards the launches of a
+  // speculative level (set only while such a level is enqueued)
+  DevBuf cc_ctl;
+  CcCtl* cc_ctl_host = nullptr;
+  std::vector<hipEvent_t> cc_ev;
+  const int* guard = nullptr;
   DevBuf ws;                     // execute workspace (T0, T1, Ya, Yb)
   DevBuf scratch;                // transient plans (phiq_action) and phiq_expm
   std::vector<DevBuf> cc_levels; // node vectors of the adaptive rule, per level
@@ -433,6 +441,7 @@ phiq_status L_ttm(phiq_handle h, int cls, const TtmArgs& a0, phiq_precision prec
                   const TwinMap* tw = nullptr) {
   double fl, by;
   TtmArgs a = a0;
+  a.stop = h->guard;
   if (prec != PHIQ_PREC_FP64) {
     if (!tw) return PHIQ_ERR_INVALID_ARG;
     tw->lookup(a.E, prec, &a.Ea, &a.Eb);
@@ -746,7 +755,8 @@ phiq_status plan_build(phiq_handle h, const phiq_kron_op* op, double t, int p, d
   if (tol < precision_floor(opt.precision) && !opt.accept_floor) return PHIQ_ERR_UNSUPPORTED;
   if (!std::isfinite(opt.c1) || !std::isfinite(opt.c2) || !std::isfinite(opt.alpha)) return PHIQ_ERR_NONFINITE;
   if (opt.c1 < 0 || opt.c2 < 0 || opt.l < -1 || opt.l > 60 || opt.m < -1 || opt.m == 0 || opt.m > 4096 ||
-      opt.cc_max_doublings < 1 || opt.cc_max_doublings > 10)
+      opt.cc_max_doublings < 1 || opt.cc_max_doublings > 10 || !(opt.selector_slack >= 0.0) ||
+      opt.selector_slack > 12.0)
     return PHIQ_ERR_INVALID_ARG;
 
   PlanParams pp;
@@ -1009,7 +1019,7 @@ phiq_status chain_front(const phiq_plan_s* P, const double* X, long long xs, dou
   // on a side stream, where a block that takes a whole CU's LDS waits for a
   // free CU
   const int sp = P->opt.slab_products;
-  if (P->D == 3 && P->n[1] == kSlabN && P->n[2] == kSlabN && P->opt.precision == PHIQ_PREC_FP64 &&
+  if (P->D == 3 && P->n[1] == kSlabN && P->n[2] == kSlabN && P->opt.precision == PHIQ_PREC_FP64 && !P->h->guard &&
       (sp == 2 || (sp == 1 && nb == 1 && !beside))) {
     SlabArgs s{};
     s.X = X;
@@ -1701,12 +1711,29 @@ phiq_status execute_cc(phiq_plan P, const double* v, double* out, hipStream_t st
     }
   }
 
-  double* ycur = Ya;
-  double* ynew = Yb;
-  double err = INFINITY;
-  int level = 0;
-  bool converged = false;
-  for (;; ++level) {
+  // per-level device decisions, their pinned host copies and events
+  const int nlev = cap + 1;
+  PHIQ_TRY(ensure(h, h->cc_ctl, (size_t)(nlev + 1) * sizeof(CcCtl)));
+  if (!h->cc_ctl_host) {
+    if (hipHostMalloc((void**)&h->cc_ctl_host, 16 * sizeof(CcCtl), hipHostMallocDefault) != hipSuccess) {
+      h->cc_ctl_host = nullptr;
+      return PHIQ_ERR_OOM;
+    }
+  }
+  while ((int)h->cc_ev.size() < nlev + 1) {
+    hipEvent_t e = nullptr;
+    PHIQ_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    h->cc_ev.push_back(e);
+  }
+  CcCtl* ctl = (CcCtl*)h->cc_ctl.p;
+  double* ybuf[2] = {Ya, Yb};
+
+  // One level of Algorithm 2: the node vectors of its new nodes, the node sum
+  // over every stored node with the weights of the level's rule, and (from
+  // level 1 on) the relative change, decided on the device and copied to the
+  // host.  guard (nullable): when the flag is set on the device, the level's
+  // products, node sum and change test do nothing.
+  auto run_level = [&](int level, const int* guard) -> phiq_status {
     PHIQ_TRY(cc_ensure_level(P, level, st));
     const int cnt = P->cc_count[level];
     if ((int)h->cc_levels.size() <= level) h->cc_levels.resize(level + 1);
@@ -1719,12 +1746,17 @@ phiq_status execute_cc(phiq_plan P, const double* v, double* out, hipStream_t st
       E[d] = cc_level_E(P, level, d);
       es[d] = (long long)P->n[d] * P->n[d];
     }
+    h->guard = guard;
     Front f;
-    PHIQ_TRY(chain_front(P, v, 0, E, es, cnt, T0, T1, st, &f));
-    TtmArgs a = final_args(P, E[0], es[0], f, cnt);
-    a.O = V;
-    a.os = N;
-    PHIQ_TRY(L_ttm(P->h, K_TTM_STORE, a, P->opt.precision, st, &P->twins));
+    phiq_status sf = chain_front(P, v, 0, E, es, cnt, T0, T1, st, &f);
+    if (sf == PHIQ_OK) {
+      TtmArgs a = final_args(P, E[0], es[0], f, cnt);
+      a.O = V;
+      a.os = N;
+      sf = L_ttm(P->h, K_TTM_STORE, a, P->opt.precision, st, &P->twins);
+    }
+    h->guard = nullptr;
+    PHIQ_TRY(sf);
     // weights of the full (2n+1)-point rule, n = 3*2^level, in storage order
     const int n2 = 6 << level;
     std::vector<double> xt(n2 + 1), wt(n2 + 1);
@@ -1753,33 +1785,42 @@ phiq_status execute_cc(phiq_plan P, const double* v, double* out, hipStream_t st
     }
     PHIQ_TRY(stage_copy(h, slot, P->coef, sizeof(double) * (size_t)p * total, st));
     // y_j = sum_i w_i x_i^{j-1}/(j-1)! v_i (Algorithm 2, step 3)
+    double* ynew = ybuf[level % 2];
     PHIQ_TRY(prof_launch(h, st, K_NODE_SUM, 2.0 * p * total * (double)N, 8.0 * (total + p) * (double)N,
-                         [&] { return launch_node_sum(segs, N, P->coef, total, p, ynew, st); }));
+                         [&] { return launch_node_sum(segs, N, P->coef, total, p, ynew, st, guard); }));
     if (level > 0) {
       // err = max_j ||y_j - y~_j||_inf / ||y_j||_inf (Algorithm 2, step 4)
+      double* yold = ybuf[(level - 1) % 2];
       PHIQ_TRY(prof_launch(h, st, K_ABSDIFF, 2.0 * p * (double)N, 16.0 * p * (double)N, [&] {
-        return launch_absdiff_max(ynew, ycur, p, N, (double*)h->partial.p, nblk, st);
+        return launch_absdiff_max(ynew, yold, p, N, (double*)h->partial.p, nblk, st, guard);
       }));
-      PHIQ_HIP(hipMemcpyAsync(h->partial_host, h->partial.p, (size_t)nblk * p * 2 * sizeof(double),
-                              hipMemcpyDeviceToHost, st));
-      PHIQ_HIP(hipStreamSynchronize(st));
-      err = 0.0;
-      for (int j = 0; j < p; ++j) {
-        double num = 0.0, den = 0.0;
-        for (int b = 0; b < nblk; ++b) {
-          num = std::max(num, h->partial_host[((size_t)b * p + j) * 2 + 0]);
-          den = std::max(den, h->partial_host[((size_t)b * p + j) * 2 + 1]);
-        }
-        err = std::max(err, den > 0 ? num / den : num);
-      }
+      PHIQ_HIP(launch_cc_decide((const double*)h->partial.p, nblk, p, cc_tolerance(P), guard, ctl + level, st));
+      PHIQ_HIP(hipMemcpyAsync(h->cc_ctl_host + level, ctl + level, sizeof(CcCtl), hipMemcpyDeviceToHost, st));
+      PHIQ_HIP(hipEventRecord(h->cc_ev[level], st));
     }
-    std::swap(ycur, ynew);
-    if (level > 0 && err <= cc_tolerance(P)) {
+    return PHIQ_OK;
+  };
+
+  // Levels 0 and 1 always run.  Then, before the host reads level k's
+  // decision, level k + 1 is already enqueued behind a guard on that
+  // decision: the GPU works on it while the host waits, and after
+  // convergence its launches return at once.
+  PHIQ_TRY(run_level(0, nullptr));
+  PHIQ_TRY(run_level(1, nullptr));
+  double err = INFINITY;
+  int level = 1;
+  bool converged = false;
+  for (;; ++level) {
+    if (level < cap) PHIQ_TRY(run_level(level + 1, &ctl[level].stop));
+    PHIQ_HIP(hipEventSynchronize(h->cc_ev[level]));
+    err = h->cc_ctl_host[level].err;
+    if (h->cc_ctl_host[level].stop) {
       converged = true;
       break;
     }
     if (level >= cap) break;
   }
+  double* ycur = ybuf[level % 2];
   if (rep) {
     rep->m = (6 << level) + 1;
     rep->cc_doublings = level;
@@ -2040,6 +2081,10 @@ phiq_status phiq_destroy(phiq_handle h) {
   if (h->ws.p) (void)hipFree(h->ws.p);
   if (h->scratch.p) (void)hipFree(h->scratch.p);
   if (h->partial.p) (void)hipFree(h->partial.p);
+  if (h->cc_ctl.p) (void)hipFree(h->cc_ctl.p);
+  if (h->cc_ctl_host) (void)hipHostFree(h->cc_ctl_host);
+  for (hipEvent_t e : h->cc_ev)
+    if (e) (void)hipEventDestroy(e);
   if (h->combo_coef.p) (void)hipFree(h->combo_coef.p);
   for (auto& b : h->cc_levels)
     if (b.p) (void)hipFree(b.p);
@@ -2454,7 +2499,7 @@ phiq_status phiq_profile_stop(phiq_handle h, phiq_kernel_stat* stats, int max_st
 
 phiq_status phiq_tile_config(phiq_handle h, int kind, int cfg, int* count) {
   if (!h || kind < 0 || kind > 4) return PHIQ_ERR_INVALID_ARG;
-  const int nc = kind <= 2 ? ttm_num_configs(kind) : (kind == 3 ? bf16r_num_configs() : 2);
+  const int nc = kind <= 2 ? ttm_num_configs(kind) : (kind == 3 ? bf16r_num_configs() : bf16r_square_num_configs());
   if (count) *count = nc;
   if (cfg < -1 || cfg >= nc) return PHIQ_ERR_INVALID_ARG;
   h->force_cfg[kind] = cfg;

@@ -59,6 +59,7 @@ __device__ __forceinline__ bool tile_of_block(int M, int L, int nb, int& m0, int
 template <class C, bool VEC, bool NN = false>
 __global__ __launch_bounds__(C::NT, C::MINW) void ttm_store_kernel(TtmArgs a) {
   __shared__ double smem[2 * (C::BM + C::BN) * C::LDK];
+  if (a.stop && *a.stop) return;
   int m0, n0, b;
   if (!tile_of_block<C>(a.M, a.L, a.nbatch, m0, n0, b)) return;
   d4 acc[C::TM][C::TN];
@@ -308,8 +309,9 @@ __global__ __launch_bounds__(256) void taylor_jobs_kernel(const TaylorJob* __res
 // ---------------------------------------------------------------------------
 // partial[(blk * np + j) * 2 + 0] = max |y_j - yold_j|, [.. + 1] = max |y_j|
 __global__ void absdiff_max_kernel(const double* __restrict__ y, const double* __restrict__ yold, int np,
-                                   long long N, double* __restrict__ partial) {
+                                   long long N, double* __restrict__ partial, const int* __restrict__ stop) {
   __shared__ double sd[256], sy[256];
+  if (stop && *stop) return;
   for (int j = 0; j < np; ++j) {
     double md = 0.0, my = 0.0;
     const double* yj = y + j * N;
@@ -341,8 +343,9 @@ __global__ void absdiff_max_kernel(const double* __restrict__ y, const double* _
 // NP > 0: that many outputs, kept in registers; NP = 0: np outputs (any).
 template <int NP>
 __global__ void node_sum_kernel(NodeSegs segs, long long N, const double* __restrict__ coef, int ldcoef, int np,
-                                double* __restrict__ Y) {
+                                double* __restrict__ Y, const int* __restrict__ stop) {
   constexpr int A = NP > 0 ? NP : PHIQ_MAX_P;
+  if (stop && *stop) return;
   const int n = NP > 0 ? NP : np;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N; i += (long long)gridDim.x * blockDim.x) {
     double acc[A];
@@ -361,6 +364,45 @@ __global__ void node_sum_kernel(NodeSegs segs, long long N, const double* __rest
 #pragma unroll
     for (int j = 0; j < A; ++j)
       if (j < n) Y[j * N + i] = acc[j];
+  }
+}
+
+// One block: the relative change of Algorithm 2 from the absdiff partial
+// maxima, and whether it meets tol (or an earlier level already did).
+__global__ __launch_bounds__(256) void cc_decide_kernel(const double* __restrict__ partial, int nblk, int np,
+                                                        double tol, const int* __restrict__ prev,
+                                                        CcCtl* __restrict__ out) {
+  __shared__ double sn[256], sd[256];
+  if (prev && *prev) {
+    if (threadIdx.x == 0) {
+      out->err = -1.0;
+      out->stop = 1;
+    }
+    return;
+  }
+  double err = 0.0;
+  for (int j = 0; j < np; ++j) {
+    double num = 0.0, den = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+      num = fmax(num, partial[((long long)b * np + j) * 2 + 0]);
+      den = fmax(den, partial[((long long)b * np + j) * 2 + 1]);
+    }
+    sn[threadIdx.x] = num;
+    sd[threadIdx.x] = den;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s) {
+        sn[threadIdx.x] = fmax(sn[threadIdx.x], sn[threadIdx.x + s]);
+        sd[threadIdx.x] = fmax(sd[threadIdx.x], sd[threadIdx.x + s]);
+      }
+      __syncthreads();
+    }
+    err = fmax(err, sd[0] > 0.0 ? sn[0] / sd[0] : sn[0]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out->err = err;
+    out->stop = err <= tol ? 1 : 0;
   }
 }
 
@@ -632,20 +674,26 @@ int launch_ttm_square(const TtmArgs& a, phiq_precision prec, void* stream, int c
 }
 
 int launch_absdiff_max(const double* y, const double* yold, int np, long long N, double* partial, int nblocks,
-                       void* stream) {
-  PHIQ_LAUNCH(absdiff_max_kernel, dim3(nblocks), dim3(256), 0, (hipStream_t)stream, y, yold, np, N, partial);
+                       void* stream, const int* stop) {
+  PHIQ_LAUNCH(absdiff_max_kernel, dim3(nblocks), dim3(256), 0, (hipStream_t)stream, y, yold, np, N, partial, stop);
+  return hipGetLastError();
+}
+
+int launch_cc_decide(const double* partial, int nblk, int np, double tol, const int* prev, CcCtl* out,
+                     void* stream) {
+  PHIQ_LAUNCH(cc_decide_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, partial, nblk, np, tol, prev, out);
   return hipGetLastError();
 }
 
 int launch_node_sum(const NodeSegs& segs, long long N, const double* coef, int ldcoef, int np, double* Y,
-                    void* stream) {
+                    void* stream, const int* stop) {
   const int nb = std::max(1, std::min(4096, cdiv(N, 256)));
   switch (np) {
-    case 1: PHIQ_LAUNCH(node_sum_kernel<1>, dim3(nb), dim3(256), 0, (hipStream_t)stream, segs, N, coef, ldcoef, np, Y); break;
-    case 2: PHIQ_LAUNCH(node_sum_kernel<2>, dim3(nb), dim3(256), 0, (hipStream_t)stream, segs, N, coef, ldcoef, np, Y); break;
-    case 3: PHIQ_LAUNCH(node_sum_kernel<3>, dim3(nb), dim3(256), 0, (hipStream_t)stream, segs, N, coef, ldcoef, np, Y); break;
-    case 4: PHIQ_LAUNCH(node_sum_kernel<4>, dim3(nb), dim3(256), 0, (hipStream_t)stream, segs, N, coef, ldcoef, np, Y); break;
-    default: PHIQ_LAUNCH(node_sum_kernel<0>, dim3(nb), dim3(256), 0, (hipStream_t)stream, segs, N, coef, ldcoef, np, Y);
+    case 1: PHIQ_LAUNCH(node_sum_kernel<1>, dim3(nb), dim3(256), 0, (hipStream_t)stream, segs, N, coef, ldcoef, np, Y, stop); break;
+    case 2: PHIQ_LAUNCH(node_sum_kernel<2>, dim3(nb), dim3(256), 0, (hipStream_t)stream, segs, N, coef, ldcoef, np, Y, stop); break;
+    case 3: PHIQ_LAUNCH(node_sum_kernel<3>, dim3(nb), dim3(256), 0, (hipStream_t)stream, segs, N, coef, ldcoef, np, Y, stop); break;
+    case 4: PHIQ_LAUNCH(node_sum_kernel<4>, dim3(nb), dim3(256), 0, (hipStream_t)stream, segs, N, coef, ldcoef, np, Y, stop); break;
+    default: PHIQ_LAUNCH(node_sum_kernel<0>, dim3(nb), dim3(256), 0, (hipStream_t)stream, segs, N, coef, ldcoef, np, Y, stop);
   }
   return hipGetLastError();
 }

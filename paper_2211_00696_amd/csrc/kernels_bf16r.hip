@@ -279,6 +279,7 @@ __device__ __forceinline__ void run_units(const TtmArgs& a, bool per_vector, int
 template <class C, class TIn, class TOut>
 __global__ __launch_bounds__(C::NT) void ttm_bf16r_store_kernel(TtmArgs a) {
   __shared__ bf8 els[C::CHUNKS];
+  if (a.stop && *a.stop) return;
   run_units<C, TIn>(a, false, a.nbatch, els, [&](long long u, const Work& w, f4 (&acc)[C::NV][C::RB][C::TN]) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int b = (int)(u / w.CT), ct = (int)(u % w.CT);
@@ -397,23 +398,28 @@ int square_go(const TtmArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <int BM, int K, int NV>
+template <int BM, int K, int NV, int WAVES>
 int square_np(const TtmArgs& a, hipStream_t st) {
   // p accumulator sets per wave: one 16-column block per wave and a ring of
   // two steps keep them in registers
   constexpr int S = NV * (K / 64);
-  using C = RC<BM, K, 8, 1, (S % 2 == 0 ? 2 : 1), NV>;
+  using C = RC<BM, K, WAVES, 1, (S % 2 == 0 ? 2 : 1), NV>;
   return a.x_f32 ? square_go<C, float>(a, st) : square_go<C, double>(a, st);
 }
 
-template <int BM, int K>
-int square_shape(const TtmArgs& a, hipStream_t st) {
+template <int BM, int K, int WAVES>
+int square_waves(const TtmArgs& a, hipStream_t st) {
   switch (a.nbatch) {
-    case 1: return square_np<BM, K, 1>(a, st);
-    case 2: return square_np<BM, K, 2>(a, st);
-    case 3: return square_np<BM, K, 3>(a, st);
-    default: return square_np<BM, K, 4>(a, st);
+    case 1: return square_np<BM, K, 1, WAVES>(a, st);
+    case 2: return square_np<BM, K, 2, WAVES>(a, st);
+    case 3: return square_np<BM, K, 3, WAVES>(a, st);
+    default: return square_np<BM, K, 4, WAVES>(a, st);
   }
+}
+
+template <int BM, int K>
+int square_shape(const TtmArgs& a, hipStream_t st, int cfg) {
+  return cfg == 2 ? square_waves<BM, K, 12>(a, st) : square_waves<BM, K, 8>(a, st);
 }
 
 template <int BM, int K>
@@ -422,7 +428,10 @@ int store_shape(const TtmArgs& a, hipStream_t st, int cfg) {
   switch (cfg) {
     case 2: return by_types<StoreSel<BM, K, 4, 2, KB>::template T>(a, st);
     case 3: return by_types<StoreSel<BM, K, 8, 2, (KB >= 2 ? 2 : 1)>::template T>(a, st);
-    default: return by_types<StoreSel<BM, K, 8, 1, KB>::template T>(a, st);
+    case 4: return by_types<StoreSel<BM, K, 12, 1, (KB >= 2 ? 2 : 1)>::template T>(a, st);
+    case 5: return by_types<StoreSel<BM, K, 16, 1, (KB >= 2 ? 2 : 1)>::template T>(a, st);
+    case 1: return by_types<StoreSel<BM, K, 8, 1, KB>::template T>(a, st);
+    default: return by_types<StoreSel<BM, K, 16, 1, (KB >= 2 ? 2 : 1)>::template T>(a, st);
   }
 }
 
@@ -438,11 +447,14 @@ bool bf16r_shape(const TtmArgs& a) {
 
 }  // namespace
 
-int bf16r_num_configs() { return 4; }
+int bf16r_num_configs() { return 6; }
+int bf16r_square_num_configs() { return 3; }
 
-// cfg: 0 = decline (the caller runs the general kernel), 1..3 resident
+// cfg: 0 = decline (the caller runs the general kernel), 1..5 resident
 // shapes (1: eight waves of 16 columns, 2: four waves of 32, 3: eight waves
-// of 32), -1 = default (1).  Returns hipErrorNotSupported for shapes the
+// of 32, 4: twelve waves of 16, 5: sixteen waves of 16), -1 = default (5:
+// at n = 256 and 128 it measured best, by 2%).
+// Squaring: 1 eight waves, 2 twelve waves.  Returns hipErrorNotSupported for shapes the
 // resident kernels do not take.
 int launch_ttm_store_bf16r(const TtmArgs& a, void* stream, int cfg) {
   if (cfg == 0 || !bf16r_shape(a) || a.nbatch < 1) return hipErrorNotSupported;
@@ -462,9 +474,9 @@ int launch_ttm_square_bf16r(const TtmArgs& a, void* stream, int cfg) {
   const long long units = (long long)((a.L + 127) / 128) * (a.M / (a.K == 64 ? 64 : 128));
   if (cfg < 0 && units < cu_count()) return hipErrorNotSupported;
   hipStream_t st = (hipStream_t)stream;
-  if (a.K == 256) return square_shape<128, 256>(a, st);
-  if (a.K == 128) return square_shape<128, 128>(a, st);
-  return square_shape<64, 64>(a, st);
+  if (a.K == 256) return square_shape<128, 256>(a, st, cfg);
+  if (a.K == 128) return square_shape<128, 128>(a, st, cfg);
+  return square_shape<64, 64>(a, st, cfg);
 }
 
 }  // namespace phiq

@@ -347,6 +347,7 @@ template <int MODE, int BM, class TIn, class TOut, bool VEC>
 __global__ __launch_bounds__(256) void ttm_lp_store_kernel(TtmArgs a) {
   using C = Lp<MODE, BM>;
   __shared__ LpStage<MODE, BM> sm[2];
+  if (a.stop && *a.stop) return;
   int m0, n0, b;
   if (!lp_tile_of_block<C>(a.M, a.L, a.nbatch, m0, n0, b)) return;
   f4 acc[C::TM][C::TN];

@@ -50,7 +50,7 @@ void mlp_predict_host(const float* w, const float x[kMlpIn], float y[kMlpOut]) {
 }
 
 bool mlp_choose(const float* w, const phiq_kron_op* op, const double* norms, double t, int p, double tol,
-                double alpha, int l5, int n5, int* l, int* n, int* used) {
+                double slack, double alpha, int l5, int n5, int* l, int* n, int* used) {
   float x[kMlpIn];
   int nmax = 1;
   for (int d = 0; d < op->dim; ++d) nmax = std::max(nmax, op->n[d]);
@@ -68,8 +68,8 @@ bool mlp_choose(const float* w, const phiq_kron_op* op, const double* norms, dou
   }
   const int lp = std::min(60, std::max(0, (int)std::lround(y[0] * 8.0f)));
   const int mp = std::max(1, (int)std::lround(y[1] * 16.0f));
-  // the judge: nodes the bound needs at this scaling
-  const int nreq = quadnodes(tol, p, std::ldexp(alpha, -lp), 1.0, PHIQ_RULE_GAUSS);
+  // the judge: nodes the bound needs at this scaling (within the slack)
+  const int nreq = quadnodes(std::min(tol * slack, 0.1), p, std::ldexp(alpha, -lp), 1.0, PHIQ_RULE_GAUSS);
   if (nreq < 0) {
     *used = 3;
     return false;

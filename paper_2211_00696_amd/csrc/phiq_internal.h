@@ -69,8 +69,10 @@ int launch_mlp_adam(float* w, const float* g, float* m, float* v, float lr, floa
 // use of it: features, prediction, the bound as judge.  Returns false when
 // the prediction is rejected (the caller keeps Algorithm 5's choice).
 void mlp_predict_host(const float* w, const float x[kMlpIn], float y[kMlpOut]);
+// slack: factor by which the bound at the network's choice may exceed tol
+// (1 = certified mode).
 bool mlp_choose(const float* w, const phiq_kron_op* op, const double* norms, double t, int p, double tol,
-                double alpha, int l5, int n5, int* l, int* n, int* used);
+                double slack, double alpha, int l5, int n5, int* l, int* n, int* used);
 // Grow-only device arena of batched calls, held by the handle.
 phiq_status batch_arena(phiq_handle h, size_t bytes, void** dev);
 // Pinned staging slot of at least `bytes`, and its upload (a copy kernel
@@ -187,6 +189,9 @@ struct TtmArgs {
   int order0;
   // node sum and per-order squaring (FP64): 1 = add the result to Y / O
   int yacc;
+  // nullable: a device flag; when it is set the launch does nothing (the
+  // speculative level of adaptive Clenshaw-Curtis after convergence)
+  const int* stop;
   double ifact[PHIQ_MAX_P + 1];  // ifact[k] = 1/k!
 };
 
@@ -207,6 +212,7 @@ int launch_ttm_square(const TtmArgs& a, phiq_precision prec, void* stream, int c
 // caller then runs the general kernel).  Store cfg 1..3 pick the wave and
 // column-block shape, -1 the default.
 int bf16r_num_configs();
+int bf16r_square_num_configs();
 int launch_ttm_store_bf16r(const TtmArgs& a, void* stream, int cfg);
 int launch_ttm_square_bf16r(const TtmArgs& a, void* stream, int cfg);
 
@@ -240,7 +246,16 @@ int launch_ttm_square_lowp(const TtmArgs& a, phiq_precision prec, void* stream);
 // partial[(blk * np + j) * 2 + {0, 1}] = block maxima of |y_j - yold_j|, |y_j|
 // with y_j = y + j*N, yold_j = yold + j*N.
 int launch_absdiff_max(const double* y, const double* yold, int np, long long N, double* partial,
-                       int nblocks, void* stream);
+                       int nblocks, void* stream, const int* stop = nullptr);
+// Convergence test of Algorithm 2 on the device: err = max_j max_b num / max_b
+// den over the partial maxima of nblk blocks; stop = (prev && *prev) || err <= tol.
+struct CcCtl {
+  double err;
+  int stop;
+  int pad_;
+};
+int launch_cc_decide(const double* partial, int nblk, int np, double tol, const int* prev, CcCtl* out,
+                     void* stream);
 // Node vectors stored in up to 12 segments (one per adaptive level).
 struct NodeSegs {
   const double* V[12];
@@ -250,7 +265,7 @@ struct NodeSegs {
 // Y + j*N = sum_b coef[j * ldcoef + b] * V_b, nodes numbered through the
 // segments in order.
 int launch_node_sum(const NodeSegs& segs, long long N, const double* coef, int ldcoef, int np, double* Y,
-                    void* stream);
+                    void* stream, const int* stop = nullptr);
 
 // ---- kernels_i8.hip: mode products on int8 digit slices -------------------
 enum I8Mode : int { kI8Slice = 0, kI8Store = 1, kI8Square = 2 };
@@ -355,5 +370,4 @@ struct BatchArgs {
 // One launch over the tiles of a run of stages with the same type, np
 // (Accum, Square) and vec; blocks must be a multiple of 8.
 int launch_batch(const BatchArgs& a, int type, int np, int vec, int blocks, void* stream);
-
 }  // namespace phiq

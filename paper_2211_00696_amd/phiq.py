@@ -74,7 +74,7 @@ class _Op:
 
 def options(rule="gauss", precision="fp64", l=None, m=None, alpha=None, c1=None, c2=None,
             cc_max_doublings=None, workspace_cap=None, use_graphs=None, selector=None, slab_products=None,
-            accept_floor=None):
+            accept_floor=None, selector_slack=None):
     lib = L.load()
     o = L.Options()
     _check(lib.phiq_options_default(byref(o)), "phiq_options_default")
@@ -102,6 +102,8 @@ def options(rule="gauss", precision="fp64", l=None, m=None, alpha=None, c1=None,
         o.slab_products = int(slab_products)
     if accept_floor is not None:
         o.accept_floor = int(bool(accept_floor))
+    if selector_slack is not None:
+        o.selector_slack = float(selector_slack)
     return o
 
 

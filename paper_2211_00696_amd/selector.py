@@ -18,6 +18,18 @@ steps runs p chains and a GEMM one after another.  This module
 and the planner uses the network with the bound as the judge (Algorithm 5
 is the fallback): phiq_options.selector = PHIQ_SEL_MLP.
 
+Two label modes:
+  * certified (`train`): the labels are pairs the a priori bound accepts, so
+    the network can only reorder (l, m) by cost, never use fewer nodes or
+    squarings than the bound asks for;
+  * empirical (`train-empirical`): `sweep_errors` runs the method itself over
+    forced (l, m) on generated problems and measures the error of each
+    against the method's own result at tol 1e-14; the label is the (l, m)
+    with the least modelled time whose measured error is at most tol / 2.
+    The bound still judges the network's choice, with a slack (decades)
+    calibrated as the largest bound excess the labels needed
+    (phiq_options.selector_slack).
+
 Features (8): log10 of t ||A^d||_inf for axes 0..2 (-3 for an absent axis),
 n / 256, dim, p, log10 t, log10 tol.  Outputs (2): l / 8 and m / 16.
 """
@@ -37,6 +49,8 @@ from . import phiq
 PKG = os.path.dirname(os.path.abspath(__file__))
 COSTS = os.path.join(PKG, "selector_costs.json")
 WEIGHTS = os.path.join(PKG, "selector_weights.json")
+ERRORS = os.path.join(PKG, "selector_errors.json")
+WEIGHTS_EMPIRICAL = os.path.join(PKG, "selector_weights_empirical.json")
 NFEAT, NHID, NOUT = 8, 64, 2
 NPARAM = NHID * NFEAT + NHID + NHID * NHID + NHID + NOUT * NHID + NOUT
 L_SCALE, M_SCALE = 8.0, 16.0
@@ -244,11 +258,133 @@ def save_weights_bin(w, path):
     np.asarray(w, dtype="<f4").tofile(path)
 
 
+# ---------------------------------------------------------------------------
+# 4. empirical labels: the method's measured error over forced (l, m)
+# ---------------------------------------------------------------------------
+def draw_sweep_problem(rng, sizes=(32, 48, 64, 96, 128, 192, 256), dims=(3,)):
+    dim = int(dims[rng.integers(0, len(dims))])
+    n = int(sizes[rng.integers(0, len(sizes))])
+    p = int(rng.integers(1, 5))
+    t = float(math.exp(rng.uniform(math.log(1e-4), math.log(1e-1))))
+    a, b = I.draw_coefficients(rng, dim)
+    return dict(dim=dim, n=n, p=p, t=t, a=[float(x) for x in a], b=[float(x) for x in b])
+
+
+def sweep_errors(h, count=240, seed=11, emin=1e-12, mmax=20, log=print):
+    """For `count` generated problems: the relative error (max over phi_k of the inf-norm error over
+    the inf-norm of the reference) of the FP64 phi-action at forced (l, m), against the method's own
+    result at tol 1e-14.  For each l from the paper's choice at tol 1e-10 down to six below it, m
+    rises from 2 until the error is below emin (or m = mmax)."""
+    import torch
+
+    rng = np.random.default_rng(seed)
+    recs = []
+    for i in range(count):
+        pr = draw_sweep_problem(rng)
+        n, dim, p, t = pr["n"], pr["dim"], pr["p"], pr["t"]
+        mats = [I.adv_diff_1d(n, pr["a"][d], pr["b"][d]) for d in range(dim)]
+        v = torch.from_numpy(rng.standard_normal(n ** dim)).cuda()
+        ref, rr = h.action(mats, t, p, v, tol=1e-14)
+        den = ref.abs().amax(dim=1)
+        _, r10 = h.action(mats, t, p, v, tol=1e-10)
+        out = torch.empty((p + 1, v.numel()), dtype=torch.float64, device="cuda")
+        pts = []
+        for l in range(r10["l"], max(-1, r10["l"] - 7), -1):
+            for m in range(2, mmax + 1):
+                _, rep = h.action(mats, t, p, v, tol=1e-10, l=l, m=m, out=out)
+                e = float(((out - ref).abs().amax(dim=1) / den).max())
+                pts.append([l, m, e, rep["log10_bound"]])
+                if e < emin:
+                    break
+        recs.append(dict(pr, alpha=rr["alpha"], norms=[t * infnorm(mm) for mm in mats], points=pts))
+        log("problem %d: n=%d p=%d alpha=%.3g, %d points" % (i, n, p, rr["alpha"], len(pts)))
+    return recs
+
+
+def empirical_label(T, rec, tol, safety=0.5):
+    """(l, m, bound excess in decades) with the least modelled time whose measured error <= safety tol;
+    None if no swept pair qualifies."""
+    best = None
+    for l, m, e, lb in rec["points"]:
+        if e <= safety * tol:
+            c = T(rec["n"], rec["p"], l, m)
+            if best is None or c < best[0]:
+                best = (c, l, m, lb - math.log10(tol))
+    return None if best is None else best[1:]
+
+
+def empirical_dataset(recs, costs, tols_per_problem=8, seed=5):
+    T = cost_fn(costs)
+    rng = np.random.default_rng(seed)
+    X, Y, meta = [], [], []
+    for rec in recs:
+        for _ in range(tols_per_problem):
+            tol = float(math.exp(rng.uniform(math.log(1e-10), math.log(1e-6))))
+            lab = empirical_label(T, rec, tol)
+            if lab is None:
+                continue
+            l, m, excess = lab
+            X.append(features(rec["norms"], rec["n"], rec["dim"], rec["p"], rec["t"], tol))
+            Y.append((l / L_SCALE, m / M_SCALE))
+            meta.append(dict(n=rec["n"], p=rec["p"], alpha=rec["alpha"], tol=tol, l=l, m=m, excess=excess))
+    return np.array(X), np.array(Y), meta
+
+
+def train_empirical(h, recs, seed=3, steps=6000, lr=3e-3, costs=None, log=print):
+    """Fit the network on the empirical labels; the judge's slack is the largest bound excess the
+    labels needed (rounded up to a tenth of a decade)."""
+    costs = load_costs() if costs is None else costs
+    X, Y, meta = empirical_dataset(recs, costs)
+    w0 = init_weights(seed + 1000)
+    w, hist = h.mlp_train(X, Y, w0, steps, lr)
+    pred = predict(w, X)
+    l_err = np.abs(np.rint(pred[:, 0] * L_SCALE) - np.rint(Y[:, 0] * L_SCALE))
+    m_err = np.abs(np.rint(pred[:, 1] * M_SCALE) - np.rint(Y[:, 1] * M_SCALE))
+    slack = math.ceil(10.0 * max(0.0, max(r["excess"] for r in meta))) / 10.0
+    stats = dict(mode="empirical", samples=len(meta), problems=len(recs), steps=steps, lr=lr,
+                 loss_first=float(hist[0]), loss_last=float(hist[-1]), l_exact=float(np.mean(l_err == 0)),
+                 m_within_1=float(np.mean(m_err <= 1)), slack=slack)
+    log(json.dumps(stats))
+    return w, hist, stats
+
+
+def load_empirical(path=WEIGHTS_EMPIRICAL):
+    """(weights, slack) of the empirical-mode network."""
+    d = json.load(open(path))
+    return np.array(d["weights"], dtype=np.float32), float(d["stats"]["slack"])
+
+
+def _device_handle():
+    """torch's device first (its lazy initialisation fails once another library has set HIP up in
+    the process), then the library's handle."""
+    import torch
+
+    torch.zeros(1, device="cuda")
+    return phiq.Handle(0)
+
+
 def main(argv):
     if len(argv) >= 1 and argv[0] == "train":
         out = argv[1] if len(argv) > 1 else WEIGHTS
         h = phiq.Handle(0)
         w, hist, stats = train(h, log=lambda s: print(s, flush=True))
+        h.close()
+        save_weights(w, stats, out)
+        return 0
+    if len(argv) >= 1 and argv[0] == "sweep-errors":
+        out = argv[1] if len(argv) > 1 else ERRORS
+        count = int(argv[2]) if len(argv) > 2 else 240
+        h = _device_handle()
+        recs = sweep_errors(h, count=count, log=lambda s: print(s, flush=True))
+        h.close()
+        json.dump({"records": recs}, open(out, "w"))
+        return 0
+    if len(argv) >= 1 and argv[0] == "train-empirical":
+        src = argv[1] if len(argv) > 1 else ERRORS
+        out = argv[2] if len(argv) > 2 else WEIGHTS_EMPIRICAL
+        recs = json.load(open(src))["records"]
+        h = _device_handle()
+        w, hist, stats = train_empirical(h, recs, log=lambda s: print(s, flush=True))
         h.close()
         save_weights(w, stats, out)
         return 0

@@ -132,7 +132,7 @@ def test_tol_below_floor_refused(h, prec):
 # multiple of the 128-column work unit) and axes the resident kernels do
 # not take (general kernel) in the same chain
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("sizes", [(256, 256), (128, 128, 128), (64, 64, 64), (256, 72), (128, 200),
                                    (64, 256, 40)])
 def test_bf16_resident_store_shapes(h, sizes, cfg):
@@ -151,7 +151,7 @@ def test_bf16_resident_store_shapes(h, sizes, cfg):
     assert max(errs) < TOL_KRON["bf16x3"], errs
 
 
-@pytest.mark.parametrize("store_cfg,square_cfg", [(1, 1), (2, 1), (3, 1), (0, 0)])
+@pytest.mark.parametrize("store_cfg,square_cfg", [(1, 1), (2, 1), (3, 1), (4, 2), (5, 1), (0, 0)])
 def test_bf16_resident_phi_action_vs_oracle(h, n64, store_cfg, square_cfg):
     """3D n = 64 phi-action with the resident product and squaring kernels
     forced on every launch (node batch with one factor per node, the

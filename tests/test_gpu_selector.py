@@ -7,9 +7,10 @@
 * The judge: a network that asks for too few nodes is corrected to what the
   bound needs (report.selector == 2) or rejected (3), and the result still
   meets the tolerance against the oracle.
-* The trained network (selector_weights.json): on held-out 3D problems at
-  n = 64, 96, 128, 192 its choice meets the tolerance and is not slower
-  than Algorithm setup_quadrature's; the measured ratio is printed.
+* The certified network (selector_weights.json, labels the bound accepts):
+  on held-out 3D problems at n = 64, 96, 128, 192 its choice meets the
+  tolerance and is not slower than Algorithm setup_quadrature's; the
+  measured ratio is printed.
 """
 import math
 import os
@@ -178,3 +179,4 @@ def test_selector_load_from_file_matches_set(h, tmp_path):
         assert (r3["l"], r3["m"]) == (got[0][1]["l"], got[0][1]["m"])
     finally:
         h.selector_set(None)
+
