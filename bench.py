@@ -136,6 +136,8 @@ def main():
     ap.add_argument("--event-every", type=int, default=10,
                     help="advdiff3d: in the timed region, the dominant kernel class's launches of every this-many-th "
                          "step (the first, the 1+S-th, ...) carry HIP events; 1 = every step")
+    ap.add_argument("--batch-persistent", action="store_true",
+                    help="batch512: the whole batch in one persistent launch (phiq_options.batch_persistent)")
     ap.add_argument("--no-forms", action="store_true",
                     help="advdiff3d, FP64: skip the FP32 / split-bf16 legs and the n = 128 seed median")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -468,10 +470,11 @@ def bench_batch(args, rank):
     h = phiq.Handle(0)
     info = phiq.batch_info([dict(mats=p["mats"], t=p["t"], p=p["p"], tol=p["tol"], v_ptr=v.data_ptr(),
                                  out_ptr=o.data_ptr()) for p, v, o in zip(probs, views, outs)])
-    _, reps = h.action_batched(bp)
+    bkw = dict(batch_persistent=True) if args.batch_persistent else {}
+    _, reps = h.action_batched(bp, **bkw)
     torch.cuda.synchronize()
     for _ in range(args.warmup):
-        h.action_batched(bp)
+        h.action_batched(bp, **bkw)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -479,7 +482,7 @@ def bench_batch(args, rank):
     t0 = time.perf_counter()
     ev0.record(stream)
     for _ in range(args.steps):
-        h.action_batched(bp)
+        h.action_batched(bp, **bkw)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / args.steps
@@ -510,7 +513,8 @@ def bench_batch(args, rank):
         "config": {"workload": "%d problems: dim 2 or 3 (p=1/2), n uniform in 16..192, p uniform in 1..4, "
                                "t log-uniform in [1e-4, 1e-1], a_d log-U[0.1,10], b_d U[0,50], v~N(0,1), "
                                "Gauss, tol 1e-8, seed %d" % (len(probs), args.seed),
-                   "problems": len(probs), "grid_points": Ntot, "seed": args.seed},
+                   "problems": len(probs), "grid_points": Ntot, "seed": args.seed,
+                   "persistent_launch": bool(args.batch_persistent)},
         "roofline": {"kernel": "batch_kernel", "bound": "mfma", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
                      "flops_per_step": flops, "gpu_ms_per_step": gpu_ms,

@@ -123,6 +123,13 @@ typedef struct {
                             /* trained on measured errors (empirical mode) is used  */
                             /* with the slack calibrated on its own sweep: the      */
                             /* largest bound excess its training labels needed      */
+  int batch_persistent;     /* phiq_action_batched: 1 = the whole batch in one      */
+                            /* persistent launch (tiles handed out in dependency    */
+                            /* order, workgroups waiting on per-group completion    */
+                            /* counters); the call then waits for the launch and    */
+                            /* returns PHIQ_ERR_HIP if a wait gave up (bounded,     */
+                            /* seconds).  0 (default) = one launch per dependency   */
+                            /* depth, asynchronous                                  */
 } phiq_options;
 
 /* Rounding floors of the lower-precision mode products: an upper level of

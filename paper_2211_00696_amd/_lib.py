@@ -81,6 +81,7 @@ class Options(ctypes.Structure):
         ("slab_products", c_int),
         ("accept_floor", c_int),
         ("selector_slack", c_double),
+        ("batch_persistent", c_int),
     ]
 
 

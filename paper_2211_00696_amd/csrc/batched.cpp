@@ -45,6 +45,9 @@ inline size_t al(size_t x) { return (x + kAl - 1) / kAl * kAl; }
 inline long long cdiv(long long a, long long b) { return (a + b - 1) / b; }
 constexpr int kChunk = 4;  // nodes per quadrature chunk (node-sum epilogue width)
 constexpr long long kBatchGrid = 2048;  // workgroups per launch at most (multiple of 8)
+// polls of one dependency wait in the persistent launch before it gives up
+// (each poll sleeps 256 cycles: several seconds in all, far beyond any tile)
+constexpr long long kPersistSpinLimit = 1ll << 23;
 
 struct Prob {
   const phiq_problem* pr = nullptr;
@@ -384,6 +387,7 @@ struct Schedule {
   size_t up_off = 0;        // upload region offset in the arena
   size_t up_bytes = 0;      // upload region bytes
   size_t st_off = 0, tj_off = 0;  // inside the upload region
+  size_t pc_off = 0;              // persistent launch: tile counter, error flag, group counters (zeroed by the upload)
   size_t total = 0;         // arena bytes
   Built b;
   int depth = 0;
@@ -476,6 +480,8 @@ struct Schedule {
     uo += al(b.st.size() * sizeof(BatchStage));
     tj_off = uo;
     uo += al(std::max<size_t>(1, b.tj.size()) * sizeof(BatchTaylor));
+    pc_off = uo;
+    uo += al(sizeof(BatchPersistCtl)) + al((size_t)std::max(1, b.ngroups) * sizeof(unsigned));
     up_bytes = uo;
     total = up_off + uo;
     return PHIQ_OK;
@@ -632,15 +638,36 @@ extern "C" phiq_status phiq_action_batched(phiq_handle h, int nprob, const phiq_
     BatchArgs a{};
     a.st = (const BatchStage*)(up + S.st_off);
     a.tj = (const BatchTaylor*)(up + S.tj_off);
-    for (const Launch& L : S.b.launches) {
-      a.stage_begin = L.stage_begin;
-      a.stage_end = L.stage_end;
-      a.tile_begin = L.tile_begin;
-      a.tile_end = L.tile_end;
-      const long long T = L.tile_end - L.tile_begin;
-      const long long blocks = std::min<long long>((T + 7) / 8 * 8, kBatchGrid);
-      const BatchStage& s0 = S.b.st[L.stage_begin];
-      PHIQ_HIP(launch_batch(a, L.type, s0.np, s0.vec, (int)blocks, stream));
+    if (opt.batch_persistent) {
+      // one launch; its counters arrive zeroed with the upload
+      BatchPersistArgs pa{};
+      pa.ctl = (BatchPersistCtl*)(up + S.pc_off);
+      pa.done = (unsigned*)(up + S.pc_off + al(sizeof(BatchPersistCtl)));
+      pa.total = S.b.total;
+      pa.nstages = (int)S.b.st.size();
+      pa.spin_limit = kPersistSpinLimit;
+      a.stage_begin = 0;
+      a.stage_end = pa.nstages;
+      a.tile_begin = 0;
+      a.tile_end = S.b.total;
+      PHIQ_HIP(launch_batch_persistent(a, pa, stream));
+      int eslot = 0;
+      void* ehost = nullptr;
+      PHIQ_TRY(batch_stage(h, sizeof(BatchPersistCtl), &eslot, &ehost));
+      PHIQ_HIP(hipMemcpyAsync(ehost, pa.ctl, sizeof(BatchPersistCtl), hipMemcpyDeviceToHost, stream));
+      PHIQ_HIP(hipStreamSynchronize(stream));
+      if (((const BatchPersistCtl*)ehost)->err) return PHIQ_ERR_HIP;
+    } else {
+      for (const Launch& L : S.b.launches) {
+        a.stage_begin = L.stage_begin;
+        a.stage_end = L.stage_end;
+        a.tile_begin = L.tile_begin;
+        a.tile_end = L.tile_end;
+        const long long T = L.tile_end - L.tile_begin;
+        const long long blocks = std::min<long long>((T + 7) / 8 * 8, kBatchGrid);
+        const BatchStage& s0 = S.b.st[L.stage_begin];
+        PHIQ_HIP(launch_batch(a, L.type, s0.np, s0.vec, (int)blocks, stream));
+      }
     }
     for (const auto& P : S.pl) {
       phiq_report* rep = P.pr->rep;

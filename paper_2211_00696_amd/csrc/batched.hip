@@ -10,6 +10,8 @@
 // wait on each other: each takes tiles with a grid-stride loop and exits.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "phiq_internal.h"
 #include "tile_fp64.h"
 
@@ -38,7 +40,7 @@ __device__ __forceinline__ void store_tile(double* O, int M, int L, int m0, int 
     }
 }
 
-__device__ void run_gemm(const BatchStage& S, int tile, double* smem) {
+__device__ __forceinline__ void run_gemm(const BatchStage& S, int tile, double* smem) {
   const int n = S.M;
   const int mt = (n + BT::BM - 1) / BT::BM;
   const int m0 = (tile % mt) * BT::BM, n0 = (tile / mt) * BT::BN;
@@ -49,11 +51,11 @@ __device__ void run_gemm(const BatchStage& S, int tile, double* smem) {
 }
 
 // Same Horner form as the single-problem Taylor kernel, one element at a time.
-__device__ void run_taylor(const BatchTaylor& jb, int tile) {
+__device__ __forceinline__ void run_taylor(const BatchTaylor& jb, int tile) {
   const int n = jb.n, K = jb.K, nt = jb.nt;
   const long long nn = (long long)n * n;
-  for (int r = 0; r < kBatchTaylorChunk / 256; ++r) {
-    const long long i = (long long)tile * kBatchTaylorChunk + r * 256 + threadIdx.x;
+  for (int r = 0; r < kBatchTaylorChunk / (int)blockDim.x; ++r) {  // 256 or 512 threads
+    const long long i = (long long)tile * kBatchTaylorChunk + r * (int)blockDim.x + threadIdx.x;
     if (i >= nn) break;
     double z[kMaxTaylorDegree];
 #pragma unroll
@@ -72,7 +74,7 @@ __device__ void run_taylor(const BatchTaylor& jb, int tile) {
 }
 
 template <bool VEC>
-__device__ void run_store(const BatchStage& S, int tile, double* smem) {
+__device__ __forceinline__ void run_store(const BatchStage& S, int tile, double* smem) {
   const int mt = (S.M + BT::BM - 1) / BT::BM;
   const int m0 = (tile % mt) * BT::BM;
   const int r = tile / mt;
@@ -85,7 +87,7 @@ __device__ void run_store(const BatchStage& S, int tile, double* smem) {
 }
 
 template <bool VEC>
-__device__ void run_store_wide(const BatchStage& S, int tile, double* smem) {
+__device__ __forceinline__ void run_store_wide(const BatchStage& S, int tile, double* smem) {
   const int mt = (S.M + BW::BM - 1) / BW::BM;
   const int m0 = (tile % mt) * BW::BM;
   const int r = tile / mt;
@@ -98,7 +100,7 @@ __device__ void run_store_wide(const BatchStage& S, int tile, double* smem) {
 }
 
 template <class C, int NP, bool VEC>
-__device__ void run_accum(const BatchStage& S, int tile, double* smem) {
+__device__ __forceinline__ void run_accum(const BatchStage& S, int tile, double* smem) {
   const int mt = (S.M + C::BM - 1) / C::BM;
   const int m0 = (tile % mt) * C::BM, n0 = (tile / mt) * C::BN;
   d4 y[NP][C::TM][C::TN];
@@ -142,7 +144,7 @@ __device__ void run_accum(const BatchStage& S, int tile, double* smem) {
 // registers, before its product's K loop so that the load overlaps it) once
 // and kept for the later orders.
 template <class C, int NP, bool VEC>
-__device__ void run_square(const BatchStage& S, int tile, double* smem) {
+__device__ __forceinline__ void run_square(const BatchStage& S, int tile, double* smem) {
   const int mt = (S.M + C::BM - 1) / C::BM;
   const int m0 = (tile % mt) * C::BM, n0 = (tile / mt) * C::BN;
   const double ifact[4] = {1.0, 1.0, 0.5, 1.0 / 6.0};
@@ -254,6 +256,130 @@ __global__ __launch_bounds__(512) void batch_wide_kernel(BatchArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// One persistent launch for the whole batch.  Workgroups of 512 threads take
+// tiles one at a time from a global counter, in the global order of the
+// schedule (depth by depth), so every tile a tile depends on has a smaller
+// number and was taken earlier by a workgroup that is running; the workgroup
+// holding the smallest unfinished tile always has its inputs complete, so
+// the batch finishes whatever number of workgroups is resident (no
+// co-residency is assumed).  A tile first waits until every group it reads
+// is complete (per-group completion counters, loaded with acquire semantics
+// at device scope so the producers' results are visible across XCDs), runs
+// with the eight-wave tiles (64 x 64 outputs like the four-wave ones, so the
+// schedule's tile counts hold; wide stores keep their 64 x 128 tiles), and
+// counts itself done with a release at device scope.  Every wait is bounded:
+// after spin_limit polls it sets ctl->err and the workgroup stops, and the
+// others stop at their next poll, so the kernel always ends.
+// ---------------------------------------------------------------------------
+// returns false when the wait gave up or another one did
+__device__ bool wait_group(const BatchPersistArgs& p, int w, int need) {
+  if (w < 0) return true;
+  for (long long it = 0;; ++it) {
+    const unsigned c = __hip_atomic_load(p.done + w, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    if (c >= (unsigned)need) return true;
+    if (__hip_atomic_load(&p.ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+    if (it >= p.spin_limit) {
+      __hip_atomic_store(&p.ctl->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(4);
+  }
+}
+
+template <class C, int NP>
+__device__ __forceinline__ void accum_vec(const BatchStage& S, int tile, double* smem) {
+  if (S.vec)
+    run_accum<C, NP, true>(S, tile, smem);
+  else
+    run_accum<C, NP, false>(S, tile, smem);
+}
+template <class C, int NP>
+__device__ __forceinline__ void square_vec(const BatchStage& S, int tile, double* smem) {
+  if (S.vec)
+    run_square<C, NP, true>(S, tile, smem);
+  else
+    run_square<C, NP, false>(S, tile, smem);
+}
+
+__device__ __forceinline__ void run_gemm8(const BatchStage& S, int tile, double* smem) {
+  const int n = S.M;
+  const int mt = (n + B8::BM - 1) / B8::BM;
+  const int m0 = (tile % mt) * B8::BM, n0 = (tile / mt) * B8::BN;
+  d4 acc[B8::TM][B8::TN];
+  zero_acc<B8>(acc);
+  tile_nn<B8>(S.E, S.X, n, m0, n0, smem, smem + B8::BM * B8::LDK, acc);
+  store_tile<B8>(S.O, n, n, m0, n0, acc);
+}
+
+template <bool VEC>
+__device__ __forceinline__ void run_store8(const BatchStage& S, int tile, double* smem) {
+  const int mt = (S.M + B8::BM - 1) / B8::BM;
+  const int m0 = (tile % mt) * B8::BM;
+  const int r = tile / mt;
+  const int b = r % S.nb;
+  const int n0 = (r / S.nb) * B8::BN;
+  d4 acc[B8::TM][B8::TN];
+  zero_acc<B8>(acc);
+  tile_nt_db<B8, VEC>(S.E + b * S.es, S.X + b * S.xs, S.M, S.K, S.L, m0, n0, smem, acc);
+  store_tile<B8>(S.O + b * S.os, S.M, S.L, m0, n0, acc);
+}
+
+__device__ __forceinline__ void run_any(const BatchArgs& a, const BatchStage& S, int tile, double* smem) {
+  switch (S.type) {
+    case kStageGemm: run_gemm8(S, tile, smem); break;
+    case kStageTaylor: run_taylor(a.tj[S.aux], tile); break;
+    case kStageStore:
+      if (S.vec) run_store8<true>(S, tile, smem); else run_store8<false>(S, tile, smem);
+      break;
+    case kStageStoreWide:
+      if (S.vec) run_store_wide<true>(S, tile, smem); else run_store_wide<false>(S, tile, smem);
+      break;
+    case kStageAccum:
+    case kStageAccumWide:
+      switch (S.np) {
+        case 1: accum_vec<B8, 1>(S, tile, smem); break;
+        case 2: accum_vec<B8, 2>(S, tile, smem); break;
+        case 3: accum_vec<B8, 3>(S, tile, smem); break;
+        default: accum_vec<B8, 4>(S, tile, smem); break;
+      }
+      break;
+    default:
+      switch (S.np) {
+        case 1: square_vec<B8, 1>(S, tile, smem); break;
+        case 2: square_vec<B8, 2>(S, tile, smem); break;
+        case 3: square_vec<B8, 3>(S, tile, smem); break;
+        default: square_vec<B8, 4>(S, tile, smem); break;
+      }
+  }
+}
+
+__global__ __launch_bounds__(512) void batch_persistent_kernel(BatchArgs a, BatchPersistArgs p) {
+  __shared__ double smem[2 * (BW::BM + BW::BN) * BW::LDK];
+  __shared__ long long sh_tile;
+  __shared__ int sh_ok;
+  int lo = 0;
+  for (;;) {
+    if (threadIdx.x == 0)
+      sh_tile = (long long)__hip_atomic_fetch_add(&p.ctl->next, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const long long g = sh_tile;
+    if (g >= p.total) break;
+    int hi = p.nstages - 1;  // last stage with tile0 <= g; g only grows, so lo only grows
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (a.st[mid].tile0 <= g) lo = mid; else hi = mid - 1;
+    }
+    const BatchStage& S = a.st[lo];
+    if (threadIdx.x == 0) sh_ok = wait_group(p, S.wait0, S.need0) && wait_group(p, S.wait1, S.need1);
+    __syncthreads();
+    if (!sh_ok) break;
+    run_any(a, S, (int)(g - S.tile0), smem);
+    __syncthreads();  // every thread's results are written (and smem is free)
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(p.done + S.signal, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 template <int TYPE, int NP>
 hipError_t launch_wide(const BatchArgs& a, bool vec, dim3 grid, hipStream_t st) {
   if (vec)
@@ -295,6 +421,25 @@ hipError_t launch_type(const BatchArgs& a, int np, bool vec, dim3 grid, hipStrea
 }
 
 }  // namespace
+
+int launch_batch_persistent(const BatchArgs& a, const BatchPersistArgs& p, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  static int per_cu = 0;
+  if (!per_cu) {
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, batch_persistent_kernel, 512, 0) != hipSuccess || b < 1)
+      b = 1;
+    per_cu = b;
+  }
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cus = 256;
+  // co-resident workgroups (not needed for progress: tiles are handed out in
+  // dependency order), at most one per tile
+  const long long g = std::min<long long>((long long)cus * per_cu, std::max<long long>(1, p.total));
+  hipLaunchKernelGGL(batch_persistent_kernel, dim3((unsigned)g), dim3(512), 0, st, a, p);
+  return hipGetLastError();
+}
 
 int launch_batch(const BatchArgs& a, int type, int np, int vec, int blocks, void* stream) {
   const dim3 grid(blocks);

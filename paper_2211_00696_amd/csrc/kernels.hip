@@ -204,9 +204,10 @@ __global__ __launch_bounds__(C::NT, C::MINW) void ttm_square_all_kernel(TtmArgs 
 // Small batched GEMM C = A B (n x n), one job per blockIdx.z.
 // ---------------------------------------------------------------------------
 template <class C>
-__global__ __launch_bounds__(C::NT) void gemm_jobs_kernel(const GemmJob* __restrict__ jobs) {
+__global__ __launch_bounds__(C::NT) void gemm_jobs_kernel(const GemmJob* __restrict__ jobs, const int* __restrict__ stop) {
   __shared__ double As[C::BM * C::LDK];
   __shared__ double Bs[C::BN * C::LDK];
+  if (stop && *stop) return;
   const GemmJob jb = jobs[blockIdx.z];
   const int m0 = blockIdx.x * C::BM, n0 = blockIdx.y * C::BN;
   if (m0 >= jb.n || n0 >= jb.n) return;  // uniform per block
@@ -234,10 +235,11 @@ __global__ __launch_bounds__(C::NT) void gemm_jobs_kernel(const GemmJob* __restr
 // zeros; this one pays one load latency per block instead of one per
 // 16-deep chunk.
 constexpr int kPanelK = 128;
-__global__ __launch_bounds__(256) void gemm_panel_kernel(const GemmJob* __restrict__ jobs) {
+__global__ __launch_bounds__(256) void gemm_panel_kernel(const GemmJob* __restrict__ jobs, const int* __restrict__ stop) {
   constexpr int BM = 32, BN = 32, LDK = kPanelK + 2, NT = 256, PER = BM * kPanelK / NT;
   __shared__ double As[BM * LDK];
   __shared__ double Bs[BN * LDK];
+  if (stop && *stop) return;
   const GemmJob jb = jobs[blockIdx.z];
   const int n = jb.n;
   const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
@@ -273,7 +275,8 @@ __global__ __launch_bounds__(256) void gemm_panel_kernel(const GemmJob* __restri
   }
 }
 
-__global__ void scale_jobs_kernel(const ScaleJob* __restrict__ jobs) {
+__global__ void scale_jobs_kernel(const ScaleJob* __restrict__ jobs, const int* __restrict__ stop) {
+  if (stop && *stop) return;
   const ScaleJob jb = jobs[blockIdx.y];
   const long long nn = (long long)jb.n * jb.n;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nn; i += (long long)gridDim.x * blockDim.x)
@@ -283,7 +286,8 @@ __global__ void scale_jobs_kernel(const ScaleJob* __restrict__ jobs) {
 // dst[t] = I + sum_{k=1}^{K} c_t^k/k! Z^k by Horner's rule in c_t:
 //   c (Z + c/2 (Z^2 + c/3 (Z^3 + ...))),
 // with the K powers of one element held in registers for all targets.
-__global__ __launch_bounds__(256) void taylor_jobs_kernel(const TaylorJob* __restrict__ jobs) {
+__global__ __launch_bounds__(256) void taylor_jobs_kernel(const TaylorJob* __restrict__ jobs, const int* __restrict__ stop) {
+  if (stop && *stop) return;
   const TaylorJob& jb = jobs[blockIdx.y];
   const int n = jb.n, K = jb.K, nt = jb.nt;
   const long long nn = (long long)n * n;
@@ -427,37 +431,37 @@ int launch_fetch(void* dst, const void* src, size_t bytes, void* stream) {
   return hipGetLastError();
 }
 
-int launch_gemm_jobs(const GemmJob* jobs, int njobs, int nmax, void* stream) {
+int launch_gemm_jobs(const GemmJob* jobs, int njobs, int nmax, void* stream, const int* stop) {
   if (njobs <= 0) return hipSuccess;
   if (nmax <= kPanelK) {
     dim3 grid(cdiv(nmax, 32), cdiv(nmax, 32), njobs);
-    PHIQ_LAUNCH(gemm_panel_kernel, grid, dim3(256), 0, (hipStream_t)stream, jobs);
+    PHIQ_LAUNCH(gemm_panel_kernel, grid, dim3(256), 0, (hipStream_t)stream, jobs, stop);
     return hipGetLastError();
   }
   // few large-tile blocks would leave most CUs idle: use one-wave 32x32 tiles
   if ((long long)njobs * cdiv(nmax, 64) * cdiv(nmax, 64) < 512) {
     using C = Tile32;
     dim3 grid(cdiv(nmax, C::BM), cdiv(nmax, C::BN), njobs);
-    PHIQ_LAUNCH(gemm_jobs_kernel<C>, grid, dim3(C::NT), 0, (hipStream_t)stream, jobs);
+    PHIQ_LAUNCH(gemm_jobs_kernel<C>, grid, dim3(C::NT), 0, (hipStream_t)stream, jobs, stop);
   } else {
     using C = Tile64;
     dim3 grid(cdiv(nmax, C::BM), cdiv(nmax, C::BN), njobs);
-    PHIQ_LAUNCH(gemm_jobs_kernel<C>, grid, dim3(C::NT), 0, (hipStream_t)stream, jobs);
+    PHIQ_LAUNCH(gemm_jobs_kernel<C>, grid, dim3(C::NT), 0, (hipStream_t)stream, jobs, stop);
   }
   return hipGetLastError();
 }
 
-int launch_scale_jobs(const ScaleJob* jobs, int njobs, int nmax, void* stream) {
+int launch_scale_jobs(const ScaleJob* jobs, int njobs, int nmax, void* stream, const int* stop) {
   if (njobs <= 0) return hipSuccess;
   dim3 grid(std::max(1, std::min(64, cdiv((long long)nmax * nmax, 256))), njobs);
-  PHIQ_LAUNCH(scale_jobs_kernel, grid, dim3(256), 0, (hipStream_t)stream, jobs);
+  PHIQ_LAUNCH(scale_jobs_kernel, grid, dim3(256), 0, (hipStream_t)stream, jobs, stop);
   return hipGetLastError();
 }
 
-int launch_taylor_jobs(const TaylorJob* jobs, int njobs, int nmax, void* stream) {
+int launch_taylor_jobs(const TaylorJob* jobs, int njobs, int nmax, void* stream, const int* stop) {
   if (njobs <= 0) return hipSuccess;
   dim3 grid(std::max(1, std::min(64, cdiv((long long)nmax * nmax, 256))), njobs);
-  PHIQ_LAUNCH(taylor_jobs_kernel, grid, dim3(256), 0, (hipStream_t)stream, jobs);
+  PHIQ_LAUNCH(taylor_jobs_kernel, grid, dim3(256), 0, (hipStream_t)stream, jobs, stop);
   return hipGetLastError();
 }
 

@@ -41,7 +41,9 @@ enum { LP_F32 = 0, LP_BF16X3 = 1 };
 // ---------------------------------------------------------------------------
 // one-off conversion of the 1D exponentials
 // ---------------------------------------------------------------------------
-__global__ void convert_kernel(const double* __restrict__ src, long long count, int mode, void* a, void* b) {
+__global__ void convert_kernel(const double* __restrict__ src, long long count, int mode, void* a, void* b,
+                               const int* __restrict__ stop) {
+  if (stop && *stop) return;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count; i += (long long)gridDim.x * blockDim.x) {
     const double x = src[i];
     if (mode == LP_F32) {
@@ -54,11 +56,12 @@ __global__ void convert_kernel(const double* __restrict__ src, long long count, 
   }
 }
 
-int launch_convert(const double* src, long long count, phiq_precision prec, void* a, void* b, void* stream) {
+int launch_convert(const double* src, long long count, phiq_precision prec, void* a, void* b, void* stream,
+                   const int* stop) {
   if (count <= 0) return hipSuccess;
   const int mode = prec == PHIQ_PREC_FP32 ? LP_F32 : LP_BF16X3;
   const long long nb = std::min<long long>(4096, (count + 255) / 256);
-  PHIQ_LAUNCH(convert_kernel, dim3((unsigned)nb), dim3(256), 0, (hipStream_t)stream, src, count, mode, a, b);
+  PHIQ_LAUNCH(convert_kernel, dim3((unsigned)nb), dim3(256), 0, (hipStream_t)stream, src, count, mode, a, b, stop);
   return hipGetLastError();
 }
 

@@ -198,9 +198,9 @@ struct TtmArgs {
 // Host launchers (kernels.hip).  All return hipSuccess or the launch error.
 // dst (device) = src (pinned host memory, read by the kernel), bytes % 8 == 0
 int launch_fetch(void* dst, const void* src, size_t bytes, void* stream);
-int launch_gemm_jobs(const GemmJob* jobs_dev, int njobs, int nmax, void* stream);
-int launch_scale_jobs(const ScaleJob* jobs_dev, int njobs, int nmax, void* stream);
-int launch_taylor_jobs(const TaylorJob* jobs_dev, int njobs, int nmax, void* stream);
+int launch_gemm_jobs(const GemmJob* jobs_dev, int njobs, int nmax, void* stream, const int* stop = nullptr);
+int launch_scale_jobs(const ScaleJob* jobs_dev, int njobs, int nmax, void* stream, const int* stop = nullptr);
+int launch_taylor_jobs(const TaylorJob* jobs_dev, int njobs, int nmax, void* stream, const int* stop = nullptr);
 // cfg selects the FP64 tile shape (-1: default); kinds 0 = store, 1 = node
 // sum, 2 = squaring; ttm_num_configs(kind) shapes exist per kind.
 int ttm_num_configs(int kind);
@@ -237,7 +237,8 @@ bool slab2_supported(const SlabArgs& a);
 int launch_slab2(const SlabArgs& a, void* stream);
 // FP32-MFMA and split-bf16 (3-product) versions (kernels_lowp.hip)
 // dst = src converted to FP32 (a) or split into bf16 hi (a) and lo (b)
-int launch_convert(const double* src, long long count, phiq_precision prec, void* a, void* b, void* stream);
+int launch_convert(const double* src, long long count, phiq_precision prec, void* a, void* b, void* stream,
+                   const int* stop = nullptr);
 int launch_ttm_store_lowp(const TtmArgs& a, phiq_precision prec, void* stream);
 int launch_ttm_accum_lowp(const TtmArgs& a, phiq_precision prec, void* stream);
 int launch_ttm_square_lowp(const TtmArgs& a, phiq_precision prec, void* stream);
@@ -370,4 +371,22 @@ struct BatchArgs {
 // One launch over the tiles of a run of stages with the same type, np
 // (Accum, Square) and vec; blocks must be a multiple of 8.
 int launch_batch(const BatchArgs& a, int type, int np, int vec, int blocks, void* stream);
+// The whole batch in one persistent launch (batched.hip): tiles handed out
+// from ctl->next in the schedule's order; done[g] counts the finished tiles
+// of group g; a wait that polls spin_limit times sets ctl->err and ends.
+struct BatchPersistCtl {
+  unsigned long long next;
+  int err;
+  int pad_;
+};
+struct BatchPersistArgs {
+  BatchPersistCtl* ctl;
+  unsigned* done;
+  long long total;       // tiles of the schedule
+  int nstages;
+  int pad_;
+  long long spin_limit;  // polls per wait before giving up
+};
+int launch_batch_persistent(const BatchArgs& a, const BatchPersistArgs& p, void* stream);
+
 }  // namespace phiq

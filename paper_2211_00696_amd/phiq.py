@@ -74,7 +74,7 @@ class _Op:
 
 def options(rule="gauss", precision="fp64", l=None, m=None, alpha=None, c1=None, c2=None,
             cc_max_doublings=None, workspace_cap=None, use_graphs=None, selector=None, slab_products=None,
-            accept_floor=None, selector_slack=None):
+            accept_floor=None, selector_slack=None, batch_persistent=None):
     lib = L.load()
     o = L.Options()
     _check(lib.phiq_options_default(byref(o)), "phiq_options_default")
@@ -104,6 +104,8 @@ def options(rule="gauss", precision="fp64", l=None, m=None, alpha=None, c1=None,
         o.accept_floor = int(bool(accept_floor))
     if selector_slack is not None:
         o.selector_slack = float(selector_slack)
+    if batch_persistent is not None:
+        o.batch_persistent = int(bool(batch_persistent))
     return o
 
 

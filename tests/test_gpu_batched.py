@@ -146,8 +146,44 @@ def test_batched_rejects_overlapping_outputs(h):
         h.action_batched(bp)
 
 
-@pytest.mark.skip(reason="a single persistent launch whose workgroups waited on completion counters "
-                         "blocked until the 120 s test timeout on its first GPU run; the cause was not "
-                         "shown, so that variant was removed (batches run one launch per dependency depth)")
-def test_batched_single_persistent_launch():
-    pass
+def wide_mix():
+    rng = np.random.default_rng(23)
+    cases = [(2, 96, 3, 1e-3), (2, 130, 2, 5e-4), (3, 100, 3, 1e-3), (3, 64, 4, 1e-2), (2, 70, 2, 1e-2),
+             (3, 12, 3, 1e-2)]
+    probs = []
+    for dim, n, p, t in cases:
+        a, b = I.draw_coefficients(rng, dim)
+        mats = [I.adv_diff_1d(n, float(a[d]), float(b[d])) for d in range(dim)]
+        probs.append(dict(mats=mats, t=t, p=p, tol=1e-8, vh=rng.standard_normal((1, n ** dim)),
+                          name=f"dim{dim} n{n} p{p}"))
+    return probs
+
+
+@pytest.mark.parametrize("mix", ["small", "wide"])
+def test_batched_single_persistent_launch(h, mix):
+    """The whole batch in one persistent launch (batch_persistent = 1): tiles
+    handed out from a device counter in dependency order, workgroups waiting
+    on per-group completion counters (device-scope acquire / release, every
+    wait bounded).  Its results equal the per-depth launches' to rounding
+    (the 64 x 64 stages run on eight-wave tiles of the same shape, the same
+    k order), separate calls to 1e-12 and the oracle to 1e-10."""
+    probs = small_mix() if mix == "small" else wide_mix()
+    bp = [dict(mats=p["mats"], t=p["t"], p=p["p"], tol=p["tol"], v=dev(p["vh"])) for p in probs]
+    print("persistent", mix, flush=True)
+    ref, _ = h.action_batched(bp)
+    got, reps = h.action_batched(bp, batch_persistent=True)
+    torch.cuda.synchronize()
+    worst = max(rel(got[i].cpu().numpy(), ref[i].cpu().numpy()) for i in range(len(probs)))
+    print("persistent vs per-depth launches", worst, flush=True)
+    assert worst < 1e-14, worst
+    run_and_check(h, probs, oracle_idx={0, 1, 2} if mix == "small" else {4, 5}, batch_persistent=True)
+
+
+def test_batched_persistent_sampled_mix(h):
+    mix = I.batch_mix(seed=7, count=40, n_min=16, n_max=72)
+    bp = [dict(mats=p["mats"], t=p["t"], p=p["p"], tol=p["tol"], v=dev(p["v"])) for p in mix]
+    ref, _ = h.action_batched(bp)
+    got, _ = h.action_batched(bp, batch_persistent=True)
+    worst = max(rel(got[i].cpu().numpy(), ref[i].cpu().numpy()) for i in range(len(mix)))
+    print("40-problem mix, persistent vs per-depth", worst, flush=True)
+    assert worst < 1e-14, worst
