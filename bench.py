@@ -48,14 +48,19 @@ def kernel_source_digest():
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel, digest):
+def traffic_key(kernel, precision):
+    """Entry name in profiles/traffic.json: the class, suffixed by the precision form unless FP64."""
+    return kernel if precision == "fp64" else "%s@%s" % (kernel, precision)
+
+
+def load_traffic(kernel, digest, precision="fp64"):
     """HBM bytes per launch from committed rocprofv3 counter runs, if current."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
     try:
         d = json.load(open(p))
-        ent = d.get(kernel)
+        ent = d.get(traffic_key(kernel, precision))
         if not ent or ent.get("kernel_digest") != digest:
             return None
         return float(ent["bytes_per_launch"])
@@ -262,7 +267,7 @@ def main():
     # its matrix roofline; its bound is the FP32 intermediates' HBM traffic
     bound = "hbm" if args.precision == "bf16x3" else "mfma"
     digest = kernel_source_digest()
-    traffic = load_traffic(dom, digest)
+    traffic = load_traffic(dom, digest, args.precision)
     ttm_total = {k: v for k, v in all_stats.items() if k.startswith("ttm")}
     ttm_ms = sum(s["ms"] for s in ttm_total.values())
     ttm_tflops = sum(s["flops"] for s in ttm_total.values()) / (ttm_ms * 1e-3) / 1e12
@@ -393,6 +398,7 @@ def time_form(h, pr, prec, v, out, steps, warmup, ms_fp64, **opts):
     else:
         roof = {"kernel": dom, "bound": "mfma", "achieved": tflops, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
                 "frac": tflops / PEAK_TFLOPS[prec], "gbs": gbs}
+    roof["traffic"] = load_traffic(dom, kernel_source_digest(), prec)
     roof.update({"avg_launch_ms": avg_ms, "launches": st["launches"], "fp64_equivalent_tflops": tflops,
                  "algorithmic_bytes_per_launch": st["bytes"] / st["launches"]})
     torch.cuda.synchronize()

@@ -22,12 +22,13 @@ timed region (to compare with the live HIP-event figure in BENCH.json).
 the same command, calibrates each counter with the plain device copy that
 `bench.py --copy-probe-mib COPY_MIB` launches (a negation of COPY_MIB MiB into
 another buffer: COPY_MIB MiB read, COPY_MIB MiB written), and prints the HBM
-bytes per launch of the dominant class as JSON for profiles/traffic.json.
+bytes per launch of the dominant class as JSON for profiles/traffic.json
+(keyed by the class, suffixed `@fp32` / `@bf16x3` for the reduced forms).
 
 `mfma` reads a `--pmc` counter CSV and prints, for the dominant class's
 timed-region launches, every counter's mean per launch; with
-SQ_INSTS_VALU_MFMA_MOPS_F64 the FP64 MFMA flops the hardware executed (MOPS x
-512) next to the algorithmic flops, with MfmaUtil rocprofv3's derived MFMA
+SQ_INSTS_VALU_MFMA_MOPS_F64 (or _F32, _BF16) the MFMA flops the hardware
+executed (MOPS x 512) next to the algorithmic flops, with MfmaUtil rocprofv3's derived MFMA
 utilisation, and with the LDS / wait counters the bank-conflict cycles per
 LDS instruction and the wait fractions of the wave cycles.
 
@@ -160,7 +161,9 @@ def traffic(fetch_csv, write_csv, bench_json, copy_mib):
                       "launches": len(sl)}
     total = res["fetch"]["bytes_per_launch"] + res["write"]["bytes_per_launch"]
     alg = bench["roofline"]["algorithmic_bytes_per_launch"]
-    print(json.dumps({dom: {"kernel_digest": bench["kernel_digest"], "bytes_per_launch": total,
+    prec = bench["config"].get("precision", "fp64")
+    key = dom if prec == "fp64" else "%s@%s" % (dom, prec)
+    print(json.dumps({key: {"kernel_digest": bench["kernel_digest"], "bytes_per_launch": total,
                             "algorithmic_bytes_per_launch": alg, "ratio_to_algorithmic": total / alg,
                             "fetch": res["fetch"], "write": res["write"],
                             "workload": bench["config"]["workload"]}}, indent=1))
@@ -180,10 +183,15 @@ def mfma(csv_path, bench_json):
     alg = bench["roofline"]["flops_per_launch"]
     out = {"launches": len(sl), "kernel_digest": bench["kernel_digest"], "workload": bench["config"]["workload"],
            "algorithmic_flops_per_launch": alg}
-    if any("SQ_INSTS_VALU_MFMA_MOPS_F64" in c for _, c in sl):
-        mops = sum(c.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0) for _, c in sl) / len(sl)
-        out["mfma_flops_executed_per_launch"] = mops * 512.0
-        out["executed_over_algorithmic"] = mops * 512.0 / alg
+    for ty in ("F64", "F32", "BF16"):
+        # each MOPS count stands for 512 floating-point operations of that type
+        cn = "SQ_INSTS_VALU_MFMA_MOPS_" + ty
+        if any(cn in c for _, c in sl):
+            mops = sum(c.get(cn, 0.0) for _, c in sl) / len(sl)
+            out["mfma_flops_executed_per_launch"] = mops * 512.0
+            out["mfma_type"] = ty
+            # split bf16 runs three bf16 products per FP64-equivalent product
+            out["executed_over_algorithmic"] = mops * 512.0 / alg
     if any("MfmaUtil" in c for _, c in sl):
         # rocprofv3's derived metric: MFMA busy cycles / (GPU active cycles x SIMDs), in percent
         out["mfma_util_percent_mean"] = sum(c["MfmaUtil"] for _, c in sl) / len(sl)
