@@ -130,7 +130,17 @@ typedef struct {
                             /* returns PHIQ_ERR_HIP if a wait gave up (bounded,     */
                             /* seconds).  0 (default) = one launch per dependency   */
                             /* depth, asynchronous                                  */
+  int rhs_per_launch;       /* phiq_plan_execute, Gauss rule, FP64, no slab         */
+                            /* products: right-hand sides that share each mode-     */
+                            /* product launch (node, vector) as one batch index.    */
+                            /* 0 (default) = as many as fit in PHIQ_RHS_GROUP_BYTES */
+                            /* of intermediates; 1 = one vector at a time; k = at   */
+                            /* most k.  The results are bitwise the same.           */
 } phiq_options;
+
+/* Device bytes of intermediates a group of right-hand sides may take when
+ * they share launches (rhs_per_launch = 0). */
+#define PHIQ_RHS_GROUP_BYTES ((size_t)8 << 30)
 
 /* Rounding floors of the lower-precision mode products: an upper level of
  * the relative error per phi_k (inf-norm, against the exact action) that
@@ -229,8 +239,12 @@ phiq_status phiq_plan_create(phiq_handle h, const phiq_kron_op* op, double t, in
 /* Execute a plan on nrhs vectors: v DEVICE nrhs x N, out DEVICE
  * nrhs x (p+1) x N (out[r][k] = phi_k(-tA) v[r]).  v and out must not
  * overlap.  Gauss plans run asynchronously and allocate nothing once the
- * handle's workspace is large enough; Clenshaw-Curtis plans synchronise the
- * stream once per doubling to read the error.  rep may be NULL. */
+ * handle's workspace is large enough; with FP64 products the vectors of a
+ * group (opt.rhs_per_launch) share every launch: one per mode product for
+ * all their node chains, one node sum, one phi_0 product and one per
+ * squaring product, so the workspace grows with the group.  Clenshaw-Curtis
+ * plans read the convergence decision of each level back to the host
+ * (Algorithm 2).  rep may be NULL. */
 phiq_status phiq_plan_execute(phiq_plan plan, const double* v, int nrhs, double* out,
                               phiq_report* rep, hipStream_t stream);
 

@@ -82,6 +82,7 @@ class Options(ctypes.Structure):
         ("accept_floor", c_int),
         ("selector_slack", c_double),
         ("batch_persistent", c_int),
+        ("rhs_per_launch", c_int),
     ]
 
 

@@ -130,10 +130,15 @@ phiq_status phiq_plan_execute(phiq_plan plan, const double* v, int nrhs, double*
   const char* oe = ob + (size_t)nrhs * (plan->p + 1) * N * sizeof(double);
   if (vb < oe && ob < ve) return PHIQ_ERR_INVALID_ARG;
   DeviceGuard g(plan->h->device);
-  for (int r = 0; r < nrhs; ++r) {
+  const int grp = rhs_group(plan, nrhs);
+  for (int r = 0; r < nrhs;) {
     const double* vr = v + (size_t)r * N;
     double* outr = out + (size_t)r * (plan->p + 1) * N;
-    if (plan->opt.precision == PHIQ_PREC_INT8) {
+    const int gr = std::min(grp, nrhs - r);
+    r += gr;
+    if (gr > 1) {
+      PHIQ_TRY(execute_gauss_group(plan, vr, gr, outr, stream));
+    } else if (plan->opt.precision == PHIQ_PREC_INT8) {
       PHIQ_TRY(execute_gauss_i8(plan, vr, outr, stream));
     } else if (plan->opt.rule == PHIQ_RULE_GAUSS) {
       PHIQ_TRY(execute_gauss(plan, vr, outr, stream));

@@ -368,7 +368,7 @@ inline const void* elem_offset(const void* X, long long elems, int f32) {
 }
 
 phiq_status chain_front(const phiq_plan_s* P, const double* X, long long xs, double* const* Ebase, long long const* es,
-                        int nb, void* T0, void* T1, hipStream_t st, Front* f, bool beside = false);
+                        int nb, void* T0, void* T1, hipStream_t st, Front* f, bool beside = false, int group = 0);
 TtmArgs final_args(const phiq_plan_s* P, const double* E, long long es, const Front& f, int nb);
 phiq_status phi0_chain(const phiq_plan_s* P, const double* v, double* out0, void* T0, void* T1, hipStream_t st,
                        bool side = false);
@@ -376,7 +376,9 @@ phiq_status phi0_start(const phiq_plan_s* P, const double* v, double* out0, void
 phiq_status phi0_finish(const phiq_plan_s* P, hipStream_t st);
 phiq_status squaring(const phiq_plan_s* P, double* Ycur, double* Yother, double* dst_final, void* T0, void* T1,
                      hipStream_t st);
-size_t gauss_ws_bytes(const phiq_plan_s* P);
+size_t gauss_ws_bytes(const phiq_plan_s* P, int g = 1);
+int rhs_group(const phiq_plan_s* P, int nrhs);
+phiq_status execute_gauss_group(phiq_plan P, const double* v, int g, double* out, hipStream_t st);
 phiq_status execute_gauss(phiq_plan P, const double* v, double* out, hipStream_t st, void* ws = nullptr,
                           size_t ws_cap = 0);
 

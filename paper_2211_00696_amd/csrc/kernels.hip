@@ -62,9 +62,11 @@ __global__ __launch_bounds__(C::NT, C::MINW) void ttm_store_kernel(TtmArgs a) {
   if (a.stop && *a.stop) return;
   int m0, n0, b;
   if (!tile_of_block<C>(a.M, a.L, a.nbatch, m0, n0, b)) return;
+  const int be = a.emod > 0 ? b % a.emod : b;
+  const int bx = a.xdiv > 0 ? b / a.xdiv : b;
   d4 acc[C::TM][C::TN];
   zero_acc<C>(acc);
-  tile_nt_db<C, VEC, NN>(a.E + b * a.es, (const double*)a.X + b * a.xs, a.M, a.K, a.L, m0, n0, smem, acc);
+  tile_nt_db<C, VEC, NN>(a.E + be * a.es, (const double*)a.X + bx * a.xs, a.M, a.K, a.L, m0, n0, smem, acc);
   double* O = (double*)a.O + b * a.os;
 #pragma unroll
   for (int i = 0; i < C::TM; ++i)
@@ -84,15 +86,16 @@ __global__ __launch_bounds__(C::NT, C::MINW) void ttm_store_kernel(TtmArgs a) {
 template <class C, int NP, bool VEC, bool NN = false>
 __global__ __launch_bounds__(C::NT, C::MINW) void ttm_accum_kernel(TtmArgs a) {
   __shared__ double smem[2 * (C::BM + C::BN) * C::LDK];
-  int m0, n0, bb;
-  if (!tile_of_block<C>(a.M, a.L, 1, m0, n0, bb)) return;
+  int m0, n0, r;
+  if (!tile_of_block<C>(a.M, a.L, a.nouter > 1 ? a.nouter : 1, m0, n0, r)) return;
+  const double* X = (const double*)a.X + r * a.xo;
   d4 y[NP][C::TM][C::TN];
 #pragma unroll
   for (int q = 0; q < NP; ++q) zero_acc<C>(y[q]);
   for (int b = 0; b < a.nbatch; ++b) {
     d4 acc[C::TM][C::TN];
     zero_acc<C>(acc);
-    tile_nt_db<C, VEC, NN>(a.E + b * a.es, (const double*)a.X + b * a.xs, a.M, a.K, a.L, m0, n0, smem, acc);
+    tile_nt_db<C, VEC, NN>(a.E + b * a.es, X + b * a.xs, a.M, a.K, a.L, m0, n0, smem, acc);
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
       const double w = ldexp(a.coef[q * a.ldcoef + b], a.cexp);
@@ -104,7 +107,7 @@ __global__ __launch_bounds__(C::NT, C::MINW) void ttm_accum_kernel(TtmArgs a) {
   }
 #pragma unroll
   for (int q = 0; q < NP; ++q) {
-    double* Y = a.Y + q * a.ys;
+    double* Y = a.Y + r * a.yo + q * a.ys;
 #pragma unroll
     for (int i = 0; i < C::TM; ++i)
 #pragma unroll
@@ -128,14 +131,18 @@ __global__ __launch_bounds__(C::NT, C::MINW) void ttm_accum_kernel(TtmArgs a) {
 template <class C, bool VEC, bool NN = false>
 __global__ __launch_bounds__(C::NT, C::MINW) void ttm_square_kernel(TtmArgs a) {
   __shared__ double smem[2 * (C::BM + C::BN) * C::LDK];
-  int m0, n0, b;
-  if (!tile_of_block<C>(a.M, a.L, a.nbatch, m0, n0, b)) return;
+  int m0, n0, bt;
+  const int no = a.nouter > 1 ? a.nouter : 1;
+  if (!tile_of_block<C>(a.M, a.L, a.nbatch * no, m0, n0, bt)) return;
+  const int r = bt / a.nbatch, b = bt % a.nbatch;
   d4 acc[C::TM][C::TN];
   zero_acc<C>(acc);
-  tile_nt_db<C, VEC, NN>(a.E + b * a.es, (const double*)a.X + b * a.xs, a.M, a.K, a.L, m0, n0, smem, acc);
+  tile_nt_db<C, VEC, NN>(a.E + b * a.es, (const double*)a.X + r * a.xo + b * a.xs, a.M, a.K, a.L, m0, n0, smem,
+                         acc);
   const int order = b + 1 + a.order0;
   const double scale = ldexp(1.0, -order);
-  double* O = (double*)a.O + b * a.os;
+  double* O = (double*)a.O + r * a.oo + b * a.os;
+  const double* Yp = a.Yprev + r * a.ypo;
 #pragma unroll
   for (int i = 0; i < C::TM; ++i)
 #pragma unroll
@@ -147,7 +154,7 @@ __global__ __launch_bounds__(C::NT, C::MINW) void ttm_square_kernel(TtmArgs a) {
         if (row < a.M && col < a.L) {
           const long long idx = (long long)row * a.L + col;
           double s = acc[i][j][e];
-          for (int jj = 1; jj <= order; ++jj) s += a.Yprev[(jj - 1) * a.yps + idx] * a.ifact[order - jj];
+          for (int jj = 1; jj <= order; ++jj) s += Yp[(jj - 1) * a.yps + idx] * a.ifact[order - jj];
           O[idx] = a.yacc ? O[idx] + scale * s : scale * s;
         }
       }
@@ -160,8 +167,10 @@ __global__ __launch_bounds__(C::NT, C::MINW) void ttm_square_kernel(TtmArgs a) {
 template <class C, int NP, bool VEC, bool NN = false>
 __global__ __launch_bounds__(C::NT, C::MINW) void ttm_square_all_kernel(TtmArgs a) {
   __shared__ double smem[2 * (C::BM + C::BN) * C::LDK];
-  int m0, n0, bb;
-  if (!tile_of_block<C>(a.M, a.L, 1, m0, n0, bb)) return;
+  int m0, n0, r;
+  if (!tile_of_block<C>(a.M, a.L, a.nouter > 1 ? a.nouter : 1, m0, n0, r)) return;
+  const double* X = (const double*)a.X + r * a.xo;
+  const double* Yp = a.Yprev + r * a.ypo;
   d4 ys[NP][C::TM][C::TN];
 #pragma unroll
   for (int i = 0; i < NP; ++i) {
@@ -175,14 +184,14 @@ __global__ __launch_bounds__(C::NT, C::MINW) void ttm_square_all_kernel(TtmArgs 
         for (int e = 0; e < 4; ++e) {
           const int row = m0 + acc_row<C>(ti, e);
           const int rc = row < a.M ? row : a.M - 1, cc = col < a.L ? col : a.L - 1;
-          ys[i][ti][tj][e] = a.Yprev[i * a.yps + (long long)rc * a.L + cc];
+          ys[i][ti][tj][e] = Yp[i * a.yps + (long long)rc * a.L + cc];
         }
       }
     d4 acc[C::TM][C::TN];
     zero_acc<C>(acc);
-    tile_nt_db<C, VEC, NN>(a.E, (const double*)a.X + i * a.xs, a.M, a.K, a.L, m0, n0, smem, acc);
+    tile_nt_db<C, VEC, NN>(a.E, X + i * a.xs, a.M, a.K, a.L, m0, n0, smem, acc);
     const double scale = ldexp(1.0, -(i + 1));
-    double* O = (double*)a.O + i * a.os;
+    double* O = (double*)a.O + r * a.oo + i * a.os;
 #pragma unroll
     for (int ti = 0; ti < C::TM; ++ti)
 #pragma unroll
@@ -466,6 +475,10 @@ int launch_taylor_jobs(const TaylorJob* jobs, int njobs, int nmax, void* stream,
 }
 
 namespace {
+inline int outer(const TtmArgs& a) { return a.nouter > 1 ? a.nouter : 1; }
+// several right-hand sides in one launch: only the FP64 rotated kernels
+inline bool two_index(const TtmArgs& a) { return a.emod > 0 || a.xdiv > 0 || a.nouter > 1; }
+
 template <class C>
 dim3 ttm_grid(const TtmArgs& a, int nb) {
   const long long T = ttm_tiles<C>(a.M, a.L, nb);
@@ -476,7 +489,7 @@ dim3 ttm_grid(const TtmArgs& a, int nb) {
 // (natural layout: X rows have L elements)
 bool vec_ok(const TtmArgs& a) {
   return (a.K % 2 == 0) && (!a.nn || a.L % 2 == 0) && (((uintptr_t)a.E | (uintptr_t)a.X) % 16 == 0) &&
-         (a.es % 2 == 0) && (a.xs % 2 == 0);
+         (a.es % 2 == 0) && (a.xs % 2 == 0) && (a.xo % 2 == 0);
 }
 
 template <class C>
@@ -490,14 +503,14 @@ int store_cfg(const TtmArgs& a, hipStream_t st) {
 template <class C>
 int square_cfg(const TtmArgs& a, hipStream_t st) {
   if (vec_ok(a))
-    PHIQ_LAUNCH((ttm_square_kernel<C, true>), ttm_grid<C>(a, a.nbatch), dim3(C::NT), 0, st, a);
+    PHIQ_LAUNCH((ttm_square_kernel<C, true>), ttm_grid<C>(a, a.nbatch * outer(a)), dim3(C::NT), 0, st, a);
   else
-    PHIQ_LAUNCH((ttm_square_kernel<C, false>), ttm_grid<C>(a, a.nbatch), dim3(C::NT), 0, st, a);
+    PHIQ_LAUNCH((ttm_square_kernel<C, false>), ttm_grid<C>(a, a.nbatch * outer(a)), dim3(C::NT), 0, st, a);
   return hipGetLastError();
 }
 template <class C, bool VEC>
 int accum_np(const TtmArgs& a, hipStream_t st) {
-  const dim3 g = ttm_grid<C>(a, 1);
+  const dim3 g = ttm_grid<C>(a, outer(a));
   switch (a.np) {
     case 1: PHIQ_LAUNCH((ttm_accum_kernel<C, 1, VEC>), g, dim3(C::NT), 0, st, a); break;
     case 2: PHIQ_LAUNCH((ttm_accum_kernel<C, 2, VEC>), g, dim3(C::NT), 0, st, a); break;
@@ -524,7 +537,7 @@ int store_nn(const TtmArgs& a, hipStream_t st) {
 template <class C, bool VEC>
 int accum_nn_v(const TtmArgs& a, hipStream_t st) {
   static_assert(C::BM == Tile64p1w8::BM && C::BN == Tile64p1w8::BN && C::NT == Tile64p1w8::NT, "same grid");
-  const dim3 g = ttm_grid<C>(a, 1);
+  const dim3 g = ttm_grid<C>(a, outer(a));
   switch (a.np) {
     case 1: PHIQ_LAUNCH((ttm_accum_kernel<C, 1, VEC, true>), g, dim3(C::NT), 0, st, a); break;
     case 2: PHIQ_LAUNCH((ttm_accum_kernel<C, 2, VEC, true>), g, dim3(C::NT), 0, st, a); break;
@@ -537,14 +550,14 @@ int accum_nn_v(const TtmArgs& a, hipStream_t st) {
 template <class C>
 int square_nn(const TtmArgs& a, hipStream_t st) {
   if (vec_ok(a))
-    PHIQ_LAUNCH((ttm_square_kernel<C, true, true>), ttm_grid<C>(a, a.nbatch), dim3(C::NT), 0, st, a);
+    PHIQ_LAUNCH((ttm_square_kernel<C, true, true>), ttm_grid<C>(a, a.nbatch * outer(a)), dim3(C::NT), 0, st, a);
   else
-    PHIQ_LAUNCH((ttm_square_kernel<C, false, true>), ttm_grid<C>(a, a.nbatch), dim3(C::NT), 0, st, a);
+    PHIQ_LAUNCH((ttm_square_kernel<C, false, true>), ttm_grid<C>(a, a.nbatch * outer(a)), dim3(C::NT), 0, st, a);
   return hipGetLastError();
 }
 template <class C, bool VEC>
 int square_all_nn_v(const TtmArgs& a, hipStream_t st) {
-  const dim3 g = ttm_grid<C>(a, 1);
+  const dim3 g = ttm_grid<C>(a, outer(a));
   switch (a.nbatch) {
     case 1: PHIQ_LAUNCH((ttm_square_all_kernel<C, 1, VEC, true>), g, dim3(C::NT), 0, st, a); break;
     case 2: PHIQ_LAUNCH((ttm_square_all_kernel<C, 2, VEC, true>), g, dim3(C::NT), 0, st, a); break;
@@ -579,6 +592,7 @@ int default_cfg(int kind, int M, int nb) {
 int ttm_num_configs(int kind) { return kind == 1 ? 7 : (kind == 2 ? 12 : 14); }
 
 int launch_ttm_store(const TtmArgs& a, phiq_precision prec, void* stream, int cfg) {
+  if (two_index(a) && prec != PHIQ_PREC_FP64) return hipErrorInvalidValue;
   if (prec == PHIQ_PREC_BF16X3 && !a.nn) {
     const int r = launch_ttm_store_bf16r(a, stream, cfg);
     if (r != hipErrorNotSupported) return r;
@@ -607,6 +621,7 @@ int launch_ttm_store(const TtmArgs& a, phiq_precision prec, void* stream, int cf
 }
 
 int launch_ttm_accum(const TtmArgs& a, phiq_precision prec, void* stream, int cfg) {
+  if (two_index(a) && prec != PHIQ_PREC_FP64) return hipErrorInvalidValue;
   if (a.np > 4 || a.np < 1) return hipErrorInvalidValue;
   if (prec != PHIQ_PREC_FP64) return a.nn ? hipErrorInvalidValue : launch_ttm_accum_lowp(a, prec, stream);
   hipStream_t st = (hipStream_t)stream;
@@ -627,7 +642,7 @@ int launch_ttm_accum(const TtmArgs& a, phiq_precision prec, void* stream, int cf
 namespace {
 template <class C, bool VEC>
 int square_all_np(const TtmArgs& a, hipStream_t st) {
-  const dim3 g = ttm_grid<C>(a, 1);
+  const dim3 g = ttm_grid<C>(a, outer(a));
   switch (a.nbatch) {
     case 1: PHIQ_LAUNCH((ttm_square_all_kernel<C, 1, VEC>), g, dim3(C::NT), 0, st, a); break;
     case 2: PHIQ_LAUNCH((ttm_square_all_kernel<C, 2, VEC>), g, dim3(C::NT), 0, st, a); break;
@@ -643,6 +658,7 @@ int square_all_cfg(const TtmArgs& a, hipStream_t st) {
 }  // namespace
 
 int launch_ttm_square(const TtmArgs& a, phiq_precision prec, void* stream, int cfg) {
+  if (two_index(a) && prec != PHIQ_PREC_FP64) return hipErrorInvalidValue;
   if (prec == PHIQ_PREC_BF16X3 && !a.nn) {
     const int r = launch_ttm_square_bf16r(a, stream, cfg);
     if (r != hipErrorNotSupported) return r;

@@ -20,16 +20,20 @@ hipEvent_t prof_event(phiq_handle h) {
 
 void ttm_work(const TtmArgs& a, int cls, double* flops, double* bytes) {
   const double N = (double)a.L * a.K;
-  *flops = 2.0 * a.M * a.K * (double)a.L * a.nbatch;
-  const double xin = (a.xs == 0 ? 1.0 : (double)a.nbatch) * N;
-  double out = (double)a.nbatch * a.M * a.L;
+  const double no = a.nouter > 1 ? a.nouter : 1;  // independent problems of one launch
+  *flops = 2.0 * a.M * a.K * (double)a.L * a.nbatch * no;
+  // distinct inputs: one when shared, nbatch / xdiv when grouped
+  const double nx = a.xs == 0 ? 1.0 : (a.xdiv > 0 ? (double)((a.nbatch + a.xdiv - 1) / a.xdiv) : (double)a.nbatch);
+  const double xin = nx * N * no;
+  double out = (double)a.nbatch * a.M * a.L * no;
   double extra = 0.0;
-  if (cls == K_TTM_ACCUM) out = (double)a.np * a.M * a.L;
-  if (cls == K_TTM_SQUARE) extra = (double)(a.nbatch + a.order0) * a.M * a.L;  // the y_j read once
+  if (cls == K_TTM_ACCUM) out = (double)a.np * a.M * a.L * no;
+  if (cls == K_TTM_SQUARE) extra = (double)(a.nbatch + a.order0) * a.M * a.L * no;  // the y_j read once
   if (a.yacc) extra += out;  // the previous output read back
   const double xb = a.x_f32 ? 4.0 : 8.0;
   const double ob = (a.o_f32 && cls == K_TTM_STORE) ? 4.0 : 8.0;
-  *bytes = xb * xin + ob * out + 8.0 * (extra + (double)a.nbatch * a.M * a.K * (a.es == 0 ? 0.0 : 1.0));
+  const double nf = a.es == 0 ? 0.0 : (a.emod > 0 ? (double)std::min(a.emod, a.nbatch) : (double)a.nbatch);
+  *bytes = xb * xin + ob * out + 8.0 * (extra + nf * a.M * a.K);
 }
 
 int tuned_cfg(phiq_handle h, int kind, const TtmArgs& a) {

@@ -192,6 +192,16 @@ struct TtmArgs {
   // nullable: a device flag; when it is set the launch does nothing (the
   // speculative level of adaptive Clenshaw-Curtis after convergence)
   const int* stop;
+  // Several right-hand sides in one launch (FP64 rotated kernels only).
+  // Plain products: when emod > 0 batch b takes factor b % emod, and when
+  // xdiv > 0 input b / xdiv (the node chains of several vectors, b = r *
+  // emod + i for vector r and node i: emod in every product, xdiv in the
+  // first, which reads the vectors themselves).  Node sum and
+  // squaring: nouter > 1 independent problems r, each offset by r * xo in X,
+  // r * yo in Y, r * oo in O and r * ypo in Yprev.
+  int emod, xdiv;
+  int nouter;
+  long long xo, yo, oo, ypo;
   double ifact[PHIQ_MAX_P + 1];  // ifact[k] = 1/k!
 };
 

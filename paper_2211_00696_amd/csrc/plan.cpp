@@ -277,7 +277,7 @@ phiq_status plan_build(phiq_handle h, const phiq_kron_op* op, double t, int p, d
   if (!std::isfinite(opt.c1) || !std::isfinite(opt.c2) || !std::isfinite(opt.alpha)) return PHIQ_ERR_NONFINITE;
   if (opt.c1 < 0 || opt.c2 < 0 || opt.l < -1 || opt.l > 60 || opt.m < -1 || opt.m == 0 || opt.m > 4096 ||
       opt.cc_max_doublings < 1 || opt.cc_max_doublings > 10 || !(opt.selector_slack >= 0.0) ||
-      opt.selector_slack > 12.0)
+      opt.selector_slack > 12.0 || opt.rhs_per_launch < 0)
     return PHIQ_ERR_INVALID_ARG;
 
   PlanParams pp;

@@ -74,7 +74,7 @@ class _Op:
 
 def options(rule="gauss", precision="fp64", l=None, m=None, alpha=None, c1=None, c2=None,
             cc_max_doublings=None, workspace_cap=None, use_graphs=None, selector=None, slab_products=None,
-            accept_floor=None, selector_slack=None, batch_persistent=None):
+            accept_floor=None, selector_slack=None, batch_persistent=None, rhs_per_launch=None):
     lib = L.load()
     o = L.Options()
     _check(lib.phiq_options_default(byref(o)), "phiq_options_default")
@@ -106,6 +106,8 @@ def options(rule="gauss", precision="fp64", l=None, m=None, alpha=None, c1=None,
         o.selector_slack = float(selector_slack)
     if batch_persistent is not None:
         o.batch_persistent = int(bool(batch_persistent))
+    if rhs_per_launch is not None:
+        o.rhs_per_launch = int(rhs_per_launch)
     return o
 
 
