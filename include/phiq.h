@@ -135,7 +135,12 @@ typedef struct {
                             /* product launch (node, vector) as one batch index.    */
                             /* 0 (default) = as many as fit in PHIQ_RHS_GROUP_BYTES */
                             /* of intermediates; 1 = one vector at a time; k = at   */
-                            /* most k.  The results are bitwise the same.           */
+                            /* most k.  The results are bitwise the same.  1 also   */
+                            /* keeps the vectors of phiq_plan_execute_combo in      */
+                            /* separate launches (otherwise, FP64 Gauss with every  */
+                            /* b_1..b_p set and p <= 4, all node chains and phi_0's */
+                            /* chain share one launch per mode product and one node */
+                            /* sum: the same sums, another rounding order)          */
 } phiq_options;
 
 /* Device bytes of intermediates a group of right-hand sides may take when

@@ -61,12 +61,85 @@ phiq_status combo_squaring(const phiq_plan_s* P, double* cur, double* other, int
 //   y_{p-j+k} += 2^{l(p-j)} sum_q w_q theta_q^{k-1}/(k-1)! e^{(1-theta_q) s Z} b_j,
 // k = 1..j: the usual node coefficients with a power-of-two factor.  Only y_p
 // is needed after the last step, so that step applies one chain.
+// FP64 with every b_1..b_p set (p <= 4): one batch per mode product for the
+// node chains of all b_j and phi_0's chain of b_0 (batch segments), then one
+// node sum for all of them with the plan's combined coefficients.
+phiq_status execute_combo_fused(phiq_plan P, const double* const* b, double* out, hipStream_t st) {
+  phiq_handle h = P->h;
+  const long long N = P->N;
+  const int p = P->p, m = P->m;
+  TtmSegs sg{};
+  int nb = 0;
+  for (int j = p; j >= 1; --j) {
+    sg.sb[sg.n] = nb;
+    sg.se[sg.n] = 0;
+    sg.sx[sg.n] = b[j];
+    ++sg.n;
+    nb += m;
+  }
+  const bool have0 = b[0] != nullptr;
+  if (have0) {  // slot m of the node tables is phi_0's factor
+    sg.sb[sg.n] = nb;
+    sg.se[sg.n] = m;
+    sg.sx[sg.n] = b[0];
+    ++sg.n;
+    nb += 1;
+  }
+  sg.sb[sg.n] = nb;
+  const size_t tbytes = (size_t)std::max(nb, p) * N * sizeof(double);
+  const size_t ybytes = (size_t)p * N * sizeof(double);
+  PHIQ_TRY(ensure(h, h->ws, 2 * align_up(tbytes) + 2 * align_up(ybytes)));
+  char* wb = (char*)h->ws.p;
+  void* T0 = wb;
+  void* T1 = wb + align_up(tbytes);
+  double* Ya = (double*)(wb + 2 * align_up(tbytes));
+  double* Yb = (double*)(wb + 2 * align_up(tbytes) + align_up(ybytes));
+
+  double* E[PHIQ_MAX_DIM];
+  long long es[PHIQ_MAX_DIM];
+  for (int d = 0; d < P->D; ++d) {
+    E[d] = P->Enode[d];
+    es[d] = (long long)P->n[d] * P->n[d];
+  }
+  PHIQ_TRY(wait_join(P, st));
+  Front f;
+  PHIQ_TRY(chain_front(P, nullptr, 0, E, es, nb, T0, T1, st, &f, false, 0, &sg));
+  if (have0) {  // phi_0 b_0 into out: the last product of the b_0 segment
+    Front f0 = f;
+    f0.X = elem_offset(f.X, (long long)p * m * f.xs, f.f32);
+    TtmArgs a = final_args(P, P->Ephi0[0], 0, f0, 1);
+    a.O = out;
+    a.os = 0;
+    PHIQ_TRY(L_ttm(h, K_TTM_STORE, a, P->opt.precision, st, &P->twins));
+  }
+  // node sum of all b_j: y_q = sum over (j, i) of the combined coefficients;
+  // without squaring only y_p, added to phi_0 b_0 in out
+  const bool direct = (P->l == 0);
+  TtmArgs a = final_args(P, P->Enode[0], es[0], f, p * m);
+  a.emod = m;
+  a.ldcoef = p * m;
+  a.coef = P->coefc + (direct ? (size_t)(p - 1) * a.ldcoef : 0);
+  a.np = direct ? 1 : p;
+  a.Y = direct ? out : Ya;
+  a.ys = N;
+  a.yacc = (direct && have0) ? 1 : 0;
+  PHIQ_TRY(L_ttm(h, K_TTM_ACCUM, a, P->opt.precision, st, &P->twins));
+  if (direct) return PHIQ_OK;
+  return combo_squaring(P, Ya, Yb, p, out, have0, false, T0, T1, st);
+}
+
 phiq_status execute_combo(phiq_plan P, const double* const* b, double* out, hipStream_t st) {
   phiq_handle h = P->h;
   const long long N = P->N;
   int pe = 0;  // highest order with a vector
-  for (int j = 1; j <= P->p; ++j)
+  bool all = true;
+  for (int j = 1; j <= P->p; ++j) {
     if (b[j]) pe = j;
+    all = all && b[j];
+  }
+  if (all && P->coefc && P->opt.precision == PHIQ_PREC_FP64 && P->opt.slab_products == 0 && P->D >= 2 &&
+      P->opt.rhs_per_launch != 1)
+    return execute_combo_fused(P, b, out, st);
   const int nb = std::max(P->m + 1, P->p);
   const size_t tbytes = (P->D > 1 ? (size_t)nb * N * sizeof(double) : 0);
   const size_t ybytes = (size_t)std::max(1, P->p) * N * sizeof(double);

@@ -210,6 +210,11 @@ struct phiq_plan_s {
   double* S[2][PHIQ_MAX_DIM] = {};   // ping-pong for the sigma squarings
   double* coef = nullptr;            // p x ldcoef
   int ldcoef = 0;
+  // Gauss, 1 <= p <= 4: the node-sum coefficients of a linear combination
+  // with every b_1..b_p set, p x (p m): row q (y_{q+1}), column (p - j) m + i
+  // (node i of b_j) holds 2^{l (p - j)} w_i theta_i^k / k!, k = q - (p - j),
+  // zero where k < 0 (execute_combo's one-launch node sum)
+  double* coefc = nullptr;
   char* jobs = nullptr;              // device job tables (per upload)
   size_t jobs_cap = 0;
   TwinMap twins;  // lower-precision copies of the matrices
@@ -368,7 +373,8 @@ inline const void* elem_offset(const void* X, long long elems, int f32) {
 }
 
 phiq_status chain_front(const phiq_plan_s* P, const double* X, long long xs, double* const* Ebase, long long const* es,
-                        int nb, void* T0, void* T1, hipStream_t st, Front* f, bool beside = false, int group = 0);
+                        int nb, void* T0, void* T1, hipStream_t st, Front* f, bool beside = false, int group = 0,
+                        const TtmSegs* segs = nullptr);
 TtmArgs final_args(const phiq_plan_s* P, const double* E, long long es, const Front& f, int nb);
 phiq_status phi0_chain(const phiq_plan_s* P, const double* v, double* out0, void* T0, void* T1, hipStream_t st,
                        bool side = false);

@@ -12,15 +12,19 @@ namespace phiq {
 // factor b % group in every product, and input b / group in the first
 // (later products read their own batch b of the intermediates).
 phiq_status chain_front(const phiq_plan_s* P, const double* X, long long xs, double* const* Ebase, long long const* es,
-                        int nb, void* T0, void* T1, hipStream_t st, Front* f, bool beside, int group) {
+                        int nb, void* T0, void* T1, hipStream_t st, Front* f, bool beside, int group,
+                        const TtmSegs* segs) {
   if (group > 0 && (P->opt.precision != PHIQ_PREC_FP64 || nb % group != 0)) return PHIQ_ERR_INVALID_ARG;
+  // segs (FP64 only): the batch in segments (TtmSegs), the inputs named there
+  if (segs && (P->opt.precision != PHIQ_PREC_FP64 || segs->n < 1 || segs->n > kSegMax || segs->sb[segs->n] != nb))
+    return PHIQ_ERR_INVALID_ARG;
   // 1: single-vector chains only (with a batch the per-axis kernels keep more
   // waves per CU busy and were faster at n = 128), and not beside other work
   // on a side stream, where a block that takes a whole CU's LDS waits for a
   // free CU
   const int sp = P->opt.slab_products;
   if (P->D == 3 && P->n[1] == kSlabN && P->n[2] == kSlabN && P->opt.precision == PHIQ_PREC_FP64 && !P->h->guard &&
-      group == 0 && (sp == 2 || (sp == 1 && nb == 1 && !beside))) {
+      group == 0 && !segs && (sp == 2 || (sp == 1 && nb == 1 && !beside))) {
     SlabArgs s{};
     s.X = X;
     s.xs = xs;
@@ -66,6 +70,11 @@ phiq_status chain_front(const phiq_plan_s* P, const double* X, long long xs, dou
     if (group > 0) {
       a.emod = group;
       if (s == 0) a.xdiv = group;
+    }
+    if (segs) {
+      a.seg = *segs;
+      if (s > 0)  // later products read their own batch of the intermediates
+        for (int q = 0; q < kSegMax; ++q) a.seg.sx[q] = nullptr;
     }
     PHIQ_TRY(L_ttm(P->h, K_TTM_STORE, a, P->opt.precision, st, &P->twins));
     cur = a.O;

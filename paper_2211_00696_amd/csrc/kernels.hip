@@ -62,11 +62,29 @@ __global__ __launch_bounds__(C::NT, C::MINW) void ttm_store_kernel(TtmArgs a) {
   if (a.stop && *a.stop) return;
   int m0, n0, b;
   if (!tile_of_block<C>(a.M, a.L, a.nbatch, m0, n0, b)) return;
-  const int be = a.emod > 0 ? b % a.emod : b;
-  const int bx = a.xdiv > 0 ? b / a.xdiv : b;
+  int be = a.emod > 0 ? b % a.emod : b;
+  int bx = a.xdiv > 0 ? b / a.xdiv : b;
+  const double* X = (const double*)a.X;
+  if (a.seg.n > 0) {
+    // constant indices only: the table stays in the argument segment
+    int s0 = a.seg.sb[0], e0 = a.seg.se[0];
+    const double* x0 = a.seg.sx[0];
+#pragma unroll
+    for (int s = 1; s < kSegMax; ++s)
+      if (s < a.seg.n && b >= a.seg.sb[s]) {
+        s0 = a.seg.sb[s];
+        e0 = a.seg.se[s];
+        x0 = a.seg.sx[s];
+      }
+    be = e0 + (b - s0);
+    if (x0) {
+      X = x0;
+      bx = 0;
+    }
+  }
   d4 acc[C::TM][C::TN];
   zero_acc<C>(acc);
-  tile_nt_db<C, VEC, NN>(a.E + be * a.es, (const double*)a.X + bx * a.xs, a.M, a.K, a.L, m0, n0, smem, acc);
+  tile_nt_db<C, VEC, NN>(a.E + be * a.es, X + bx * a.xs, a.M, a.K, a.L, m0, n0, smem, acc);
   double* O = (double*)a.O + b * a.os;
 #pragma unroll
   for (int i = 0; i < C::TM; ++i)
@@ -95,7 +113,8 @@ __global__ __launch_bounds__(C::NT, C::MINW) void ttm_accum_kernel(TtmArgs a) {
   for (int b = 0; b < a.nbatch; ++b) {
     d4 acc[C::TM][C::TN];
     zero_acc<C>(acc);
-    tile_nt_db<C, VEC, NN>(a.E + b * a.es, X + b * a.xs, a.M, a.K, a.L, m0, n0, smem, acc);
+    tile_nt_db<C, VEC, NN>(a.E + (a.emod > 0 ? b % a.emod : b) * a.es, X + b * a.xs, a.M, a.K, a.L, m0, n0, smem,
+                           acc);
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
       const double w = ldexp(a.coef[q * a.ldcoef + b], a.cexp);
@@ -477,7 +496,7 @@ int launch_taylor_jobs(const TaylorJob* jobs, int njobs, int nmax, void* stream,
 namespace {
 inline int outer(const TtmArgs& a) { return a.nouter > 1 ? a.nouter : 1; }
 // several right-hand sides in one launch: only the FP64 rotated kernels
-inline bool two_index(const TtmArgs& a) { return a.emod > 0 || a.xdiv > 0 || a.nouter > 1; }
+inline bool two_index(const TtmArgs& a) { return a.emod > 0 || a.xdiv > 0 || a.nouter > 1 || a.seg.n > 0; }
 
 template <class C>
 dim3 ttm_grid(const TtmArgs& a, int nb) {
@@ -488,8 +507,10 @@ dim3 ttm_grid(const TtmArgs& a, int nb) {
 // 16-byte vector loads need even row lengths and 16-byte aligned operands
 // (natural layout: X rows have L elements)
 bool vec_ok(const TtmArgs& a) {
-  return (a.K % 2 == 0) && (!a.nn || a.L % 2 == 0) && (((uintptr_t)a.E | (uintptr_t)a.X) % 16 == 0) &&
-         (a.es % 2 == 0) && (a.xs % 2 == 0) && (a.xo % 2 == 0);
+  uintptr_t ptrs = (uintptr_t)a.E | (uintptr_t)a.X;
+  for (int s = 0; s < a.seg.n && s < kSegMax; ++s) ptrs |= (uintptr_t)a.seg.sx[s];
+  return (a.K % 2 == 0) && (!a.nn || a.L % 2 == 0) && (ptrs % 16 == 0) && (a.es % 2 == 0) && (a.xs % 2 == 0) &&
+         (a.xo % 2 == 0);
 }
 
 template <class C>
@@ -666,8 +687,12 @@ int launch_ttm_square(const TtmArgs& a, phiq_precision prec, void* stream, int c
   if (prec != PHIQ_PREC_FP64) return a.nn ? hipErrorInvalidValue : launch_ttm_square_lowp(a, prec, stream);
   hipStream_t st = (hipStream_t)stream;
   if (a.nn) return launch_nn(2, a, st);
-  // an order offset or an accumulating store needs the per-order kernel
-  if ((a.order0 != 0 || a.yacc) && (cfg < 0 || cfg >= 7)) cfg = a.M >= 128 ? 5 : 6;
+  // an order offset or an accumulating store needs the per-order kernel:
+  // 64 x 128 tiles when they fill the GPU twice over, else 64 x 64 (the last
+  // step of a linear combination is one vector: 64 x 128 tiles left one
+  // four-wave block per CU)
+  if ((a.order0 != 0 || a.yacc) && (cfg < 0 || cfg >= 7))
+    cfg = (a.M >= 128 && ttm_tiles<Tile64x128>(a.M, a.L, a.nbatch * outer(a)) >= 768) ? 5 : 6;
   if (cfg < 0) cfg = default_cfg(2, a.M, a.nbatch);
   // shapes 7.. : all orders per block (p <= 4)
   if (cfg >= 7) {

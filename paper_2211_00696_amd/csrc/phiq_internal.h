@@ -161,6 +161,18 @@ struct TaylorJob {
 // which side is FP32; strides are in elements).  With nn set (FP64 only)
 // X is read in its natural layout instead, X[k * L + j]: the last product
 // after the two-axis slab product, which leaves the layout unchanged.
+// Batch segments of a plain FP64 product: batches [sb[s], sb[s+1]) take
+// factor se[s] + (b - sb[s]) and, when sx[s] is set, the one input vector
+// sx[s] (the first product of the node chains of several vectors of a
+// linear combination, plus phi_0's factor for b_0).
+constexpr int kSegMax = 5;
+struct TtmSegs {
+  int n;
+  int sb[kSegMax + 1];
+  int se[kSegMax];
+  const double* sx[kSegMax];
+};
+
 struct TtmArgs {
   const double* E;
   long long es;
@@ -202,6 +214,7 @@ struct TtmArgs {
   int emod, xdiv;
   int nouter;
   long long xo, yo, oo, ypo;
+  TtmSegs seg;  // n = 0: none (plain products only; emod and xdiv unused)
   double ifact[PHIQ_MAX_P + 1];  // ifact[k] = 1/k!
 };
 

@@ -333,6 +333,9 @@ phiq_status plan_build(phiq_handle h, const phiq_kron_op* op, double t, int p, d
   for (int d = 0; d < P->D; ++d) offA[d] = L.take((size_t)P->n[d] * P->n[d] * sizeof(double));
   const size_t coef_bytes = sizeof(double) * (size_t)std::max(1, p) * P->ldcoef;
   const size_t offCoef = L.take(coef_bytes);
+  const bool combo_tab = opt.rule == PHIQ_RULE_GAUSS && p >= 1 && p <= 4;
+  const size_t coefc_bytes = combo_tab ? sizeof(double) * (size_t)p * p * P->m : 0;
+  const size_t offCoefC = combo_tab ? L.take(coefc_bytes) : 0;
   const size_t jobs_cap = 1 << 20;
   const size_t offJobs = L.take(jobs_cap);
   const int nslots = P->m + 1;  // Taylor targets: nodes + E^(0)
@@ -389,6 +392,7 @@ phiq_status plan_build(phiq_handle h, const phiq_kron_op* op, double t, int p, d
     P->S[1][d] = P->sigma[d] > 1 ? (double*)(base + offS1[d]) : nullptr;
   }
   P->coef = (double*)(base + offCoef);
+  P->coefc = combo_tab ? (double*)(base + offCoefC) : nullptr;
   P->jobs = base + offJobs;
   P->jobs_cap = jobs_cap;
   if (lp) {
@@ -458,6 +462,18 @@ phiq_status plan_build(phiq_handle h, const phiq_kron_op* op, double t, int p, d
       for (int k = 2; k <= j; ++k) fact *= k;
       for (int q = 0; q < P->m; ++q) hc[(size_t)j * P->ldcoef + q] = w[q] * std::pow(theta[q], j) / fact;
     }
+  }
+  if (combo_tab) {
+    const int ld = p * P->m;
+    double* hcc = (double*)(hp + offCoefC);
+    std::fill(hcc, hcc + (size_t)p * ld, 0.0);
+    for (int q = 0; q < p; ++q)
+      for (int j = 1; j <= p; ++j) {
+        const int k = q - (p - j);
+        if (k < 0) continue;
+        for (int i = 0; i < P->m; ++i)
+          hcc[(size_t)q * ld + (size_t)(p - j) * P->m + i] = std::ldexp(hc[(size_t)k * P->ldcoef + i], l * (p - j));
+      }
   }
   std::memcpy(hp + offJobs, blob.bytes.data(), blob.bytes.size());
   // upload: a copy kernel on the caller's stream reads the pinned staging

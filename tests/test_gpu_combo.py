@@ -284,3 +284,32 @@ def test_combo_lower_precision_vs_fp64(h, precision, bar, rule):
     e = rel(got, ref)
     print(rep["l"], rep["m"], e, flush=True)
     assert e < bar, e
+
+
+@pytest.mark.parametrize("sizes,p,b0,t", [([24, 40, 56], 3, True, 2e-3), ([64, 48], 1, True, 5e-3),
+                                          ([33, 20, 17], 4, False, 2e-3), ([16, 24, 20], 2, True, 1e-7)])
+def test_combo_fused_matches_separate_launches(h, sizes, p, b0, t):
+    """With every b_1..b_p set (FP64, p <= 4) the node chains of all b_j and phi_0's chain of b_0 share one
+    launch per mode product and one node sum (the combined coefficient table).  Same sums as the launches
+    per vector (rhs_per_launch = 1) in another rounding order; fewer launches."""
+    mats = ops(sizes, seed=11)
+    N = int(np.prod(sizes))
+    rng = np.random.default_rng(p)
+    bs = draw(rng, p, N, none=() if b0 else (0,))
+    dev = [None if b is None else torch.from_numpy(b).cuda() for b in bs]
+    print("combo fused vs separate", sizes, p, b0, t, flush=True)
+    outs, counts = [], []
+    for grp in (0, 1):
+        plan = h.plan(mats, t, p, tol=1e-10, rhs_per_launch=grp)
+        plan.execute_combo(dev)
+        torch.cuda.synchronize()
+        h.profile_start()
+        o = plan.execute_combo(dev)
+        st = h.profile_stop()
+        outs.append(o.cpu().numpy())
+        counts.append(sum(s["launches"] for k, s in st.items() if k.startswith("ttm")))
+        plan.close()
+    e = rel(outs[0], outs[1])
+    print("rel diff", e, "mode-product launches fused / separate", counts, flush=True)
+    assert e < 1e-13, e
+    assert counts[0] < counts[1], counts
