@@ -87,7 +87,17 @@ phiq_status L_ttm(phiq_handle h, int cls, const TtmArgs& a0, phiq_precision prec
             : (prec != PHIQ_PREC_FP64) ? -1
                                        : (h->force_cfg[kind] >= 0 ? h->force_cfg[kind] : tuned_cfg(h, kind, a));
   if (prec == PHIQ_PREC_FP64 && cfg < 0) cfg = fallback_cfg(kind, a);
-  return prof_launch(h, st, cls, fl, by, [&] { return launch_kind(kind, a, prec, st, cfg); });
+  // FP64 plain and squaring products: the resident-factor kernels first
+  // (kinds 5 / 6 of phiq_tile_config), unless a tile shape is forced
+  const bool try_r = prec == PHIQ_PREC_FP64 && kind != 1 && h->force_cfg[kind] < 0;
+  const int rcfg = h->force_cfg[kind == 0 ? 5 : 6];
+  return prof_launch(h, st, cls, fl, by, [&] {
+    if (try_r) {
+      const int r = kind == 0 ? launch_ttm_store_f64r(a, st, rcfg) : launch_ttm_square_f64r(a, st, rcfg);
+      if (r != hipErrorNotSupported) return r;
+    }
+    return launch_kind(kind, a, prec, st, cfg);
+  });
 }
 
 phiq_status L_gemm(phiq_handle h, const GemmJob* jobs, int njobs, int nm, hipStream_t st) {

@@ -237,6 +237,11 @@ int launch_ttm_square(const TtmArgs& a, phiq_precision prec, void* stream, int c
 int bf16r_num_configs();
 int bf16r_square_num_configs();
 int launch_ttm_store_bf16r(const TtmArgs& a, void* stream, int cfg);
+// FP64 with the factor resident in LDS (kernels_f64r.hip): n in {64, 128,
+// 256}; cfg 0 declines, -1 = default; hipErrorNotSupported when declined
+int launch_ttm_store_f64r(const TtmArgs& a, void* stream, int cfg);
+int launch_ttm_square_f64r(const TtmArgs& a, void* stream, int cfg);
+int f64r_num_configs();
 int launch_ttm_square_bf16r(const TtmArgs& a, void* stream, int cfg);
 
 // Products along axes 2 and 1 of nbatch tensors n0 x kSlabN x kSlabN in one
