@@ -135,7 +135,10 @@ typedef struct {
                             /* product launch (node, vector) as one batch index.    */
                             /* 0 (default) = as many as fit in PHIQ_RHS_GROUP_BYTES */
                             /* of intermediates; 1 = one vector at a time; k = at   */
-                            /* most k.  The results are bitwise the same.  1 also   */
+                            /* most k.  Same sums: bitwise the same when the same   */
+                            /* kernels run (the kernel can depend on the launch's   */
+                            /* size: at n_d = 256 large plain products sum k in     */
+                            /* another order, see phiq_tile_config kind 5).  1 also */
                             /* keeps the vectors of phiq_plan_execute_combo in      */
                             /* separate launches (otherwise, FP64 Gauss with every  */
                             /* b_1..b_p set and p <= 4, all node chains and phi_0's */

@@ -197,9 +197,11 @@ int rhs_group(const phiq_plan_s* P, int nrhs) {
 // takes the pair (vector r, node i) as batch r (m+1) + i, the later products
 // are plain batches over the contiguous intermediates, and the node sum, the
 // phi_0 product and the squaring products run the g problems side by side
-// (TtmArgs::nouter).  Each output element is formed by the same kernels in
-// the same order as for one vector, so the results are bitwise those of
-// g separate executions.
+// (TtmArgs::nouter).  Each output element is formed by the same sums in the
+// same order as for one vector, so the results are bitwise those of g
+// separate executions whenever the same kernels are chosen (the choice can
+// depend on a launch's size; at n = 256 the resident-factor kernel sums k in
+// another order).
 phiq_status execute_gauss_group(phiq_plan P, const double* v, int g, double* out, hipStream_t st) {
   phiq_handle h = P->h;
   const long long N = P->N;
