@@ -385,10 +385,12 @@ int square_go(const TtmArgs& a, hipStream_t st) {
 }
 
 // NV orders, NY = order0 + NV iterates (NY <= 4)
-template <int K, int NV>
+// (WR = 2: eight waves in two row groups, two waves per SIMD, so one wave's
+// epilogue can run beside another's products)
+template <int K, int NV, int WR>
 int square_nv(const TtmArgs& a, hipStream_t st) {
   constexpr int S = NV * (K / 32);
-  using C = FC<Shape<K>::BM, K, Shape<K>::WR, 4, Shape<K>::TN, (S % 4 == 0 ? 4 : (S % 2 == 0 ? 2 : 1)), NV>;
+  using C = FC<Shape<K>::BM, K, WR, 4, Shape<K>::TN, (S % 4 == 0 ? 4 : (S % 2 == 0 ? 2 : 1)), NV>;
   switch (a.order0 + NV) {
     case 1: return square_go<C, (NV <= 1 ? 1 : NV)>(a, st);
     case 2: return square_go<C, (NV <= 2 ? 2 : NV)>(a, st);
@@ -397,13 +399,13 @@ int square_nv(const TtmArgs& a, hipStream_t st) {
   }
 }
 
-template <int K>
+template <int K, int WR>
 int square_shape(const TtmArgs& a, hipStream_t st) {
   switch (a.nbatch) {
-    case 1: return square_nv<K, 1>(a, st);
-    case 2: return square_nv<K, 2>(a, st);
-    case 3: return square_nv<K, 3>(a, st);
-    default: return square_nv<K, 4>(a, st);
+    case 1: return square_nv<K, 1, WR>(a, st);
+    case 2: return square_nv<K, 2, WR>(a, st);
+    case 3: return square_nv<K, 3, WR>(a, st);
+    default: return square_nv<K, 4, WR>(a, st);
   }
 }
 
@@ -443,17 +445,29 @@ int launch_ttm_store_f64r(const TtmArgs& a, void* stream, int cfg) {
   return store_shape<64>(a, st, cfg);
 }
 
-// Squaring: cfg 1 = the resident kernel (four waves), 0 or -1 (default) =
-// decline: at n = 256 the three-order step took 4.05 ms per phi-action
-// against 3.78 with the tile kernel, at n = 128 0.24 against 0.21.
+// Squaring: cfg 1 = the resident kernel (four waves), 2 = eight waves in two
+// row groups, 0 = decline, -1 = default: cfg 2 at n = 256 with at least one
+// unit per CU, else decline.  Per 3D phi-action (seven three-order steps at
+// n = 256, five at n = 128): n = 256 3.40 ms (cfg 2) and 4.04 ms (cfg 1)
+// against 3.73 ms with the tile kernel; n = 128 0.23 / 0.24 against 0.21.
 int launch_ttm_square_f64r(const TtmArgs& a, void* stream, int cfg) {
-  if (cfg <= 0 || !f64r_shape(a) || a.nbatch > 4 || a.es != 0 || a.order0 < 0 || a.order0 + a.nbatch > 4 ||
+  if (cfg == 0 || !f64r_shape(a) || a.nbatch > 4 || a.es != 0 || a.order0 < 0 || a.order0 + a.nbatch > 4 ||
       a.yps % 2 != 0 || (a.nbatch > 1 && a.os % 2 != 0))
     return hipErrorNotSupported;
+  if (cfg < 0) {
+    const long long units = (long long)((a.L + 63) / 64) * (a.K == 256 ? 4 : 1);
+    if (a.K != 256 || units < cu_count()) return hipErrorNotSupported;
+    cfg = 2;
+  }
   hipStream_t st = (hipStream_t)stream;
-  if (a.K == 256) return square_shape<256>(a, st);
-  if (a.K == 128) return square_shape<128>(a, st);
-  return square_shape<64>(a, st);
+  if (cfg == 2) {
+    if (a.K == 256) return square_shape<256, 2>(a, st);
+    if (a.K == 128) return square_shape<128, 2>(a, st);
+    return square_shape<64, 2>(a, st);
+  }
+  if (a.K == 256) return square_shape<256, 1>(a, st);
+  if (a.K == 128) return square_shape<128, 1>(a, st);
+  return square_shape<64, 1>(a, st);
 }
 
 }  // namespace phiq

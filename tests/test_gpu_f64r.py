@@ -3,7 +3,8 @@
 The plain product (phiq_tile_config kind 5) and the product fused with the
 modified squaring of eq. squaring (kind 6) for n_d in {64, 128, 256},
 forced on every launch (cfg 1: four waves with all row blocks, cfg 2: eight
-waves in two row groups), through the C ABI:
+waves in two row groups; the default takes cfg 2 for n = 256 launches with
+at least one unit per CU), through the C ABI:
 
   * Kronecker products (F^0 (x) F^1 (x) F^2) x against the oracle's
     apply_kron (numpy, FP64) and against the tile kernels (cfg 0): the same
@@ -94,7 +95,7 @@ def adv128():
     return pr, ref
 
 
-@pytest.mark.parametrize("store,square", [(1, 1), (2, 1), (1, 0), (0, 1), (-1, -1)])
+@pytest.mark.parametrize("store,square", [(1, 1), (2, 1), (2, 2), (1, 0), (0, 2), (-1, -1)])
 def test_f64r_phi_action_n128_vs_oracle(h, adv128, store, square):
     """3D n = 128 phi_0..phi_3 (seed 0, tol 1e-8) with the resident kernels
     forced on the plain products and/or the squaring products (0: the tile
@@ -108,8 +109,9 @@ def test_f64r_phi_action_n128_vs_oracle(h, adv128, store, square):
     assert max(errs) < 1e-8, errs
 
 
+@pytest.mark.parametrize("cfg", [1, 2])
 @pytest.mark.parametrize("sizes,p", [([64, 8], 3), ([128, 6], 1), ([64, 4, 5], 2), ([128, 9], 4)])
-def test_f64r_combination_vs_definition(h, sizes, p):
+def test_f64r_combination_vs_definition(h, sizes, p, cfg):
     """sum_j phi_j(-tA) b_j with both kinds forced: the last squaring step
     forms y_p alone (order offset p - 1) and adds it to phi_0 b_0."""
     rng = np.random.default_rng(p)
@@ -120,8 +122,8 @@ def test_f64r_combination_vs_definition(h, sizes, p):
     N = int(np.prod(sizes))
     bs = [rng.standard_normal(N) for _ in range(p + 1)]
     t = 0.01
-    print("f64r combination", sizes, p, flush=True)
-    with forced(h, 1, 1):
+    print("f64r combination", sizes, p, cfg, flush=True)
+    with forced(h, cfg, cfg):
         plan = h.plan(mats, t, p, tol=1e-12)
         got = host(plan.execute_combo([dev(b) for b in bs]))
         rep = plan.report
