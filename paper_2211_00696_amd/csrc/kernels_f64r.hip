@@ -78,7 +78,6 @@ __device__ __forceinline__ int frag(int rb, int kb, int q) {
 // rows row0 .. row0 + BM - 1 of E (row-major, K columns) into LDS
 template <class C>
 __device__ __forceinline__ void load_e(dv2* __restrict__ els, const double* __restrict__ E, int row0) {
-  static_assert(C::PAIRS % (4 * C::NT) == 0, "whole rounds of the copy");
 #pragma unroll 4
   for (int c = threadIdx.x; c < C::PAIRS; c += C::NT) {
     const int lane = c & 63;
@@ -372,6 +371,12 @@ int store_go(const TtmArgs& a, hipStream_t st) {
 
 template <int K>
 int store_shape(const TtmArgs& a, hipStream_t st, int cfg) {
+  // cfg 3: eight waves side by side (one row group, 128-column units);
+  // cfg 4: sixteen (256-column units, two steps of loads in flight)
+  using Wide = FC<Shape<K>::BM, K, 1, 8, Shape<K>::TN, (K / 32 >= 4 ? 4 : K / 32), 1>;
+  using Wider = FC<Shape<K>::BM, K, 1, 16, Shape<K>::TN, (K / 32 >= 2 ? 2 : 1), 1>;
+  if (cfg == 3) return store_go<Wide>(a, st);
+  if (cfg == 4) return store_go<Wider>(a, st);
   return cfg == 2 ? store_go<StoreC<K, 2>>(a, st) : store_go<StoreC<K, 1>>(a, st);
 }
 
@@ -386,11 +391,12 @@ int square_go(const TtmArgs& a, hipStream_t st) {
 
 // NV orders, NY = order0 + NV iterates (NY <= 4)
 // (WR = 2: eight waves in two row groups, two waves per SIMD, so one wave's
-// epilogue can run beside another's products)
-template <int K, int NV, int WR>
+// epilogue can run beside another's products; WC = 8: eight waves side by
+// side)
+template <int K, int NV, int WR, int WC = 4>
 int square_nv(const TtmArgs& a, hipStream_t st) {
   constexpr int S = NV * (K / 32);
-  using C = FC<Shape<K>::BM, K, WR, 4, Shape<K>::TN, (S % 4 == 0 ? 4 : (S % 2 == 0 ? 2 : 1)), NV>;
+  using C = FC<Shape<K>::BM, K, WR, WC, Shape<K>::TN, (S % 4 == 0 ? 4 : (S % 2 == 0 ? 2 : 1)), NV>;
   switch (a.order0 + NV) {
     case 1: return square_go<C, (NV <= 1 ? 1 : NV)>(a, st);
     case 2: return square_go<C, (NV <= 2 ? 2 : NV)>(a, st);
@@ -399,13 +405,13 @@ int square_nv(const TtmArgs& a, hipStream_t st) {
   }
 }
 
-template <int K, int WR>
+template <int K, int WR, int WC = 4>
 int square_shape(const TtmArgs& a, hipStream_t st) {
   switch (a.nbatch) {
-    case 1: return square_nv<K, 1, WR>(a, st);
-    case 2: return square_nv<K, 2, WR>(a, st);
-    case 3: return square_nv<K, 3, WR>(a, st);
-    default: return square_nv<K, 4, WR>(a, st);
+    case 1: return square_nv<K, 1, WR, WC>(a, st);
+    case 2: return square_nv<K, 2, WR, WC>(a, st);
+    case 3: return square_nv<K, 3, WR, WC>(a, st);
+    default: return square_nv<K, 4, WR, WC>(a, st);
   }
 }
 
@@ -422,13 +428,16 @@ bool f64r_shape(const TtmArgs& a) {
 
 }  // namespace
 
-int f64r_num_configs() { return 3; }
+int f64r_num_configs() { return 5; }
 
 // cfg: 0 = decline (the caller runs the tile kernels), 1 = four waves with
 // all row blocks each, 2 = eight waves in two row groups (both 64-column
-// units), -1 = default: cfg 2 at n = 256 with at least one unit per CU, else
-// decline.  Measured on gfx950 against the tile kernels (per launch):
-// n = 256, one vector 165 us against 173, three vectors 440 against 484;
+// units), 3 = eight waves in one row group (128-column units), 4 = sixteen
+// waves in one row group (256-column units), -1 = default: cfg 4 at n = 256
+// with at least one unit per CU, else decline.  Measured on gfx950 against
+// the tile kernels (per launch): n = 256, one vector 143-153 us (cfg 4),
+// 148-166 (cfg 3), 156-165 (cfg 2) against 162-169; three vectors 396-404
+// (cfg 4), 408-412 (cfg 3), 436-462 (cfg 2) against 447-472;
 // n = 128, one vector 21 us against 17 (the fixed cost of filling 128 KB of
 // LDS and the load ring is not repaid by 7 us of matrix work), eight vectors
 // 95 against 91; n = 64 slower still.  Returns hipErrorNotSupported for
@@ -438,7 +447,7 @@ int launch_ttm_store_f64r(const TtmArgs& a, void* stream, int cfg) {
   const int H = a.K == 256 ? 4 : 1;
   const long long units = (long long)a.nbatch * ((a.L + 63) / 64) * H;
   if (cfg < 0 && (a.K != 256 || units < cu_count())) return hipErrorNotSupported;
-  if (cfg < 0) cfg = 2;
+  if (cfg < 0) cfg = 4;
   hipStream_t st = (hipStream_t)stream;
   if (a.K == 256) return store_shape<256>(a, st, cfg);
   if (a.K == 128) return store_shape<128>(a, st, cfg);
@@ -446,10 +455,12 @@ int launch_ttm_store_f64r(const TtmArgs& a, void* stream, int cfg) {
 }
 
 // Squaring: cfg 1 = the resident kernel (four waves), 2 = eight waves in two
-// row groups, 0 = decline, -1 = default: cfg 2 at n = 256 with at least one
-// unit per CU, else decline.  Per 3D phi-action (seven three-order steps at
-// n = 256, five at n = 128): n = 256 3.40 ms (cfg 2) and 4.04 ms (cfg 1)
-// against 3.73 ms with the tile kernel; n = 128 0.23 / 0.24 against 0.21.
+// row groups, 3 = eight waves in one row group, 0 = decline, -1 = default:
+// cfg 3 at n = 256 with at least one unit per CU, else decline.  Per 3D
+// phi-action (seven three-order steps at n = 256, five at n = 128): n = 256
+// 3.26-3.29 ms (cfg 3), 3.40-3.46 (cfg 2) and 4.04 (cfg 1) against 3.73 ms
+// with the tile kernel; n = 128 0.23 / 0.24 (cfg 2 / 1) against 0.21, and
+// the one-group shapes spill registers there (all rows per wave).
 int launch_ttm_square_f64r(const TtmArgs& a, void* stream, int cfg) {
   if (cfg == 0 || !f64r_shape(a) || a.nbatch > 4 || a.es != 0 || a.order0 < 0 || a.order0 + a.nbatch > 4 ||
       a.yps % 2 != 0 || (a.nbatch > 1 && a.os % 2 != 0))
@@ -457,9 +468,14 @@ int launch_ttm_square_f64r(const TtmArgs& a, void* stream, int cfg) {
   if (cfg < 0) {
     const long long units = (long long)((a.L + 63) / 64) * (a.K == 256 ? 4 : 1);
     if (a.K != 256 || units < cu_count()) return hipErrorNotSupported;
-    cfg = 2;
+    cfg = 3;
   }
   hipStream_t st = (hipStream_t)stream;
+  if (cfg == 3) {
+    if (a.K == 256) return square_shape<256, 1, 8>(a, st);
+    if (a.K == 128) return square_shape<128, 1, 8>(a, st);
+    return square_shape<64, 1, 8>(a, st);
+  }
   if (cfg == 2) {
     if (a.K == 256) return square_shape<256, 2>(a, st);
     if (a.K == 128) return square_shape<128, 2>(a, st);
