@@ -507,9 +507,16 @@ phiq_status phiq_profile_enable(phiq_handle h, int on);
  * squaring combination); split bf16 kind 3 (plain) and 4 (squaring), where
  * cfg 0 is the general tile kernel and cfg >= 1 the kernels that keep the
  * 1D factor resident in LDS (n_d in {64, 128, 256}; other shapes always take
- * the general kernel).  cfg -1 restores the autotuned or default choice,
- * 0..count-1 forces that shape (tuning, testing; FP64 squaring shapes 7..
- * need p <= 4).  *count (nullable) = number of shapes of the kind. */
+ * the general kernel); FP64 with the factor resident in LDS, kind 5
+ * (plain), 6 (squaring), 7 (node sum): cfg 0 declines (the tile kernels of
+ * kinds 0..2 run), cfg >= 1 forces a resident shape for the launches it
+ * takes (n_d in {64, 128, 256}, FP64 in and out), -1 = default (kinds 5
+ * and 6 resident at n_d = 256 when the launch fills the GPU; kind 7 off:
+ * it measured slower than the tile kernel).  A forced shape of kinds 0..2
+ * also turns the resident kernels off for that kind.  cfg -1 restores the
+ * autotuned or default choice, 0..count-1 forces that shape (tuning,
+ * testing; FP64 squaring shapes 7.. need p <= 4).  *count (nullable) =
+ * number of shapes of the kind. */
 phiq_status phiq_tile_config(phiq_handle h, int kind, int cfg, int* count);
 
 /* ---------------------------------------------------------------------------

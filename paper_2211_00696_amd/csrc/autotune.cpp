@@ -50,10 +50,11 @@ phiq_status phiq_profile_stop(phiq_handle h, phiq_kernel_stat* stats, int max_st
 }
 
 phiq_status phiq_tile_config(phiq_handle h, int kind, int cfg, int* count) {
-  if (!h || kind < 0 || kind > 6) return PHIQ_ERR_INVALID_ARG;
+  if (!h || kind < 0 || kind > 7) return PHIQ_ERR_INVALID_ARG;
   const int nc = kind <= 2   ? ttm_num_configs(kind)
                  : kind == 3 ? bf16r_num_configs()
                  : kind == 4 ? bf16r_square_num_configs()
+                 : kind == 7 ? f64r_accum_num_configs()
                              : f64r_num_configs();
   if (count) *count = nc;
   if (cfg < -1 || cfg >= nc) return PHIQ_ERR_INVALID_ARG;

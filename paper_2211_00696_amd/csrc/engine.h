@@ -157,7 +157,7 @@ struct phiq_handle_s {
   std::vector<GraphEntry> graphs;
   std::vector<std::vector<long long>> seen;  // keys run once eagerly
   std::vector<TuneEntry> tune;  // fastest tile shape per launch shape (autotuner)
-  int force_cfg[7] = {-1, -1, -1, -1, -1, -1, -1};  // phiq_tile_config: one shape for every launch of a kind
+  int force_cfg[8] = {-1, -1, -1, -1, -1, -1, -1, -1};  // phiq_tile_config: one shape for every launch of a kind
   // adaptive Clenshaw-Curtis: the device decisions per level, their pinned
   // host copies and events, and the flag that guards the launches of a
   // speculative level (set only while such a level is enqueued)

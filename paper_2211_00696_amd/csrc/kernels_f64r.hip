@@ -310,6 +310,83 @@ __global__ __launch_bounds__(C::NT) void ttm_f64r_square_kernel(TtmArgs a) {
   });
 }
 
+// Node sum fused into the last mode product (Algorithm 1): for every unit
+// the block runs over the nbatch nodes b in turn, reloading factor b into
+// LDS at each node (the load ring keeps streaming X across the reload), and
+// keeps the NP running sums Y_q += 2^cexp coef[q][b] E_b X_b in registers.
+template <class C, int NP>
+__global__ __launch_bounds__(C::NT) void ttm_f64r_accum_kernel(TtmArgs a) {
+  __shared__ dv2 els[C::PAIRS];
+  if (a.stop && *a.stop) return;
+  static_assert(C::NV == 1 && C::KB % C::PF == 0, "one node per step group; the ring tiles a node");
+  const Work w = block_work<C>(a.M, a.L, 1);
+  if (w.u0 >= w.u1) return;
+  const double* X = (const double*)a.X;
+  const int S = a.nbatch * C::KB;  // steps per unit
+  Ring8 ring[C::PF][C::TN];
+#pragma unroll
+  for (int t = 0; t < C::PF; ++t) load_step<C>(X, a.xs, a.L, w, w.u0, t, true, ring[t]);
+  for (long long u = w.u0; u < w.u1; ++u) {
+    dacc y[NP][C::RB][C::TN];
+#pragma unroll
+    for (int q = 0; q < NP; ++q)
+#pragma unroll
+      for (int rb = 0; rb < C::RB; ++rb)
+#pragma unroll
+        for (int c = 0; c < C::TN; ++c) y[q][rb][c] = (dacc){0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < a.nbatch; ++b) {
+      __syncthreads();  // every wave is done with the previous node's factor
+      load_e<C>(els, a.E + (long long)b * a.es, w.h * C::BM);
+      __syncthreads();
+      dacc acc[C::RB][C::TN];
+#pragma unroll
+      for (int rb = 0; rb < C::RB; ++rb)
+#pragma unroll
+        for (int c = 0; c < C::TN; ++c) acc[rb][c] = (dacc){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kb = 0; kb < C::KB; ++kb) {
+        asm volatile("" ::: "memory");
+        const int slot = kb % C::PF;  // = (b KB + kb) % PF
+        Ring8 cur[C::TN];
+#pragma unroll
+        for (int c = 0; c < C::TN; ++c) cur[c] = ring[slot][c];
+        const int tn = b * C::KB + kb + C::PF;
+        if (tn < S)
+          load_step<C>(X, a.xs, a.L, w, u, tn, true, ring[slot]);
+        else if (u + 1 < w.u1)
+          load_step<C>(X, a.xs, a.L, w, u + 1, tn - S, true, ring[slot]);
+        mma_step<C>(els, kb, cur, acc);
+      }
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        const double wq = ldexp(a.coef[q * a.ldcoef + b], a.cexp);
+#pragma unroll
+        for (int rb = 0; rb < C::RB; ++rb)
+#pragma unroll
+          for (int c = 0; c < C::TN; ++c) y[q][rb][c] += wq * acc[rb][c];
+      }
+    }
+    const int ct = (int)(u % w.CT);
+    const long long L = opaque_len(a.L);
+#pragma unroll
+    for (int c = 0; c < C::TN; ++c) {
+      const int col = out_col<C>(ct, c);
+      if (col >= a.L) continue;
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        double* Y = a.Y + q * a.ys;
+#pragma unroll
+        for (int rb = 0; rb < C::RB; ++rb)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const long long idx = out_row<C>(w, rb, e) * L + col;
+            Y[idx] = a.yacc ? Y[idx] + y[q][rb][c][e] : y[q][rb][c][e];
+          }
+      }
+    }
+  }
+}
+
 inline int cu_count() {
   static int n = 0;
   if (!n) {
@@ -426,9 +503,43 @@ bool f64r_shape(const TtmArgs& a) {
   return true;
 }
 
+template <int K, int NP>
+int accum_go(const TtmArgs& a, hipStream_t st) {
+  using C = FC<Shape<K>::BM, K, 1, 8, Shape<K>::TN, (K / 32 >= 2 ? 2 : 1), 1>;
+  auto k = ttm_f64r_accum_kernel<C, NP>;
+  const long long units = (a.L + C::COLS - 1) / C::COLS;
+  const int g = grid_of<C>(k, a.M, units);
+  PHIQ_LAUNCH_F(k, dim3(g), dim3(C::NT), 0, st, a);
+  return hipGetLastError();
+}
+
+template <int K>
+int accum_shape(const TtmArgs& a, hipStream_t st) {
+  switch (a.np) {
+    case 1: return accum_go<K, 1>(a, st);
+    case 2: return accum_go<K, 2>(a, st);
+    case 3: return accum_go<K, 3>(a, st);
+    default: return accum_go<K, 4>(a, st);
+  }
+}
+
 }  // namespace
 
 int f64r_num_configs() { return 5; }
+int f64r_accum_num_configs() { return 2; }
+
+// Node sum: cfg 1 = the resident kernel (eight waves side by side), 0 or -1
+// (default) = decline.  At n = 256 (eight nodes, three running sums, one
+// factor reload per node and unit) it measured 1.38-1.39 ms per 3D
+// phi-action against 1.35-1.36 ms for the tile kernel; at n = 128 its
+// running sums spill.
+int launch_ttm_accum_f64r(const TtmArgs& a, void* stream, int cfg) {
+  if (cfg <= 0 || !f64r_shape(a) || a.np < 1 || a.np > 4) return hipErrorNotSupported;
+  hipStream_t st = (hipStream_t)stream;
+  if (a.K == 256) return accum_shape<256>(a, st);
+  if (a.K == 128) return accum_shape<128>(a, st);
+  return accum_shape<64>(a, st);
+}
 
 // cfg: 0 = decline (the caller runs the tile kernels), 1 = four waves with
 // all row blocks each, 2 = eight waves in two row groups (both 64-column

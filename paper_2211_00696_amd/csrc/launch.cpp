@@ -87,13 +87,16 @@ phiq_status L_ttm(phiq_handle h, int cls, const TtmArgs& a0, phiq_precision prec
             : (prec != PHIQ_PREC_FP64) ? -1
                                        : (h->force_cfg[kind] >= 0 ? h->force_cfg[kind] : tuned_cfg(h, kind, a));
   if (prec == PHIQ_PREC_FP64 && cfg < 0) cfg = fallback_cfg(kind, a);
-  // FP64 plain and squaring products: the resident-factor kernels first
-  // (kinds 5 / 6 of phiq_tile_config), unless a tile shape is forced
-  const bool try_r = prec == PHIQ_PREC_FP64 && kind != 1 && h->force_cfg[kind] < 0;
-  const int rcfg = h->force_cfg[kind == 0 ? 5 : 6];
+  // FP64 products: the resident-factor kernels first (kinds 5 / 6 / 7 of
+  // phiq_tile_config for plain / squaring / node-sum products), unless a
+  // tile shape is forced
+  const bool try_r = prec == PHIQ_PREC_FP64 && h->force_cfg[kind] < 0;
+  const int rcfg = h->force_cfg[kind == 0 ? 5 : (kind == 2 ? 6 : 7)];
   return prof_launch(h, st, cls, fl, by, [&] {
     if (try_r) {
-      const int r = kind == 0 ? launch_ttm_store_f64r(a, st, rcfg) : launch_ttm_square_f64r(a, st, rcfg);
+      const int r = kind == 0   ? launch_ttm_store_f64r(a, st, rcfg)
+                    : kind == 2 ? launch_ttm_square_f64r(a, st, rcfg)
+                                : launch_ttm_accum_f64r(a, st, rcfg);
       if (r != hipErrorNotSupported) return r;
     }
     return launch_kind(kind, a, prec, st, cfg);

@@ -241,7 +241,9 @@ int launch_ttm_store_bf16r(const TtmArgs& a, void* stream, int cfg);
 // 256}; cfg 0 declines, -1 = default; hipErrorNotSupported when declined
 int launch_ttm_store_f64r(const TtmArgs& a, void* stream, int cfg);
 int launch_ttm_square_f64r(const TtmArgs& a, void* stream, int cfg);
+int launch_ttm_accum_f64r(const TtmArgs& a, void* stream, int cfg);
 int f64r_num_configs();
+int f64r_accum_num_configs();
 int launch_ttm_square_bf16r(const TtmArgs& a, void* stream, int cfg);
 
 // Products along axes 2 and 1 of nbatch tensors n0 x kSlabN x kSlabN in one

@@ -52,18 +52,18 @@ def rel(a, b):
 
 
 class forced:
-    """Force the resident kernels' shape (kinds 5 and 6) for a block of launches."""
+    """Force the resident kernels' shape (kinds 5, 6 and 7) for a block of launches."""
 
-    def __init__(self, h, store, square):
-        self.h, self.store, self.square = h, store, square
+    def __init__(self, h, store, square, accum=-1):
+        self.h, self.cfg = h, {5: store, 6: square, 7: accum}
 
     def __enter__(self):
-        self.h.tile_config(5, self.store)
-        self.h.tile_config(6, self.square)
+        for k, c in self.cfg.items():
+            self.h.tile_config(k, c)
 
     def __exit__(self, *exc):
-        self.h.tile_config(5, -1)
-        self.h.tile_config(6, -1)
+        for k in self.cfg:
+            self.h.tile_config(k, -1)
 
 
 SIZES = [(128, 128, 128), (64, 64, 64), (256, 64, 30), (128, 37, 6), (64, 256), (256, 256, 4), (6, 128, 64)]
@@ -96,13 +96,14 @@ def adv128():
     return pr, ref
 
 
-@pytest.mark.parametrize("store,square", [(1, 1), (2, 1), (2, 2), (3, 3), (4, 3), (1, 0), (0, 2), (-1, -1)])
-def test_f64r_phi_action_n128_vs_oracle(h, adv128, store, square):
+@pytest.mark.parametrize("store,square,accum", [(1, 1, 1), (2, 1, 0), (2, 2, 1), (3, 3, 1), (4, 3, 1), (1, 0, 0),
+                                                (0, 2, 0), (0, 0, 1), (-1, -1, -1)])
+def test_f64r_phi_action_n128_vs_oracle(h, adv128, store, square, accum):
     """3D n = 128 phi_0..phi_3 (seed 0, tol 1e-8) with the resident kernels
-    forced on the plain products and/or the squaring products (0: the tile
+    forced on the plain, squaring and/or node-sum products (0: the tile
     kernels; -1: the default choice)."""
     pr, ref = adv128
-    with forced(h, store, square):
+    with forced(h, store, square, accum):
         out, rep = h.action(pr["mats"], pr["t"], 3, dev(pr["v"]), tol=1e-8)
         o = host(out)
     errs = [rel(o[k], ref[k]) for k in range(4)]
@@ -110,11 +111,13 @@ def test_f64r_phi_action_n128_vs_oracle(h, adv128, store, square):
     assert max(errs) < 1e-8, errs
 
 
-@pytest.mark.parametrize("cfg", [1, 2, 3])
+@pytest.mark.parametrize("cfg,grp", [(1, 0), (2, 0), (3, 0), (1, 1), (3, 1)])
 @pytest.mark.parametrize("sizes,p", [([64, 8], 3), ([128, 6], 1), ([64, 4, 5], 2), ([128, 9], 4)])
-def test_f64r_combination_vs_definition(h, sizes, p, cfg):
-    """sum_j phi_j(-tA) b_j with both kinds forced: the last squaring step
-    forms y_p alone (order offset p - 1) and adds it to phi_0 b_0."""
+def test_f64r_combination_vs_definition(h, sizes, p, cfg, grp):
+    """sum_j phi_j(-tA) b_j with the kinds forced: the last squaring step
+    forms y_p alone (order offset p - 1) and adds it to phi_0 b_0; with
+    rhs_per_launch = 1 every b_j has its own node sum (scaled weights, added
+    into the running y), on the resident node-sum kernel."""
     rng = np.random.default_rng(p)
     mats = []
     for n in sizes:
@@ -123,9 +126,9 @@ def test_f64r_combination_vs_definition(h, sizes, p, cfg):
     N = int(np.prod(sizes))
     bs = [rng.standard_normal(N) for _ in range(p + 1)]
     t = 0.01
-    print("f64r combination", sizes, p, cfg, flush=True)
-    with forced(h, cfg, cfg):
-        plan = h.plan(mats, t, p, tol=1e-12)
+    print("f64r combination", sizes, p, cfg, grp, flush=True)
+    with forced(h, cfg, cfg, 1):
+        plan = h.plan(mats, t, p, tol=1e-12, rhs_per_launch=grp)
         got = host(plan.execute_combo([dev(b) for b in bs]))
         rep = plan.report
         plan.close()
