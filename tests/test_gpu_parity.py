@@ -308,3 +308,34 @@ def test_every_tile_shape_vs_oracle(h, kind):
                 assert e < 1e-9, (kind, cfg, pr["n"], e)
     finally:
         h.tile_config(kind, -1)
+
+
+# --------------------------------------------------------------------------
+# phi_0 from the l-th square of exp(2^-l (-tA^d)) at high Peclet number
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n,a,b,t,lmin", [(12, 1e-3, 20.0, 0.1, 8), (12, 5e-3, 5.0, 0.2, 7), (64, 5e-3, 5.0, 0.2, 9),
+                                          (64, 1e-3, 20.0, 0.1, 10)])
+def test_phi0_high_peclet_large_l_vs_definition(h, n, a, b, t, lmin):
+    """Non-normal 1D factors (upwind advection with little diffusion: cell
+    Peclet number b h / (2 a) from 8 to 770) and many squaring steps: phi_0 is
+    the l-th square of exp(2^{-l}(-tA^d)) (reading R13), and every squaring
+    step carries the rounding of the previous one through a non-normal
+    factor.  The exponentials are small here (max entry 1e-2 .. 2e-17: the
+    flow leaves the domain), so this is a relative-accuracy test of the
+    chain.  n = 12: every phi_k against the augmented-matrix definition;
+    n = 64: phi_0 against the Kronecker product of scipy's expm(-tA^d)."""
+    rng = np.random.default_rng(n + int(b))
+    mats = [I.adv_diff_1d(n, a, b * (1.0 + 0.1 * d)) for d in range(3)]
+    v = rng.standard_normal(n ** 3)
+    print("high Peclet", n, a, b, t, flush=True)
+    out, rep = h.action(mats, t, 1, dev(v), tol=1e-10)
+    o = host(out)
+    assert rep["l"] >= lmin, rep["l"]
+    if n <= 16:
+        ref = X.phi_dense_aug(mats, t, v, 1)
+        errs = rel_per_k(o, ref)
+    else:
+        E = [scipy.linalg.expm(-t * A) for A in mats]
+        errs = [rel(o[0], X.apply_kron(E, v, [n] * 3))]
+    print("l=%d m=%d" % (rep["l"], rep["m"]), errs, flush=True)
+    assert max(errs) < 1e-10, errs
