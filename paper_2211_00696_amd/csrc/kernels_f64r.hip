@@ -452,8 +452,12 @@ int store_shape(const TtmArgs& a, hipStream_t st, int cfg) {
   // cfg 4: sixteen (256-column units, two steps of loads in flight)
   using Wide = FC<Shape<K>::BM, K, 1, 8, Shape<K>::TN, (K / 32 >= 4 ? 4 : K / 32), 1>;
   using Wider = FC<Shape<K>::BM, K, 1, 16, Shape<K>::TN, (K / 32 >= 2 ? 2 : 1), 1>;
+  // cfg 5: 64 rows per block (two row parts at n = 128, 64 KB of LDS: two
+  // blocks per CU), eight waves side by side
+  using Half = FC<64, K, 1, 8, 1, (K / 32 >= 4 ? 4 : K / 32), 1>;
   if (cfg == 3) return store_go<Wide>(a, st);
   if (cfg == 4) return store_go<Wider>(a, st);
+  if (cfg == 5) return store_go<Half>(a, st);
   return cfg == 2 ? store_go<StoreC<K, 2>>(a, st) : store_go<StoreC<K, 1>>(a, st);
 }
 
@@ -470,10 +474,10 @@ int square_go(const TtmArgs& a, hipStream_t st) {
 // (WR = 2: eight waves in two row groups, two waves per SIMD, so one wave's
 // epilogue can run beside another's products; WC = 8: eight waves side by
 // side)
-template <int K, int NV, int WR, int WC = 4>
+template <int K, int NV, int WR, int WC = 4, int BM = Shape<K>::BM>
 int square_nv(const TtmArgs& a, hipStream_t st) {
   constexpr int S = NV * (K / 32);
-  using C = FC<Shape<K>::BM, K, WR, WC, Shape<K>::TN, (S % 4 == 0 ? 4 : (S % 2 == 0 ? 2 : 1)), NV>;
+  using C = FC<BM, K, WR, WC, Shape<K>::TN, (S % 4 == 0 ? 4 : (S % 2 == 0 ? 2 : 1)), NV>;
   switch (a.order0 + NV) {
     case 1: return square_go<C, (NV <= 1 ? 1 : NV)>(a, st);
     case 2: return square_go<C, (NV <= 2 ? 2 : NV)>(a, st);
@@ -482,13 +486,13 @@ int square_nv(const TtmArgs& a, hipStream_t st) {
   }
 }
 
-template <int K, int WR, int WC = 4>
+template <int K, int WR, int WC = 4, int BM = Shape<K>::BM>
 int square_shape(const TtmArgs& a, hipStream_t st) {
   switch (a.nbatch) {
-    case 1: return square_nv<K, 1, WR, WC>(a, st);
-    case 2: return square_nv<K, 2, WR, WC>(a, st);
-    case 3: return square_nv<K, 3, WR, WC>(a, st);
-    default: return square_nv<K, 4, WR, WC>(a, st);
+    case 1: return square_nv<K, 1, WR, WC, BM>(a, st);
+    case 2: return square_nv<K, 2, WR, WC, BM>(a, st);
+    case 3: return square_nv<K, 3, WR, WC, BM>(a, st);
+    default: return square_nv<K, 4, WR, WC, BM>(a, st);
   }
 }
 
@@ -525,7 +529,7 @@ int accum_shape(const TtmArgs& a, hipStream_t st) {
 
 }  // namespace
 
-int f64r_num_configs() { return 5; }
+int f64r_num_configs() { return 6; }
 int f64r_accum_num_configs() { return 2; }
 
 // Node sum: cfg 1 = the resident kernel (eight waves side by side), 0 or -1
@@ -544,8 +548,9 @@ int launch_ttm_accum_f64r(const TtmArgs& a, void* stream, int cfg) {
 // cfg: 0 = decline (the caller runs the tile kernels), 1 = four waves with
 // all row blocks each, 2 = eight waves in two row groups (both 64-column
 // units), 3 = eight waves in one row group (128-column units), 4 = sixteen
-// waves in one row group (256-column units), -1 = default: cfg 4 at n = 256
-// with at least one unit per CU, else decline.  Measured on gfx950 against
+// waves in one row group (256-column units), 5 = eight waves on 64-row
+// blocks, -1 = default: cfg 4 at n = 256 with at least one unit per CU, cfg
+// 5 at n = 128 for batches of eight or more, else decline.  Measured on gfx950 against
 // the tile kernels (per launch): n = 256, one vector 143-153 us (cfg 4),
 // 148-166 (cfg 3), 156-165 (cfg 2) against 162-169; three vectors 396-404
 // (cfg 4), 408-412 (cfg 3), 436-462 (cfg 2) against 447-472;
@@ -557,8 +562,17 @@ int launch_ttm_store_f64r(const TtmArgs& a, void* stream, int cfg) {
   if (cfg == 0 || !f64r_shape(a)) return hipErrorNotSupported;
   const int H = a.K == 256 ? 4 : 1;
   const long long units = (long long)a.nbatch * ((a.L + 63) / 64) * H;
-  if (cfg < 0 && (a.K != 256 || units < cu_count())) return hipErrorNotSupported;
-  if (cfg < 0) cfg = 4;
+  if (cfg < 0) {
+    // n = 256: sixteen waves; n = 128 with eight or more vectors (a node
+    // batch): 64 rows per block, 106-110 us against 113-117 us for ten
+    // vectors (one to three vectors stay faster on the tile kernel)
+    if (a.K == 256 && units >= cu_count())
+      cfg = 4;
+    else if (a.K == 128 && a.nbatch >= 8)
+      cfg = 5;
+    else
+      return hipErrorNotSupported;
+  }
   hipStream_t st = (hipStream_t)stream;
   if (a.K == 256) return store_shape<256>(a, st, cfg);
   if (a.K == 128) return store_shape<128>(a, st, cfg);
@@ -582,6 +596,11 @@ int launch_ttm_square_f64r(const TtmArgs& a, void* stream, int cfg) {
     cfg = 3;
   }
   hipStream_t st = (hipStream_t)stream;
+  if (cfg == 4) {  // 64 rows per block, eight waves side by side
+    if (a.K == 256) return square_shape<256, 1, 8, 64>(a, st);
+    if (a.K == 128) return square_shape<128, 1, 8, 64>(a, st);
+    return square_shape<64, 1, 8, 64>(a, st);
+  }
   if (cfg == 3) {
     if (a.K == 256) return square_shape<256, 1, 8>(a, st);
     if (a.K == 128) return square_shape<128, 1, 8>(a, st);

@@ -149,8 +149,11 @@ def test_slab_repeat_bitwise(h):
 
 def test_slab_modes(h):
     """slab_products = 1: the phi_0 chain takes the slab path, the batched
-    chains do not, so phi_1.. agree bitwise with 0 and phi_0 with 2; the
-    default is 0."""
+    chains do not, so phi_1.. agree bitwise with 0 and phi_0 with 2 up to the
+    order of the k sums (the per-axis products of the node batch, which
+    carries phi_0 as slot m, take the resident-factor kernel at n = 128 with
+    eight or more vectors, whose k order differs from the slab kernel's);
+    the default is 0."""
     sizes = [128, 128, 128]
     mats = ops(sizes, 25)
     v = torch.from_numpy(np.random.default_rng(25).standard_normal(128 ** 3)).cuda()
@@ -160,5 +163,6 @@ def test_slab_modes(h):
     dflt, _ = h.action(mats, 1e-3, 3, v, tol=1e-8)
     torch.cuda.synchronize()
     assert torch.equal(one[1:], zero[1:])
-    assert torch.equal(one[0], two[0])
+    e0 = float((one[0] - two[0]).abs().max() / two[0].abs().max())
+    assert e0 < 1e-13, e0
     assert torch.equal(dflt, zero)
