@@ -249,10 +249,15 @@ phiq_status execute_cc(phiq_plan P, const double* v, double* out, hipStream_t st
   int level = 1;
   bool converged = false;
   for (;; ++level) {
+    const size_t rec0 = h->prof.recs.size();
     if (level < cap) PHIQ_TRY(run_level(level + 1, &ctl[level].stop));
+    const size_t rec1 = h->prof.recs.size();
     PHIQ_HIP(hipEventSynchronize(h->cc_ev[level]));
     err = h->cc_ctl_host[level].err;
     if (h->cc_ctl_host[level].stop) {
+      // the speculative level's launches returned at once: drop their
+      // profile records, which would count work that did not run
+      h->prof.recs.erase(h->prof.recs.begin() + (long)rec0, h->prof.recs.begin() + (long)rec1);
       converged = true;
       break;
     }

@@ -92,3 +92,26 @@ def test_enable_needs_an_open_profile(h):
     h.profile_stop()
     with pytest.raises(PhiqError):
         h.profile_enable(False)
+
+
+def test_cc_records_only_levels_that_ran(h):
+    """Adaptive Clenshaw-Curtis enqueues one level past the last doubling test
+    behind a device flag; after convergence its launches return at once and
+    their records are dropped, so the recorded node-vector products are
+    exactly the levels that ran: 7, 6, 12, ... new nodes per level (nested
+    rules of 7, 13, 25, ... points, Algorithm 2) times D products each, plus
+    phi_0's chain and the squaring fronts."""
+    pr = I.problem("advdiff3d", seed=3, n=48)
+    v = torch.from_numpy(pr["v"]).cuda()
+    h.profile_start(["ttm_store"])
+    _, rep = h.action(pr["mats"], pr["t"], 3, v, tol=1e-8, rule="cc")
+    st = h.profile_stop()["ttm_store"]
+    n, N = 48, 48 ** 3
+    levels = rep["cc_doublings"] + 1
+    nodes = 7 + sum(3 * 2 ** (k - 1) * 2 for k in range(1, levels))  # new nodes per level: 6, 12, 24, ...
+    assert nodes == rep["m"], (nodes, rep["m"])
+    # node chains: 3 products per node vector; squaring: 2 front products of p vectors per step; phi_0: 3
+    want_vectors = 3 * nodes + rep["l"] * 2 * 3 + 3
+    got_vectors = st["flops"] / (2.0 * n * N)
+    print(rep["l"], rep["m"], rep["cc_doublings"], got_vectors, want_vectors, flush=True)
+    assert abs(got_vectors - want_vectors) < 1e-6, (got_vectors, want_vectors)
