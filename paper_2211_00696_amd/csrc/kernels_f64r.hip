@@ -455,9 +455,12 @@ int store_shape(const TtmArgs& a, hipStream_t st, int cfg) {
   // cfg 5: 64 rows per block (two row parts at n = 128, 64 KB of LDS: two
   // blocks per CU), eight waves side by side
   using Half = FC<64, K, 1, 8, 1, (K / 32 >= 4 ? 4 : K / 32), 1>;
+  // cfg 6: 64 rows per block, sixteen waves side by side
+  using HalfWide = FC<64, K, 1, 16, 1, (K / 32 >= 2 ? 2 : 1), 1>;
   if (cfg == 3) return store_go<Wide>(a, st);
   if (cfg == 4) return store_go<Wider>(a, st);
   if (cfg == 5) return store_go<Half>(a, st);
+  if (cfg == 6) return store_go<HalfWide>(a, st);
   return cfg == 2 ? store_go<StoreC<K, 2>>(a, st) : store_go<StoreC<K, 1>>(a, st);
 }
 
@@ -529,7 +532,7 @@ int accum_shape(const TtmArgs& a, hipStream_t st) {
 
 }  // namespace
 
-int f64r_num_configs() { return 6; }
+int f64r_num_configs() { return 7; }
 int f64r_accum_num_configs() { return 2; }
 
 // Node sum: cfg 1 = the resident kernel (eight waves side by side), 0 or -1
@@ -549,8 +552,9 @@ int launch_ttm_accum_f64r(const TtmArgs& a, void* stream, int cfg) {
 // all row blocks each, 2 = eight waves in two row groups (both 64-column
 // units), 3 = eight waves in one row group (128-column units), 4 = sixteen
 // waves in one row group (256-column units), 5 = eight waves on 64-row
-// blocks, -1 = default: cfg 4 at n = 256 with at least one unit per CU, cfg
-// 5 at n = 128 for batches of eight or more, else decline.  Measured on gfx950 against
+// blocks, 6 = sixteen waves on 64-row blocks, -1 = default: cfg 4 at n = 256
+// with at least one unit per CU, cfg 6 at n = 128 for batches of eight or
+// more, else decline.  Measured on gfx950 against
 // the tile kernels (per launch): n = 256, one vector 143-153 us (cfg 4),
 // 148-166 (cfg 3), 156-165 (cfg 2) against 162-169; three vectors 396-404
 // (cfg 4), 408-412 (cfg 3), 436-462 (cfg 2) against 447-472;
@@ -564,12 +568,13 @@ int launch_ttm_store_f64r(const TtmArgs& a, void* stream, int cfg) {
   const long long units = (long long)a.nbatch * ((a.L + 63) / 64) * H;
   if (cfg < 0) {
     // n = 256: sixteen waves; n = 128 with eight or more vectors (a node
-    // batch): 64 rows per block, 106-110 us against 113-117 us for ten
-    // vectors (one to three vectors stay faster on the tile kernel)
+    // batch): 64 rows per block, sixteen waves, 100-107 us against 114-117
+    // us for ten vectors (eight waves: 106-116 us; one to three vectors
+    // stay faster on the tile kernel)
     if (a.K == 256 && units >= cu_count())
       cfg = 4;
     else if (a.K == 128 && a.nbatch >= 8)
-      cfg = 5;
+      cfg = 6;
     else
       return hipErrorNotSupported;
   }

@@ -4,9 +4,10 @@ The plain product (phiq_tile_config kind 5) and the product fused with the
 modified squaring of eq. squaring (kind 6) for n_d in {64, 128, 256},
 forced on every launch (cfg 1: four waves with all row blocks, 2: eight
 waves in two row groups, 3: eight waves in one row group, 4 (plain):
-sixteen, 5 (plain) / 4 (squaring): eight waves on 64-row blocks; the default
-takes cfg 4 / 3 for n = 256 launches with at least one unit per CU and cfg 5
-for n = 128 node batches of eight or more), through the C ABI:
+sixteen, 5 (plain) / 4 (squaring): eight waves on 64-row blocks, 6 (plain):
+sixteen waves on 64-row blocks; the default takes cfg 4 / 3 for n = 256
+launches with at least one unit per CU and cfg 6 for n = 128 node batches
+of eight or more), through the C ABI:
 
   * Kronecker products (F^0 (x) F^1 (x) F^2) x against the oracle's
     apply_kron (numpy, FP64) and against the tile kernels (cfg 0): the same
@@ -71,7 +72,7 @@ SIZES = [(128, 128, 128), (64, 64, 64), (256, 64, 30), (128, 37, 6), (64, 256), 
 
 
 @pytest.mark.parametrize("sizes", SIZES)
-@pytest.mark.parametrize("cfg", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("cfg", [1, 2, 3, 4, 5, 6])
 def test_f64r_kron_apply_vs_oracle_and_tiles(h, sizes, cfg):
     rng = np.random.default_rng(sum(sizes) + cfg)
     F = [rng.standard_normal((n, n)) / np.sqrt(n) for n in sizes]
@@ -97,7 +98,7 @@ def adv128():
     return pr, ref
 
 
-@pytest.mark.parametrize("store,square,accum", [(1, 1, 1), (2, 1, 0), (2, 2, 1), (3, 3, 1), (4, 3, 1), (5, 4, 0), (1, 0, 0),
+@pytest.mark.parametrize("store,square,accum", [(1, 1, 1), (2, 1, 0), (2, 2, 1), (3, 3, 1), (4, 3, 1), (5, 4, 0), (6, 0, 0), (1, 0, 0),
                                                 (0, 2, 0), (0, 0, 1), (-1, -1, -1)])
 def test_f64r_phi_action_n128_vs_oracle(h, adv128, store, square, accum):
     """3D n = 128 phi_0..phi_3 (seed 0, tol 1e-8) with the resident kernels
