@@ -76,7 +76,7 @@ typedef enum {
 } phiq_precision;
 
 /* Choice of (l, m) for the Gauss rule. */
-typedef enum { PHIQ_SEL_PAPER = 0, PHIQ_SEL_MLP = 1 } phiq_selector;
+typedef enum { PHIQ_SEL_PAPER = 0, PHIQ_SEL_MLP = 1, PHIQ_SEL_MLP_EMPIRICAL = 2 } phiq_selector;
 
 /* The Kronecker-sum operator: D = dim factors, HOST pointers. */
 typedef struct {
@@ -100,10 +100,20 @@ typedef struct {
                             /* ROCm 7 a replay of the ~45-node graph costs more     */
                             /* than the eager launches it replaces.                 */
   int selector;             /* Gauss (l, m) choice when l and m are not forced:     */
-                            /* PHIQ_SEL_PAPER (default, Algorithm setup_quadrature) */
-                            /* or PHIQ_SEL_MLP (the handle's network, see           */
-                            /* phiq_selector_set; the bound judges its choice and   */
-                            /* Algorithm setup_quadrature is the fallback)          */
+                            /* PHIQ_SEL_PAPER (default, Algorithm setup_quadrature),*/
+                            /* PHIQ_SEL_MLP (the handle's network, certified: its   */
+                            /* outputs are l and m, the bound of Thm 3.2 judges the */
+                            /* pair; see phiq_selector_set) or                      */
+                            /* PHIQ_SEL_MLP_EMPIRICAL (the network's outputs are l  */
+                            /* and log10 rho, rho in [0.1, 1]: m is Algorithm       */
+                            /* quadnodes at the norm rho ||tA|| and scaling l, rho  */
+                            /* learned from measured errors of the method's own     */
+                            /* sweeps, so the bound at ||tA|| does not certify the  */
+                            /* result; only for tol >= 1e-10, below which           */
+                            /* Algorithm setup_quadrature chooses).  A network      */
+                            /* choice costing over 1.5x Algorithm                   */
+                            /* setup_quadrature's in chain count (m + l p) is       */
+                            /* rejected in both modes.                              */
   int slab_products;        /* FP64, three axes with n_1 = n_2 = 128: the products  */
                             /* along axes 2 and 1 in one pass per 128 x 128 slab    */
                             /* (the same sums, the k-loops associated otherwise)    */
@@ -119,10 +129,7 @@ typedef struct {
   double selector_slack;    /* PHIQ_SEL_MLP: decades by which the a priori bound at */
                             /* the network's (l, m) may exceed tol (0..12).  0, the */
                             /* default, is the certified mode: the bound must meet  */
-                            /* tol, as in Algorithm setup_quadrature.  A network    */
-                            /* trained on measured errors (empirical mode) is used  */
-                            /* with the slack calibrated on its own sweep: the      */
-                            /* largest bound excess its training labels needed      */
+                            /* tol, as in Algorithm setup_quadrature                */
   int batch_persistent;     /* phiq_action_batched: 1 = the whole batch in one      */
                             /* persistent launch (tiles handed out in dependency    */
                             /* order, workgroups waiting on per-group completion    */
@@ -171,7 +178,8 @@ typedef struct {
   size_t workspace_bytes; /* device bytes held by the handle after the call     */
   int selector;        /* how (l, m) was chosen: 0 Algorithm setup_quadrature   */
                        /* (or forced), 1 network, 2 network with m raised to    */
-                       /* what the bound needs, 3 network rejected (fallback)   */
+                       /* what the bound needs, 3 network rejected (fallback),  */
+                       /* 4 empirical-mode network (PHIQ_SEL_MLP_EMPIRICAL)     */
   double precision_floor; /* rounding floor of the mode products' precision     */
                        /* (PHIQ_FLOOR_FP32 / _BF16X3; 0 for FP64 and int8       */
                        /* digits, whose digit count follows tol)                */
@@ -421,7 +429,8 @@ phiq_status phiq_exprk(phiq_handle h, const phiq_kron_op* op, int method, double
  * layers in FP32.  Parameters, one vector of PHIQ_MLP_NPARAM floats: W1
  * (64 x 8, row-major), b1 (64), W2 (64 x 64), b2 (64), W3 (2 x 64), b3 (2).
  * Inputs (8): log10 t||A^d||_inf for axes 0..2 (-3 for an absent axis),
- * max_d n_d / 256, dim, p, log10 t, log10 tol; outputs: l / 8, m / 16.
+ * max_d n_d / 256, dim, p, log10 t, log10 tol; outputs: l / 8 and m / 16
+ * (PHIQ_SEL_MLP), or l / 8 and log10 rho (PHIQ_SEL_MLP_EMPIRICAL).
  * Loss: mean of (y - target)^2 over the B x 2 outputs.
  * ------------------------------------------------------------------------ */
 #define PHIQ_MLP_NPARAM 4866

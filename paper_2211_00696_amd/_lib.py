@@ -23,7 +23,7 @@ RULE = {"gauss": 1, "cc": 2}
 PROFILE_CLASSES = ["ttm_store", "ttm_accum", "ttm_square", "gemm", "taylor", "scale", "node_sum", "absdiff", "slice",
                    "ttm_slab"]
 PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2, "int8": 3}
-SELECTOR = {"paper": 0, "mlp": 1}
+SELECTOR = {"paper": 0, "mlp": 1, "mlp-empirical": 2}
 
 # Every symbol include/phiq.h declares.
 EXPORTS = [

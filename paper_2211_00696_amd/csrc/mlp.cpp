@@ -49,9 +49,10 @@ void mlp_predict_host(const float* w, const float x[kMlpIn], float y[kMlpOut]) {
   }
 }
 
-bool mlp_choose(const float* w, const phiq_kron_op* op, const double* norms, double t, int p, double tol,
-                double slack, double alpha, int l5, int n5, int* l, int* n, int* used) {
-  float x[kMlpIn];
+namespace {
+
+// The network's 8 inputs for this problem.
+void mlp_features(const phiq_kron_op* op, const double* norms, double t, int p, double tol, float x[kMlpIn]) {
   int nmax = 1;
   for (int d = 0; d < op->dim; ++d) nmax = std::max(nmax, op->n[d]);
   for (int d = 0; d < 3; ++d) x[d] = (d < op->dim) ? (float)std::log10(std::max(norms[d], 1e-300)) : -3.0f;
@@ -60,6 +61,14 @@ bool mlp_choose(const float* w, const phiq_kron_op* op, const double* norms, dou
   x[5] = (float)p;
   x[6] = (float)std::log10(std::fabs(t));
   x[7] = (float)std::log10(tol);
+}
+
+}  // namespace
+
+bool mlp_choose(const float* w, const phiq_kron_op* op, const double* norms, double t, int p, double tol,
+                double slack, double alpha, int l5, int n5, int* l, int* n, int* used) {
+  float x[kMlpIn];
+  mlp_features(op, norms, t, p, tol, x);
   float y[kMlpOut];
   mlp_predict_host(w, x, y);
   if (!std::isfinite(y[0]) || !std::isfinite(y[1])) {
@@ -88,6 +97,37 @@ bool mlp_choose(const float* w, const phiq_kron_op* op, const double* norms, dou
   }
   *l = lp;
   *n = m - 1;
+  return true;
+}
+
+bool mlp_choose_empirical(const float* w, const phiq_kron_op* op, const double* norms, double t, int p,
+                          double tol, double alpha, int l5, int n5, int* l, int* n, int* used) {
+  *used = 0;
+  if (tol < kEmpiricalTolMin) return false;
+  float x[kMlpIn];
+  mlp_features(op, norms, t, p, tol, x);
+  float y[kMlpOut];
+  mlp_predict_host(w, x, y);
+  if (!std::isfinite(y[0]) || !std::isfinite(y[1])) {
+    *used = 3;
+    return false;
+  }
+  const int lp = std::min(60, std::max(0, (int)std::lround(y[0] * 8.0f)));
+  // the norm at which the bound covers the measured errors, as a fraction
+  // 10^y1 of ||tA||: never above the norm itself, never below a tenth of it
+  const double ratio = std::pow(10.0, std::min(0.0, std::max(-1.0, (double)y[1])));
+  const int nq = quadnodes(tol, p, std::ldexp(alpha * ratio, -lp), 1.0, PHIQ_RULE_GAUSS);
+  if (nq < 0) {
+    *used = 3;
+    return false;
+  }
+  if ((double)(nq + 1 + lp * p) > 1.5 * (double)((n5 + 1) + l5 * p)) {
+    *used = 3;
+    return false;
+  }
+  *l = lp;
+  *n = nq;
+  *used = 4;
   return true;
 }
 

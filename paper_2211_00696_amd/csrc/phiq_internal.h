@@ -73,6 +73,14 @@ void mlp_predict_host(const float* w, const float x[kMlpIn], float y[kMlpOut]);
 // (1 = certified mode).
 bool mlp_choose(const float* w, const phiq_kron_op* op, const double* norms, double t, int p, double tol,
                 double slack, double alpha, int l5, int n5, int* l, int* n, int* used);
+// Empirical mode (PHIQ_SEL_MLP_EMPIRICAL): the network's outputs are l / 8 and
+// log10 of the norm ratio at which the a priori bound covered the measured
+// errors of the method's own sweeps; n is Algorithm quadnodes at that norm
+// and scaling l.  Declines (used 0) below kEmpiricalTolMin, the smallest
+// tolerance the sweeps covered; used 4 = the network's pair, 3 = rejected.
+constexpr double kEmpiricalTolMin = 1e-10;
+bool mlp_choose_empirical(const float* w, const phiq_kron_op* op, const double* norms, double t, int p,
+                          double tol, double alpha, int l5, int n5, int* l, int* n, int* used);
 // Grow-only device arena of batched calls, held by the handle.
 phiq_status batch_arena(phiq_handle h, size_t bytes, void** dev);
 // Pinned staging slot of at least `bytes`, and its upload (a copy kernel

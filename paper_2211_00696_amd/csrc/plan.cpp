@@ -80,11 +80,14 @@ phiq_status select_params(const phiq_kron_op* op, double t, int p, double tol, c
                : 4;
     } else {
       setup_quadrature(tol, p, alpha, 1.0, opt.rule, opt.c1, opt.c2, op->dim, &l, &nq, &cost);
-      if (opt.selector == PHIQ_SEL_MLP && mlp && opt.rule == PHIQ_RULE_GAUSS && opt.m <= 0 && alpha > 1e-12 &&
+      if (opt.selector != PHIQ_SEL_PAPER && mlp && opt.rule == PHIQ_RULE_GAUSS && opt.m <= 0 && alpha > 1e-12 &&
           l >= 0 && nq >= 0) {
         int lm = l, nm = nq, used = 0;
-        if (mlp_choose(mlp, op, norms, t, p, tol, std::pow(10.0, opt.selector_slack), alpha, l, nq, &lm, &nm,
-                       &used)) {
+        const bool ok = (opt.selector == PHIQ_SEL_MLP_EMPIRICAL)
+                            ? mlp_choose_empirical(mlp, op, norms, t, p, tol, alpha, l, nq, &lm, &nm, &used)
+                            : mlp_choose(mlp, op, norms, t, p, tol, std::pow(10.0, opt.selector_slack), alpha, l,
+                                         nq, &lm, &nm, &used);
+        if (ok) {
           l = lm;
           nq = nm;
         }
@@ -277,7 +280,8 @@ phiq_status plan_build(phiq_handle h, const phiq_kron_op* op, double t, int p, d
   if (!std::isfinite(opt.c1) || !std::isfinite(opt.c2) || !std::isfinite(opt.alpha)) return PHIQ_ERR_NONFINITE;
   if (opt.c1 < 0 || opt.c2 < 0 || opt.l < -1 || opt.l > 60 || opt.m < -1 || opt.m == 0 || opt.m > 4096 ||
       opt.cc_max_doublings < 1 || opt.cc_max_doublings > 10 || !(opt.selector_slack >= 0.0) ||
-      opt.selector_slack > 12.0 || opt.rhs_per_launch < 0)
+      opt.selector_slack > 12.0 || opt.rhs_per_launch < 0 || opt.selector < PHIQ_SEL_PAPER ||
+      opt.selector > PHIQ_SEL_MLP_EMPIRICAL)
     return PHIQ_ERR_INVALID_ARG;
 
   PlanParams pp;

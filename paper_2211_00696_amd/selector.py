@@ -18,20 +18,26 @@ steps runs p chains and a GEMM one after another.  This module
 and the planner uses the network with the bound as the judge (Algorithm 5
 is the fallback): phiq_options.selector = PHIQ_SEL_MLP.
 
-Two label modes:
-  * certified (`train`): the labels are pairs the a priori bound accepts, so
-    the network can only reorder (l, m) by cost, never use fewer nodes or
-    squarings than the bound asks for;
-  * empirical (`train-empirical`): `sweep_errors` runs the method itself over
-    forced (l, m) on generated problems and measures the error of each
-    against the method's own result at tol 1e-14; the label is the (l, m)
-    with the least modelled time whose measured error is at most tol / 2.
-    The bound still judges the network's choice, with a slack (decades)
-    calibrated as the largest bound excess the labels needed
-    (phiq_options.selector_slack).
+Two modes:
+  * certified (`train`, PHIQ_SEL_MLP): the labels are pairs the a priori
+    bound accepts, so the network can only reorder (l, m) by cost, never use
+    fewer nodes or squarings than the bound asks for; the bound judges its
+    choice;
+  * empirical (`sweep-errors`, `train-empirical`, PHIQ_SEL_MLP_EMPIRICAL):
+    `sweep_errors` runs the method itself over forced (l, m) on generated
+    problems and measures each error against the method's own result at tol
+    1e-14.  Per problem, `norm_ratio` finds the smallest rho for which the
+    bound at the norm rho ||tA|| covers twice every measured error above
+    1e-10 (for these advection-diffusion operators rho is 0.45..0.8: the
+    infinity norm overstates the reach of the spectrum).  The network learns
+    log10 rho and the scaling l with the least modelled time; the planner
+    takes m from Algorithm quadnodes at rho ||tA|| / 2^l, so a wrong l costs
+    time, not accuracy, and a margin (the largest shortfall of the predicted
+    log10 rho on the training samples) is added to the output's bias.
 
 Features (8): log10 of t ||A^d||_inf for axes 0..2 (-3 for an absent axis),
-n / 256, dim, p, log10 t, log10 tol.  Outputs (2): l / 8 and m / 16.
+n / 256, dim, p, log10 t, log10 tol.  Outputs (2): l / 8 and m / 16
+(certified) or l / 8 and log10 rho (empirical).
 """
 from __future__ import annotations
 
@@ -270,7 +276,7 @@ def draw_sweep_problem(rng, sizes=(32, 48, 64, 96, 128, 192, 256), dims=(3,)):
     return dict(dim=dim, n=n, p=p, t=t, a=[float(x) for x in a], b=[float(x) for x in b])
 
 
-def sweep_errors(h, count=240, seed=11, emin=1e-12, mmax=20, log=print):
+def sweep_errors(h, count=240, seed=11, emin=1e-12, mmax=20, dims=(3,), log=print):
     """For `count` generated problems: the relative error (max over phi_k of the inf-norm error over
     the inf-norm of the reference) of the FP64 phi-action at forced (l, m), against the method's own
     result at tol 1e-14.  For each l from the paper's choice at tol 1e-10 down to six below it, m
@@ -280,7 +286,7 @@ def sweep_errors(h, count=240, seed=11, emin=1e-12, mmax=20, log=print):
     rng = np.random.default_rng(seed)
     recs = []
     for i in range(count):
-        pr = draw_sweep_problem(rng)
+        pr = draw_sweep_problem(rng, dims=dims)
         n, dim, p, t = pr["n"], pr["dim"], pr["p"], pr["t"]
         mats = [I.adv_diff_1d(n, pr["a"][d], pr["b"][d]) for d in range(dim)]
         v = torch.from_numpy(rng.standard_normal(n ** dim)).cuda()
@@ -297,61 +303,135 @@ def sweep_errors(h, count=240, seed=11, emin=1e-12, mmax=20, log=print):
                 if e < emin:
                     break
         recs.append(dict(pr, alpha=rr["alpha"], norms=[t * infnorm(mm) for mm in mats], points=pts))
-        log("problem %d: n=%d p=%d alpha=%.3g, %d points" % (i, n, p, rr["alpha"], len(pts)))
+        log("problem %d: dim=%d n=%d p=%d alpha=%.3g, %d points" % (i, dim, n, p, rr["alpha"], len(pts)))
     return recs
 
 
-def empirical_label(T, rec, tol, safety=0.5):
-    """(l, m, bound excess in decades) with the least modelled time whose measured error <= safety tol;
-    None if no swept pair qualifies."""
+EMPIRICAL_TOL_MIN = 1e-10  # the planner's empirical mode declines below this tolerance
+
+
+def _covered(rec, lr, floor, safety):
+    a = rec["alpha"] * 10.0 ** lr
+    for l, m, e, _ in rec["points"]:
+        if e <= safety * floor or m < 2:
+            continue
+        if phiq.log_quaderr(m - 1, rec["p"], math.ldexp(a, -l)) / math.log(10.0) < math.log10(e / safety):
+            return False
+    return True
+
+
+def norm_ratio(rec, floor=EMPIRICAL_TOL_MIN, safety=0.5, iters=30):
+    """log10 rho of a sweep record: the smallest rho in [0.1, 1] for which the a priori bound (Thm 3.2)
+    at the norm rho ||tA|| covers twice (1 / safety) every measured error above safety * floor; then
+    Algorithm quadnodes at rho ||tA|| picks, for any tol >= floor, only pairs whose measured error is
+    at most safety * tol.  None if even rho = 1 does not cover them."""
+    lo, hi = -1.0, 0.0
+    if not _covered(rec, hi, floor, safety):
+        return None
+    if _covered(rec, lo, floor, safety):
+        return lo
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        if _covered(rec, mid, floor, safety):
+            hi = mid
+        else:
+            lo = mid
+    return hi
+
+
+def swept_error(rec, l, m):
+    """Measured error of the pair (l, m) in a sweep record: the pair itself, else the error at the
+    largest swept m below m at that l (the error falls as m grows, and a sweep of one l stops once
+    it is below the floor); None if that l was not swept or nothing at or below m was."""
     best = None
-    for l, m, e, lb in rec["points"]:
-        if e <= safety * tol:
-            c = T(rec["n"], rec["p"], l, m)
-            if best is None or c < best[0]:
-                best = (c, l, m, lb - math.log10(tol))
-    return None if best is None else best[1:]
+    for pl, pm, e, _ in rec["points"]:
+        if pl == l and pm <= m and (best is None or pm > best[0]):
+            best = (pm, e)
+    return None if best is None else best[1]
 
 
 def empirical_dataset(recs, costs, tols_per_problem=8, seed=5):
+    """Samples (features, (l / 8, log10 rho)): rho the record's norm ratio, l the scaling with the least
+    modelled time when m is Algorithm quadnodes at rho ||tA|| (tols log-uniform in [1e-10, 1e-6])."""
     T = cost_fn(costs)
     rng = np.random.default_rng(seed)
     X, Y, meta = [], [], []
     for rec in recs:
+        lr = norm_ratio(rec)
+        if lr is None:
+            continue
         for _ in range(tols_per_problem):
-            tol = float(math.exp(rng.uniform(math.log(1e-10), math.log(1e-6))))
-            lab = empirical_label(T, rec, tol)
-            if lab is None:
-                continue
-            l, m, excess = lab
+            tol = float(math.exp(rng.uniform(math.log(EMPIRICAL_TOL_MIN), math.log(1e-6))))
+            l, m = label(T, rec["n"], rec["p"], rec["alpha"] * 10.0 ** lr, tol)
             X.append(features(rec["norms"], rec["n"], rec["dim"], rec["p"], rec["t"], tol))
-            Y.append((l / L_SCALE, m / M_SCALE))
-            meta.append(dict(n=rec["n"], p=rec["p"], alpha=rec["alpha"], tol=tol, l=l, m=m, excess=excess))
+            Y.append((l / L_SCALE, lr))
+            meta.append(dict(n=rec["n"], dim=rec["dim"], p=rec["p"], alpha=rec["alpha"], tol=tol, l=l, m=m, log10_rho=lr))
     return np.array(X), np.array(Y), meta
 
 
 def train_empirical(h, recs, seed=3, steps=6000, lr=3e-3, costs=None, log=print):
-    """Fit the network on the empirical labels; the judge's slack is the largest bound excess the
-    labels needed (rounded up to a tenth of a decade)."""
+    """Fit the network on the empirical samples (GPU), then add to the bias of the log10 rho output
+    the largest amount by which it fell short of a training target (rounded up to 0.005 decades), so
+    that on every training sample the planner uses a norm at least the one that covered the errors."""
     costs = load_costs() if costs is None else costs
     X, Y, meta = empirical_dataset(recs, costs)
     w0 = init_weights(seed + 1000)
     w, hist = h.mlp_train(X, Y, w0, steps, lr)
     pred = predict(w, X)
+    short = float(np.max(Y[:, 1] - pred[:, 1]))
+    margin = math.ceil(max(0.0, short) / 0.005) * 0.005
+    w = np.asarray(w, dtype=np.float32).copy()
+    w[-1] += np.float32(margin)
     l_err = np.abs(np.rint(pred[:, 0] * L_SCALE) - np.rint(Y[:, 0] * L_SCALE))
-    m_err = np.abs(np.rint(pred[:, 1] * M_SCALE) - np.rint(Y[:, 1] * M_SCALE))
-    slack = math.ceil(10.0 * max(0.0, max(r["excess"] for r in meta))) / 10.0
-    stats = dict(mode="empirical", samples=len(meta), problems=len(recs), steps=steps, lr=lr,
+    stats = dict(mode="empirical", samples=len(meta), problems=len(recs),
+                 problems_used=len({(m["n"], m["p"], m["alpha"]) for m in meta}), steps=steps, lr=lr,
                  loss_first=float(hist[0]), loss_last=float(hist[-1]), l_exact=float(np.mean(l_err == 0)),
-                 m_within_1=float(np.mean(m_err <= 1)), slack=slack)
+                 rho_rms=float(np.sqrt(np.mean((pred[:, 1] - Y[:, 1]) ** 2))), margin=margin,
+                 log10_rho_range=[float(Y[:, 1].min()), float(Y[:, 1].max())])
     log(json.dumps(stats))
     return w, hist, stats
 
 
+def empirical_pair(w, rec, tol):
+    """Host copy of the planner's empirical mode (phiq_options.selector = PHIQ_SEL_MLP_EMPIRICAL):
+    (l, m, used), used 4 = the network's pair, 3 = rejected, 0 = tol below the mode's range (both
+    then Algorithm setup_quadrature's pair)."""
+    p, alpha = rec["p"], rec["alpha"]
+    l5, n5, _ = phiq.setup_quadrature(tol, p, alpha)
+    if tol < EMPIRICAL_TOL_MIN:
+        return l5, n5 + 1, 0
+    y = predict(w, features(rec["norms"], rec["n"], rec["dim"], p, rec["t"], tol)[None])[0]
+    lp = min(60, max(0, int(math.floor(y[0] * L_SCALE + 0.5))))
+    ratio = 10.0 ** min(0.0, max(-1.0, float(y[1])))
+    nq = phiq.quadnodes(tol, p, math.ldexp(alpha * ratio, -lp))
+    if nq + 1 + lp * p > 1.5 * ((n5 + 1) + l5 * p):
+        return l5, n5 + 1, 3
+    return lp, nq + 1, 4
+
+
+def holdout(recs, w, costs, tols=(1e-10, 1e-9, 1e-8, 1e-7, 1e-6)):
+    """For held-out sweep records: the empirical pair at each tol, its measured error (looked up in
+    the record) and Algorithm setup_quadrature's, and the modelled time ratio of the two."""
+    T = cost_fn(costs)
+    rows = []
+    for rec in recs:
+        for tol in tols:
+            l, m, used = empirical_pair(w, rec, tol)
+            l5, n5, _ = phiq.setup_quadrature(tol, rec["p"], rec["alpha"])
+            rows.append(dict(dim=rec["dim"], n=rec["n"], p=rec["p"], alpha=rec["alpha"], tol=tol, l=l, m=m,
+                             used=used, err=swept_error(rec, l, m), l5=l5, m5=n5 + 1,
+                             err5=swept_error(rec, l5, n5 + 1),
+                             speedup=T(rec["n"], rec["p"], l5, n5 + 1) / T(rec["n"], rec["p"], l, m)))
+    known = [r for r in rows if r["err"] is not None]
+    summ = dict(cases=len(rows), known=len(known), met=sum(r["err"] <= r["tol"] for r in known),
+                worst_over_tol=max([r["err"] / r["tol"] for r in known] or [0.0]),
+                median_modelled_speedup=float(np.median([r["speedup"] for r in rows])))
+    return rows, summ
+
+
 def load_empirical(path=WEIGHTS_EMPIRICAL):
-    """(weights, slack) of the empirical-mode network."""
-    d = json.load(open(path))
-    return np.array(d["weights"], dtype=np.float32), float(d["stats"]["slack"])
+    """Weights of the empirical-mode network (its margin already in the last bias)."""
+    return np.array(json.load(open(path))["weights"], dtype=np.float32)
 
 
 def _device_handle():
@@ -366,25 +446,29 @@ def _device_handle():
 def main(argv):
     if len(argv) >= 1 and argv[0] == "train":
         out = argv[1] if len(argv) > 1 else WEIGHTS
+        costs = load_costs(argv[2]) if len(argv) > 2 else None
         h = phiq.Handle(0)
-        w, hist, stats = train(h, log=lambda s: print(s, flush=True))
+        w, hist, stats = train(h, costs=costs, log=lambda s: print(s, flush=True))
         h.close()
         save_weights(w, stats, out)
         return 0
     if len(argv) >= 1 and argv[0] == "sweep-errors":
         out = argv[1] if len(argv) > 1 else ERRORS
         count = int(argv[2]) if len(argv) > 2 else 240
+        seed = int(argv[3]) if len(argv) > 3 else 11
+        dims = tuple(int(x) for x in argv[4].split(",")) if len(argv) > 4 else (3,)
         h = _device_handle()
-        recs = sweep_errors(h, count=count, log=lambda s: print(s, flush=True))
+        recs = sweep_errors(h, count=count, seed=seed, dims=dims, log=lambda s: print(s, flush=True))
         h.close()
         json.dump({"records": recs}, open(out, "w"))
         return 0
     if len(argv) >= 1 and argv[0] == "train-empirical":
-        src = argv[1] if len(argv) > 1 else ERRORS
+        srcs = (argv[1] if len(argv) > 1 else ERRORS).split(",")
         out = argv[2] if len(argv) > 2 else WEIGHTS_EMPIRICAL
-        recs = json.load(open(src))["records"]
+        recs = [r for src in srcs for r in json.load(open(src))["records"]]
+        costs = load_costs(argv[3]) if len(argv) > 3 else None
         h = _device_handle()
-        w, hist, stats = train_empirical(h, recs, log=lambda s: print(s, flush=True))
+        w, hist, stats = train_empirical(h, recs, costs=costs, log=lambda s: print(s, flush=True))
         h.close()
         save_weights(w, stats, out)
         return 0
