@@ -75,6 +75,13 @@ typedef enum {
                          /* 128} (else PHIQ_ERR_UNSUPPORTED).               */
 } phiq_precision;
 
+/* Scaling l of adaptive Clenshaw-Curtis (Algorithm 2). */
+typedef enum {
+  PHIQ_CC_SCALING_REALIZED = 0, /* least predicted cost of the nodes Algorithm 2 */
+                                /* will run (phiq_cc_scaling)                    */
+  PHIQ_CC_SCALING_PAPER = 1     /* Algorithm setup_quadrature with the CC bound  */
+} phiq_cc_scaling_mode;
+
 /* Choice of (l, m) for the Gauss rule. */
 typedef enum { PHIQ_SEL_PAPER = 0, PHIQ_SEL_MLP = 1, PHIQ_SEL_MLP_EMPIRICAL = 2 } phiq_selector;
 
@@ -151,6 +158,9 @@ typedef struct {
                             /* b_1..b_p set and p <= 4, all node chains and phi_0's */
                             /* chain share one launch per mode product and one node */
                             /* sum: the same sums, another rounding order)          */
+  int cc_scaling;           /* PHIQ_RULE_CC: PHIQ_CC_SCALING_REALIZED (default) or  */
+                            /* PHIQ_CC_SCALING_PAPER; the accuracy is the stopping  */
+                            /* test's either way                                    */
 } phiq_options;
 
 /* Device bytes of intermediates a group of right-hand sides may take when
@@ -214,6 +224,19 @@ phiq_status phiq_norm_bound(const phiq_kron_op* op, double t, double* alpha);
 phiq_status phiq_setup_quadrature(double eps, int p, double alpha, double beta,
                                   phiq_rule rule, double c1, double c2, int d,
                                   int* l, int* n, double* cost);
+
+/* Scaling of adaptive Clenshaw-Curtis by the cost of the nodes Algorithm 2
+ * will run (the plan's default, PHIQ_CC_SCALING_REALIZED).  Algorithm 2
+ * stops about one nested level (7, 13, 25, ... points) after the first rule
+ * that is accurate.  For each l in [l_paper - 1, l_paper + 3] (l_paper from
+ * Algorithm setup_quadrature with the CC bound), the first accurate level is
+ * predicted with the CC bound of Thm 3.2 at alpha / 4, and the l with the
+ * least C = c1 d n + c2 (n + l p) over the nodes run (n + 1) is returned;
+ * ties keep the smaller l.  The a priori bound at alpha, not alpha / 4, is
+ * what certifies the paper's l; here accuracy comes from Algorithm 2's
+ * stopping test. */
+phiq_status phiq_cc_scaling(double eps, int p, double alpha, double c1, double c2, int d,
+                            int max_doublings, int* l);
 
 /* log of Algorithm quaderr: max over q = 1..p of the Thm 3.2 bound for the
  * (n+1)-node rule at norm alpha and vector factor beta.  n may be real. */

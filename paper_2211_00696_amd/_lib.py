@@ -24,6 +24,7 @@ PROFILE_CLASSES = ["ttm_store", "ttm_accum", "ttm_square", "gemm", "taylor", "sc
                    "ttm_slab"]
 PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2, "int8": 3}
 SELECTOR = {"paper": 0, "mlp": 1, "mlp-empirical": 2}
+CC_SCALING = {"realized": 0, "paper": 1}
 
 # Every symbol include/phiq.h declares.
 EXPORTS = [
@@ -31,6 +32,7 @@ EXPORTS = [
     "phiq_options_default",
     "phiq_norm_bound",
     "phiq_setup_quadrature",
+    "phiq_cc_scaling",
     "phiq_log_quaderr",
     "phiq_quadnodes",
     "phiq_quadrature_rule",
@@ -83,6 +85,7 @@ class Options(ctypes.Structure):
         ("selector_slack", c_double),
         ("batch_persistent", c_int),
         ("rhs_per_launch", c_int),
+        ("cc_scaling", c_int),
     ]
 
 
@@ -149,6 +152,7 @@ def load():
         "phiq_status_string": (c_char_p, [c_int]),
         "phiq_options_default": (c_int, [P(Options)]),
         "phiq_norm_bound": (c_int, [P(KronOp), c_double, P(c_double)]),
+        "phiq_cc_scaling": (c_int, [c_double, c_int, c_double, c_double, c_double, c_int, c_int, POINTER(c_int)]),
         "phiq_setup_quadrature": (c_int, [c_double, c_int, c_double, c_double, c_int, c_double, c_double, c_int,
                                           P(c_int), P(c_int), P(c_double)]),
         "phiq_log_quaderr": (c_int, [c_double, c_int, c_double, c_double, c_int, P(c_double)]),

@@ -21,6 +21,9 @@ double log_quaderr(double n, int p, double alpha, double beta, phiq_rule rule);
 int quadnodes(double eps, int p, double alpha, double beta, phiq_rule rule);
 void setup_quadrature(double eps, int p, double alpha, double beta, phiq_rule rule, double c1,
                       double c2, int d, int* l, int* n, double* cost);
+// Adaptive Clenshaw-Curtis: the scaling with the least predicted cost of
+// Algorithm 2's realized node count (l_paper: Algorithm setup_quadrature's).
+int cc_scaling(double eps, int p, double alpha, double c1, double c2, int d, int max_doublings, int l_paper);
 void gauss_legendre(int m, double* theta, double* w);
 void clenshaw_curtis(int m, double* theta, double* w);
 

@@ -94,6 +94,10 @@ phiq_status select_params(const phiq_kron_op* op, double t, int p, double tol, c
         pp->selector = used;
       }
       if (opt.m > 0 && opt.rule == PHIQ_RULE_GAUSS) nq = opt.m - 1;
+      if (opt.rule == PHIQ_RULE_CC && opt.cc_scaling == PHIQ_CC_SCALING_REALIZED && l >= 0 && alpha > 1e-12) {
+        l = cc_scaling(tol, p, alpha, opt.c1, opt.c2, op->dim, opt.cc_max_doublings, l);
+        nq = quadnodes(tol, p, std::ldexp(alpha, -l), 1.0, PHIQ_RULE_CC);
+      }
     }
     if (l < 0 || nq < 0) return PHIQ_ERR_NOT_CONVERGED;
     pp->log10_bound = (alpha > 1e-12 && nq >= 1)
@@ -281,7 +285,8 @@ phiq_status plan_build(phiq_handle h, const phiq_kron_op* op, double t, int p, d
   if (opt.c1 < 0 || opt.c2 < 0 || opt.l < -1 || opt.l > 60 || opt.m < -1 || opt.m == 0 || opt.m > 4096 ||
       opt.cc_max_doublings < 1 || opt.cc_max_doublings > 10 || !(opt.selector_slack >= 0.0) ||
       opt.selector_slack > 12.0 || opt.rhs_per_launch < 0 || opt.selector < PHIQ_SEL_PAPER ||
-      opt.selector > PHIQ_SEL_MLP_EMPIRICAL)
+      opt.selector > PHIQ_SEL_MLP_EMPIRICAL || opt.cc_scaling < PHIQ_CC_SCALING_REALIZED ||
+      opt.cc_scaling > PHIQ_CC_SCALING_PAPER)
     return PHIQ_ERR_INVALID_ARG;
 
   PlanParams pp;

@@ -227,6 +227,43 @@ void setup_quadrature(double eps, int p, double alpha, double beta, phiq_rule ru
   *l_out = bl; *n_out = bn; *cost_out = bc;
 }
 
+// Scaling for adaptive Clenshaw-Curtis by the cost Algorithm 2 will have.
+// Algorithm 2 runs the nested rules of S_j = 6 2^j + 1 points (j = 0, 1, ...)
+// and stops at the first level j >= 1 whose change from level j - 1 is below
+// eps, i.e. about one level after the first rule that is accurate: it pays
+// S_{j+1} node chains for a rule with S_j nodes.  Whether a 7-point rule is
+// accurate or needs 13 decides between 13 and 25 node chains, which costs
+// more than a squaring step (p chains).  The prediction uses the CC bound of
+// Thm 3.2 at a quarter of the norm: on 3D advection-diffusion draws the bound
+// at the full norm predicted the level Algorithm 2 stopped at in 28 of 64
+// cases (always one level too late), at a quarter in 60 of 64 (the rest one
+// level too late).  A wrong prediction costs time only: the stopping test
+// still decides.  l ranges over [l_paper - 1, l_paper + 3] with the paper's
+// cost C = c1 d n + c2 (n + l p), n + 1 = the nodes run; ties keep the
+// smaller l; if no l is predicted to converge within max_doublings, the
+// paper's l.
+int cc_scaling(double eps, int p, double alpha, double c1, double c2, int d, int max_doublings, int l_paper) {
+  constexpr double kNormFraction = 0.25;
+  if (p == 0 || alpha <= kAlphaZero || l_paper < 0) return l_paper;
+  const double leps = std::log(eps);
+  int bl = l_paper;
+  double bc = std::numeric_limits<double>::infinity();
+  for (int l = std::max(0, l_paper - 1); l <= l_paper + 3; ++l) {
+    const double al = std::ldexp(alpha * kNormFraction, -l);
+    int acc = -1;  // first level whose rule the bound accepts
+    for (int j = 0; j < max_doublings && acc < 0; ++j)
+      if (log_quaderr(6 * (1 << j), p, al, 1.0, PHIQ_RULE_CC) <= leps) acc = j;
+    if (acc < 0) continue;
+    const int n = 6 << std::max(1, acc + 1);  // the stopping level's rule has n + 1 points
+    const double C = c1 * d * n + c2 * (n + (double)l * p);
+    if (C < bc) {
+      bc = C;
+      bl = l;
+    }
+  }
+  return bl;
+}
+
 // ---------------------------------------------------------------------------
 // Quadrature rules on [0, 1]
 // ---------------------------------------------------------------------------
@@ -314,6 +351,22 @@ phiq_status phiq_setup_quadrature(double eps, int p, double alpha, double beta, 
     return PHIQ_ERR_INVALID_ARG;
   phiq::setup_quadrature(eps, p, alpha, beta, rule, c1, c2, d, l, n, cost);
   if (*l < 0) return PHIQ_ERR_NOT_CONVERGED;
+  return PHIQ_OK;
+}
+
+phiq_status phiq_cc_scaling(double eps, int p, double alpha, double c1, double c2, int d, int max_doublings,
+                            int* l) {
+  if (!l) return PHIQ_ERR_INVALID_ARG;
+  if (!std::isfinite(eps) || !std::isfinite(alpha) || !std::isfinite(c1) || !std::isfinite(c2))
+    return PHIQ_ERR_NONFINITE;
+  if (eps <= 0 || p < 0 || p > PHIQ_MAX_P || alpha < 0 || c1 < 0 || c2 < 0 || d < 1 || max_doublings < 1 ||
+      max_doublings > 10)
+    return PHIQ_ERR_INVALID_ARG;
+  int lp = 0, n = 0;
+  double cost = 0.0;
+  phiq::setup_quadrature(eps, p, alpha, 1.0, PHIQ_RULE_CC, c1, c2, d, &lp, &n, &cost);
+  if (lp < 0) return PHIQ_ERR_NOT_CONVERGED;
+  *l = phiq::cc_scaling(eps, p, alpha, c1, c2, d, max_doublings, lp);
   return PHIQ_OK;
 }
 

@@ -74,7 +74,7 @@ class _Op:
 
 def options(rule="gauss", precision="fp64", l=None, m=None, alpha=None, c1=None, c2=None,
             cc_max_doublings=None, workspace_cap=None, use_graphs=None, selector=None, slab_products=None,
-            accept_floor=None, selector_slack=None, batch_persistent=None, rhs_per_launch=None):
+            accept_floor=None, selector_slack=None, batch_persistent=None, rhs_per_launch=None, cc_scaling=None):
     lib = L.load()
     o = L.Options()
     _check(lib.phiq_options_default(byref(o)), "phiq_options_default")
@@ -102,6 +102,8 @@ def options(rule="gauss", precision="fp64", l=None, m=None, alpha=None, c1=None,
         o.slab_products = int(slab_products)
     if accept_floor is not None:
         o.accept_floor = int(bool(accept_floor))
+    if cc_scaling is not None:
+        o.cc_scaling = L.CC_SCALING[cc_scaling]
     if selector_slack is not None:
         o.selector_slack = float(selector_slack)
     if batch_persistent is not None:
@@ -129,6 +131,16 @@ def setup_quadrature(eps, p, alpha, beta=1.0, rule="gauss", c1=0.0, c2=1.0, d=3)
     _check(lib.phiq_setup_quadrature(float(eps), int(p), float(alpha), float(beta), L.RULE[rule], float(c1),
                                      float(c2), int(d), byref(l), byref(n), byref(c)), "phiq_setup_quadrature")
     return l.value, n.value, c.value
+
+
+def cc_scaling(eps, p, alpha, c1=0.0, c2=1.0, d=3, max_doublings=6):
+    """Scaling l of adaptive Clenshaw-Curtis by the predicted cost of the nodes Algorithm 2 runs
+    (phiq_cc_scaling; the plans' default)."""
+    lib = L.load()
+    l = c_int()
+    _check(lib.phiq_cc_scaling(float(eps), int(p), float(alpha), float(c1), float(c2), int(d), int(max_doublings),
+                               byref(l)), "phiq_cc_scaling")
+    return l.value
 
 
 def log_quaderr(n, p, alpha, beta=1.0, rule="gauss"):

@@ -191,12 +191,34 @@ def test_plan_reuse_and_multiple_rhs(h):
 
 
 def test_cc_reports_adaptive_doublings(h):
+    """With the paper's scaling (Algorithm setup_quadrature, CC bound) the run is the oracle's:
+    the same l, node count and doublings."""
     pr = I.problem("laplace2d", n=16)
-    out, rep = h.action(pr["mats"], pr["t"], 3, dev(pr["v"]), tol=1e-10, rule="cc")
+    out, rep = h.action(pr["mats"], pr["t"], 3, dev(pr["v"]), tol=1e-10, rule="cc", cc_scaling="paper")
     ref, info = Q.phiquadmv(pr["mats"], pr["t"], pr["v"], 3, eps=1e-10, rule="cc", beta=1.0, return_info=True)
     assert (rep["l"], rep["m"], rep["cc_doublings"]) == (info["l"], info["m"], info["doublings"])
     assert rep["cc_err"] <= 1e-10
     assert max(rel_per_k(host(out), ref)) < 1e-10
+
+
+@pytest.mark.parametrize("seed,n,tol", [(1, 48, 1e-8), (4, 40, 1e-8), (0, 32, 1e-10), (7, 24, 1e-6)])
+def test_cc_default_scaling_vs_oracle(h, seed, n, tol):
+    """The default scaling of adaptive CC (phiq_cc_scaling: the l with the least predicted cost of the
+    nodes Algorithm 2 runs): the plan's l is the exported rule's, the result meets tol against the
+    oracle's quadrature (eps 1e-14), and the nodes run plus l p chains exceed the paper's by at most
+    one squaring step (the prediction errs toward a larger l)."""
+    from paper_2211_00696_amd import phiq
+
+    pr = I.problem("advdiff3d", seed=seed, n=n)
+    v = dev(pr["v"])
+    out, rep = h.action(pr["mats"], pr["t"], 3, v, tol=tol, rule="cc")
+    _, rp = h.action(pr["mats"], pr["t"], 3, v, tol=tol, rule="cc", cc_scaling="paper")
+    assert rep["l"] == phiq.cc_scaling(tol, 3, rep["alpha"])
+    ref = Q.phiquadmv(pr["mats"], pr["t"], pr["v"], 3, eps=1e-14, beta=1.0)
+    errs = rel_per_k(host(out), ref)
+    print("cc scaling", seed, n, tol, (rep["l"], rep["m"]), "paper", (rp["l"], rp["m"]), errs, flush=True)
+    assert max(errs) < tol
+    assert rep["m"] + 3 * rep["l"] <= rp["m"] + 3 * rp["l"] + 3
 
 
 def test_cc_cap_reports_not_converged(h):
