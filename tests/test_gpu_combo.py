@@ -159,8 +159,9 @@ def test_combo_errors(h):
     with pytest.raises(phiq.PhiqError, match="UNSUPPORTED"):
         plan.execute_combo([b32, b32, b32])
     plan.close()
-    # the adaptive rule's doubling cap reached before the tolerance
-    plan = h.plan(mats, 0.01, 2, tol=1e-14, rule="cc", cc_max_doublings=1)
+    # the adaptive rule's doubling cap reached before the tolerance (at the paper's scaling: the
+    # default picks an l whose 7-point rule converges within the cap)
+    plan = h.plan(mats, 0.01, 2, tol=1e-14, rule="cc", cc_max_doublings=1, cc_scaling="paper")
     with pytest.raises(phiq.PhiqError, match="NOT_CONVERGED"):
         plan.execute_combo([b, b, b])
     plan.close()
