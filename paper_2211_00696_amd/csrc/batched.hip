@@ -354,29 +354,67 @@ __device__ __forceinline__ void run_any(const BatchArgs& a, const BatchStage& S,
   }
 }
 
+// Tiles are taken kPersistChunk at a time (one atomic on the shared counter
+// per chunk instead of per tile: that counter and the completion counters
+// are the kernel's only contended addresses), and a chunk's tiles run in
+// order.  A workgroup waits only when the stage changes (tiles of one stage
+// do not read each other), and publishes the completions it holds for a
+// group when the group changes, before any wait and at the end of its chunk,
+// so it never waits while holding completions that another workgroup may
+// need: the workgroup with the smallest unfinished tile still finds its
+// inputs published or about to be.
+constexpr int kPersistChunk = 32;
+
 __global__ __launch_bounds__(512) void batch_persistent_kernel(BatchArgs a, BatchPersistArgs p) {
   __shared__ double smem[2 * (BW::BM + BW::BN) * BW::LDK];
-  __shared__ long long sh_tile;
+  __shared__ long long sh_base;
   __shared__ int sh_ok;
   int lo = 0;
+  int ready = -1;      // stage whose inputs were found complete
+  int pend_sig = -1;   // thread 0: group of the completions not yet published
+  unsigned pend = 0;   // thread 0: their number
+  auto publish = [&]() {
+    if (threadIdx.x == 0 && pend) {
+      __hip_atomic_fetch_add(p.done + pend_sig, pend, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      pend = 0;
+    }
+  };
   for (;;) {
     if (threadIdx.x == 0)
-      sh_tile = (long long)__hip_atomic_fetch_add(&p.ctl->next, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      sh_base = (long long)__hip_atomic_fetch_add(&p.ctl->next, (unsigned long long)kPersistChunk, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
-    const long long g = sh_tile;
-    if (g >= p.total) break;
-    int hi = p.nstages - 1;  // last stage with tile0 <= g; g only grows, so lo only grows
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (a.st[mid].tile0 <= g) lo = mid; else hi = mid - 1;
+    const long long base = sh_base;  // thread 0 rewrites it only after the barrier that ends a tile
+    if (base >= p.total) break;
+    const long long end = std::min(base + (long long)kPersistChunk, p.total);
+    bool ok = true;
+    for (long long g = base; g < end; ++g) {
+      int hi = p.nstages - 1;  // last stage with tile0 <= g; g only grows, so lo only grows
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.st[mid].tile0 <= g) lo = mid; else hi = mid - 1;
+      }
+      const BatchStage& S = a.st[lo];
+      if (lo != ready) {
+        publish();
+        if (threadIdx.x == 0) sh_ok = wait_group(p, S.wait0, S.need0) && wait_group(p, S.wait1, S.need1);
+        __syncthreads();
+        if (!sh_ok) {
+          ok = false;
+          break;
+        }
+        ready = lo;
+      }
+      run_any(a, S, (int)(g - S.tile0), smem);
+      __syncthreads();  // every thread's results are written (and smem is free)
+      if (threadIdx.x == 0) {
+        if (pend_sig != S.signal) publish();
+        pend_sig = S.signal;
+        ++pend;
+      }
     }
-    const BatchStage& S = a.st[lo];
-    if (threadIdx.x == 0) sh_ok = wait_group(p, S.wait0, S.need0) && wait_group(p, S.wait1, S.need1);
-    __syncthreads();
-    if (!sh_ok) break;
-    run_any(a, S, (int)(g - S.tile0), smem);
-    __syncthreads();  // every thread's results are written (and smem is free)
-    if (threadIdx.x == 0) __hip_atomic_fetch_add(p.done + S.signal, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    publish();
+    if (!ok) break;
   }
 }
 
