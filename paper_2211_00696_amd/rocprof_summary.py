@@ -183,8 +183,8 @@ def mfma(csv_path, bench_json):
     alg = bench["roofline"]["flops_per_launch"]
     out = {"launches": len(sl), "kernel_digest": bench["kernel_digest"], "workload": bench["config"]["workload"],
            "algorithmic_flops_per_launch": alg}
-    for ty in ("F64", "F32", "BF16"):
-        # each MOPS count stands for 512 floating-point operations of that type
+    for ty in ("F64", "F32", "BF16", "I8"):
+        # each MOPS count stands for 512 operations of that type (int8: multiply-adds counted as two)
         cn = "SQ_INSTS_VALU_MFMA_MOPS_" + ty
         if any(cn in c for _, c in sl):
             mops = sum(c.get(cn, 0.0) for _, c in sl) / len(sl)
