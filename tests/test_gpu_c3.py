@@ -6,7 +6,9 @@ numpy, its own selection at eps = 1e-14, beta = 1), itself pinned against
 the augmented-matrix definition in the CPU tests.  The error measure is the
 relative inf-norm error per phi_k (Section 4).
 
-  * FP64 mode products at tol 1e-8: every phi_k within 1e-8.
+  * FP64 mode products at tol 1e-8: every phi_k within 1e-8, with the
+    Gauss rule and with adaptive Clenshaw-Curtis (Algorithm 2) at its
+    default scaling (phiq_cc_scaling).
   * FP32 and split-bf16 products at tol 1e-6 and 1e-10: both tolerances lie
     below or near the forms' rounding floors, so the floor is accepted
     explicitly and asserted instead (PHIQ_FLOOR_FP32 = 2e-6,
@@ -49,19 +51,20 @@ def test_c3_every_form_vs_oracle(h, seed):
     ref = Q.phiquadmv(pr["mats"], pr["t"], pr["v"], 3, eps=1e-14, beta=1.0)
     v = torch.from_numpy(pr["v"]).cuda()
     out = torch.empty((4, v.numel()), dtype=torch.float64, device="cuda")
-    cases = [("fp64", 1e-8), ("fp32", 1e-6), ("fp32", 1e-10), ("bf16x3", 1e-6), ("bf16x3", 1e-10)]
+    cases = [("fp64", 1e-8, "gauss"), ("fp64", 1e-8, "cc"), ("fp32", 1e-6, "gauss"), ("fp32", 1e-10, "gauss"),
+             ("bf16x3", 1e-6, "gauss"), ("bf16x3", 1e-10, "gauss")]
     rows, bad = [], []
-    for prec, tol in cases:
-        print(f"C3 seed {seed} {prec} tol {tol:g}", flush=True)
-        kw = {} if prec == "fp64" else dict(accept_floor=True)
+    for prec, tol, rule in cases:
+        print(f"C3 seed {seed} {prec} {rule} tol {tol:g}", flush=True)
+        kw = dict(rule=rule) if prec == "fp64" else dict(accept_floor=True)
         _, rep = h.action(pr["mats"], pr["t"], 3, v, tol=tol, precision=prec, out=out, **kw)
         torch.cuda.synchronize()
         errs = rel_per_k(out.cpu().numpy(), ref)
         bar = tol if prec == "fp64" else FLOOR[prec]
-        rows.append((prec, tol, rep["l"], rep["m"], errs, rep["tol_met"]))
+        rows.append((prec, rule, tol, rep["l"], rep["m"], errs, rep["tol_met"]))
         print(f"  l={rep['l']} m={rep['m']} alpha={rep['alpha']:.1f} tol_met={rep['tol_met']} "
               "rel err phi_0..3 = " + " ".join(f"{e:.2e}" for e in errs), flush=True)
         if max(errs) >= bar:
-            bad.append((prec, tol, errs, bar))
+            bad.append((prec, rule, tol, errs, bar))
         assert rep["tol_met"] == (1 if tol >= (FLOOR.get(prec, 0.0)) else 0)
     assert not bad, bad
