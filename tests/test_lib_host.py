@@ -150,4 +150,7 @@ def test_options_struct_matches_the_header():
     assert (o.rule, o.precision, o.l, o.m) == (L.RULE["gauss"], L.PRECISION["fp64"], -1, -1)
     assert (o.alpha, o.c1, o.c2, o.cc_max_doublings, o.workspace_cap) == (-1.0, 0.0, 1.0, 6, 0)
     assert (o.use_graphs, o.selector, o.slab_products) == (0, 0, 0)
+    assert (o.accept_floor, o.selector_slack, o.batch_persistent, o.rhs_per_launch, o.cc_scaling) == (0, 0.0, 0, 0, 0)
     assert phiq.options(slab_products=2).slab_products == 2
+    assert phiq.options(cc_scaling="paper").cc_scaling == 1 and phiq.options(cc_scaling="realized").cc_scaling == 0
+    assert phiq.options(selector="mlp-empirical").selector == 2
