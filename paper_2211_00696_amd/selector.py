@@ -28,7 +28,7 @@ Two modes:
     problems and measures each error against the method's own result at tol
     1e-14.  Per problem, `norm_ratio` finds the smallest rho for which the
     bound at the norm rho ||tA|| covers twice every measured error above
-    1e-10 (for these advection-diffusion operators rho is 0.45..0.8: the
+    1e-10 (for these advection-diffusion operators rho is 0.39..0.75: the
     infinity norm overstates the reach of the spectrum).  The network learns
     log10 rho and the scaling l with the least modelled time; the planner
     takes m from Algorithm quadnodes at rho ||tA|| / 2^l, so a wrong l costs
