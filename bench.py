@@ -416,6 +416,24 @@ def time_form(h, pr, prec, v, out, steps, warmup, ms_fp64, **opts):
     }, out.cpu().numpy()
 
 
+def grouped_ms(call, calls, groups=3):
+    """Per-call milliseconds of `call`, run back to back in `groups` groups of calls / groups calls
+    (at least one): the median group, so that a one-off stall of the host or of one call shifts one
+    group only; the groups' values are returned too."""
+    import torch
+
+    per = max(1, calls // groups)
+    gms = []
+    for _ in range(groups):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(per):
+            call()
+        torch.cuda.synchronize()
+        gms.append((time.perf_counter() - t0) * 1e3 / per)
+    return float(np.median(gms)), gms
+
+
 def seeds_median(h, args, count=16, n=128, steps=10, warmup=2):
     """The 3D n = 128 problem (FP64, the rule of the headline) over coefficient draws 0..count-1:
     grid points per second of full phi-actions per draw and their median."""
@@ -428,20 +446,17 @@ def seeds_median(h, args, count=16, n=128, steps=10, warmup=2):
         pr = inputs.problem("advdiff3d", seed=seed, n=n)
         v = torch.from_numpy(pr["v"]).cuda()
         out = torch.empty((pr["p"] + 1, v.numel()), dtype=torch.float64, device="cuda")
-        for _ in range(warmup):
-            h.action(pr["mats"], pr["t"], pr["p"], v, tol=pr["tol"], out=out, rule=args.rule)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
         rep = None
-        for _ in range(steps):
+        for _ in range(warmup):
             _, rep = h.action(pr["mats"], pr["t"], pr["p"], v, tol=pr["tol"], out=out, rule=args.rule)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / steps
+        ms, gms = grouped_ms(lambda: h.action(pr["mats"], pr["t"], pr["p"], v, tol=pr["tol"], out=out,
+                                              rule=args.rule), steps)
         rows.append({"seed": seed, "alpha": rep["alpha"], "l": rep["l"], "m": rep["m"],
-                     "grid_pts_per_s": v.numel() / (ms * 1e-3)})
+                     "grid_pts_per_s": v.numel() / (ms * 1e-3), "group_ms": gms})
         del v, out
     return {"workload": "3D advection-diffusion n=%d (N=%d), coefficient draws 0..%d, FP64, %s, tol 1e-8, "
-                        "%d calls per draw" % (n, n ** 3, count - 1, args.rule, steps),
+                        "the median of three groups of %d back-to-back calls per draw"
+                        % (n, n ** 3, count - 1, args.rule, max(1, steps // 3)),
             "median_grid_pts_per_s": float(np.median([r["grid_pts_per_s"] for r in rows])),
             "per_seed": rows}
 
@@ -781,13 +796,10 @@ def bench_seeds(args, rank):
         for rule in ("gauss", "cc"):
             for _ in range(2):
                 _, rep = h.action(pr["mats"], pr["t"], pr["p"], v, tol=pr["tol"], out=out, rule=rule)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(args.steps):
-                h.action(pr["mats"], pr["t"], pr["p"], v, tol=pr["tol"], out=out, rule=rule)
-            torch.cuda.synchronize()
-            ms = (time.perf_counter() - t0) * 1e3 / args.steps
-            row[rule] = dict(ms=ms, grid_pts_per_s=N / (ms * 1e-3), l=rep["l"], m=rep["m"], alpha=rep["alpha"])
+            ms, gms = grouped_ms(lambda: h.action(pr["mats"], pr["t"], pr["p"], v, tol=pr["tol"], out=out, rule=rule),
+                                 args.steps)
+            row[rule] = dict(ms=ms, grid_pts_per_s=N / (ms * 1e-3), l=rep["l"], m=rep["m"], alpha=rep["alpha"],
+                             group_ms=gms)
         rows.append(row)
         print(json.dumps(row), file=sys.stderr, flush=True)
     h.close()
