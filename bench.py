@@ -434,7 +434,7 @@ def grouped_ms(call, calls, groups=3):
     return float(np.median(gms)), gms
 
 
-def seeds_median(h, args, count=16, n=128, steps=10, warmup=2):
+def seeds_median(h, args, count=16, n=128, steps=30, warmup=2):
     """The 3D n = 128 problem (FP64, the rule of the headline) over coefficient draws 0..count-1:
     grid points per second of full phi-actions per draw and their median."""
     import torch
