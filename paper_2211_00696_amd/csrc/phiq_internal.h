@@ -42,7 +42,7 @@ inline double precision_floor(phiq_precision prec) {
 }
 double sum_infnorms(const phiq_kron_op* op);
 
-// Host-chosen parameters of one phi-action (Algorithm 5 with beta = 1).
+// Host-chosen parameters of one phi-action (Algorithm setup_quadrature with beta = 1).
 struct PlanParams {
   double alpha;        // ||tA||_inf estimate
   double log10_bound;  // a priori quadrature bound at (l, m)
@@ -70,7 +70,7 @@ int launch_mlp_adam(float* w, const float* g, float* m, float* v, float lr, floa
                     void* stream);
 // Host forward pass (the same arithmetic as the kernel) and the planner's
 // use of it: features, prediction, the bound as judge.  Returns false when
-// the prediction is rejected (the caller keeps Algorithm 5's choice).
+// the prediction is rejected (the caller keeps Algorithm setup_quadrature's choice).
 void mlp_predict_host(const float* w, const float x[kMlpIn], float y[kMlpOut]);
 // slack: factor by which the bound at the network's choice may exceed tol
 // (1 = certified mode).

@@ -15,8 +15,8 @@ steps runs p chains and a GEMM one after another.  This module
      least fitted T;
   3. trains the 8 -> 64 -> 64 -> 2 network on those labels (`train`, GPU,
      through the library's own forward / backward / Adam kernels);
-and the planner uses the network with the bound as the judge (Algorithm 5
-is the fallback): phiq_options.selector = PHIQ_SEL_MLP.
+and the planner uses the network with the bound as the judge (Algorithm
+setup_quadrature is the fallback): phiq_options.selector = PHIQ_SEL_MLP.
 
 Two modes:
   * certified (`train`, PHIQ_SEL_MLP): the labels are pairs the a priori
