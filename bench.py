@@ -41,7 +41,7 @@ HBM_PEAK_GBS = 8000.0
 
 def kernel_source_digest():
     h = hashlib.sha256()
-    for f in ("kernels.hip", "tile_fp64.h", "kernels_lowp.hip", "kernels_bf16r.hip", "kernels_f64r.hip", "kernels_i8.hip", "kernels_slab.hip"):
+    for f in ("kernels.hip", "tile_fp64.h", "kernels_lowp.hip", "kernels_bf16r.hip", "kernels_f32r.hip", "kernels_f64r.hip", "kernels_i8.hip", "kernels_slab.hip"):
         p = os.path.join(ROOT, "paper_2211_00696_amd", "csrc", f)
         if os.path.exists(p):
             h.update(open(p, "rb").read())

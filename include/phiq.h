@@ -536,10 +536,12 @@ phiq_status phiq_profile_enable(phiq_handle h, int on);
 
 /* Tile shape of the mode products for every later launch of one kind:
  * FP64 kind 0 (plain mode product), 1 (with the node sum), 2 (with the
- * squaring combination); split bf16 kind 3 (plain) and 4 (squaring), where
- * cfg 0 is the general tile kernel and cfg >= 1 the kernels that keep the
- * 1D factor resident in LDS (n_d in {64, 128, 256}; other shapes always take
- * the general kernel); FP64 with the factor resident in LDS, kind 5
+ * squaring combination); split bf16 and FP32 kind 3 (plain) and 4
+ * (squaring), where cfg 0 is the general tile kernel and cfg >= 1 the
+ * kernels that keep the 1D factor resident in LDS (split bf16: n_d in {64,
+ * 128, 256}, store cfg 1..5, squaring 1..2; FP32: n_d in {128, 256}, store
+ * cfg 1..3, squaring 1..2 with FP32 input; other shapes and cfgs take the
+ * general kernel); FP64 with the factor resident in LDS, kind 5
  * (plain), 6 (squaring), 7 (node sum): cfg 0 declines (the tile kernels of
  * kinds 0..2 run), cfg >= 1 forces a resident shape for the launches it
  * takes (n_d in {64, 128, 256}, FP64 in and out), -1 = default (kinds 5

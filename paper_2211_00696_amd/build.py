@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libphiq.so")
 
-SOURCES = ["kernels.hip", "kernels_slab.hip", "kernels_lowp.hip", "kernels_bf16r.hip", "kernels_f64r.hip", "kernels_i8.hip", "batched.hip", "etd.hip", "exprk.hip", "mlp.hip", "noalloc.hip", "planner.cpp", "plan.cpp", "launch.cpp", "gauss.cpp", "int8.cpp", "combo.cpp", "cc.cpp", "autotune.cpp", "api.cpp", "batched.cpp",
+SOURCES = ["kernels.hip", "kernels_slab.hip", "kernels_lowp.hip", "kernels_bf16r.hip", "kernels_f32r.hip", "kernels_f64r.hip", "kernels_i8.hip", "batched.hip", "etd.hip", "exprk.hip", "mlp.hip", "noalloc.hip", "planner.cpp", "plan.cpp", "launch.cpp", "gauss.cpp", "int8.cpp", "combo.cpp", "cc.cpp", "autotune.cpp", "api.cpp", "batched.cpp",
            "etd.cpp", "exprk.cpp", "mlp.cpp"]
 
 HIPCC_FLAGS = [

@@ -618,6 +618,10 @@ int launch_ttm_store(const TtmArgs& a, phiq_precision prec, void* stream, int cf
     const int r = launch_ttm_store_bf16r(a, stream, cfg);
     if (r != hipErrorNotSupported) return r;
   }
+  if (prec == PHIQ_PREC_FP32 && !a.nn) {
+    const int r = launch_ttm_store_f32r(a, stream, cfg);
+    if (r != hipErrorNotSupported) return r;
+  }
   if (prec != PHIQ_PREC_FP64) return a.nn ? hipErrorInvalidValue : launch_ttm_store_lowp(a, prec, stream);
   hipStream_t st = (hipStream_t)stream;
   if (a.nn) return launch_nn(0, a, st);
@@ -682,6 +686,10 @@ int launch_ttm_square(const TtmArgs& a, phiq_precision prec, void* stream, int c
   if (two_index(a) && prec != PHIQ_PREC_FP64) return hipErrorInvalidValue;
   if (prec == PHIQ_PREC_BF16X3 && !a.nn) {
     const int r = launch_ttm_square_bf16r(a, stream, cfg);
+    if (r != hipErrorNotSupported) return r;
+  }
+  if (prec == PHIQ_PREC_FP32 && !a.nn) {
+    const int r = launch_ttm_square_f32r(a, stream, cfg);
     if (r != hipErrorNotSupported) return r;
   }
   if (prec != PHIQ_PREC_FP64) return a.nn ? hipErrorInvalidValue : launch_ttm_square_lowp(a, prec, stream);

@@ -81,9 +81,9 @@ phiq_status L_ttm(phiq_handle h, int cls, const TtmArgs& a0, phiq_precision prec
   }
   ttm_work(a, cls, &fl, &by);
   const int kind = kind_of(cls);
-  // split bf16: kinds 3 / 4 force the resident-factor shapes of the plain
-  // and the squaring products (0 = the general tile kernel)
-  int cfg = (prec == PHIQ_PREC_BF16X3 && kind != 1) ? h->force_cfg[kind == 0 ? 3 : 4]
+  // split bf16 and FP32: kinds 3 / 4 force the resident-factor shapes of the
+  // plain and the squaring products (0 = the general tile kernel)
+  int cfg = (prec != PHIQ_PREC_FP64 && kind != 1) ? h->force_cfg[kind == 0 ? 3 : 4]
             : (prec != PHIQ_PREC_FP64) ? -1
                                        : (h->force_cfg[kind] >= 0 ? h->force_cfg[kind] : tuned_cfg(h, kind, a));
   if (prec == PHIQ_PREC_FP64 && cfg < 0) cfg = fallback_cfg(kind, a);

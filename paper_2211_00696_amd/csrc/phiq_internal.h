@@ -256,6 +256,11 @@ int launch_ttm_accum_f64r(const TtmArgs& a, void* stream, int cfg);
 int f64r_num_configs();
 int f64r_accum_num_configs();
 int launch_ttm_square_bf16r(const TtmArgs& a, void* stream, int cfg);
+// FP32 with the factor resident in LDS (kernels_f32r.hip): n in {128, 256},
+// the FP32 twin of E; store cfg 1..3, squaring cfg 1..2 (FP32 X), 0
+// declines, -1 = default; hipErrorNotSupported when declined
+int launch_ttm_store_f32r(const TtmArgs& a, void* stream, int cfg);
+int launch_ttm_square_f32r(const TtmArgs& a, void* stream, int cfg);
 
 // Products along axes 2 and 1 of nbatch tensors n0 x kSlabN x kSlabN in one
 // pass (kernels_slab.hip), layout unchanged:

@@ -48,10 +48,10 @@ from collections import defaultdict
 
 CLASS_RE = {
     # int8 digit products: modes 0 (digits out) and 1 (FP64 out) count as stores, 2 as squaring
-    "ttm_store": re.compile(r"(^|::)ttm_(lp_|bf16r_|f64r_)?store_kernel|(^|::)i8_product_kernel<\d+, \d+, [01]>"),
+    "ttm_store": re.compile(r"(^|::)ttm_(lp_|bf16r_|f32r_|f64r_)?store_kernel|(^|::)i8_product_kernel<\d+, \d+, [01]>"),
     "ttm_slab": re.compile(r"(^|::)slab2_kernel"),
-    "ttm_accum": re.compile(r"(^|::)ttm_(lp_)?accum_kernel"),
-    "ttm_square": re.compile(r"(^|::)ttm_(lp_|bf16r_|f64r_)?square(_all)?_kernel|(^|::)i8_product_kernel<\d+, \d+, 2>"),
+    "ttm_accum": re.compile(r"(^|::)ttm_(lp_|f64r_)?accum_kernel"),
+    "ttm_square": re.compile(r"(^|::)ttm_(lp_|bf16r_|f32r_|f64r_)?square(_all)?_kernel|(^|::)i8_product_kernel<\d+, \d+, 2>"),
     "slice": re.compile(r"(^|::)i8_(slice_rows|absmax|slice_tensor)_kernel"),
     "gemm": re.compile(r"(^|::)gemm_(jobs|panel)_kernel"),
     "taylor": re.compile(r"(^|::)taylor_jobs_kernel"),

@@ -169,3 +169,55 @@ def test_bf16_resident_phi_action_vs_oracle(h, n64, store_cfg, square_cfg):
     errs = [rel(o[k], ref[k]) for k in range(4)]
     print("bf16 resident", store_cfg, square_cfg, rep["l"], rep["m"], errs, flush=True)
     assert max(errs) < TOL_PHI["bf16x3"], errs
+
+
+# --------------------------------------------------------------------------
+# FP32 with the 1D factor resident in LDS (n_d in {128, 256}): every store
+# shape forced (cfg 0 = the general kernel), FP64 and FP32 inputs and
+# outputs along the chain, ragged column tails, axes of other sizes on the
+# general kernel in the same chain
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
+@pytest.mark.parametrize("sizes", [(256, 256), (128, 128, 128), (256, 72), (128, 200), (128, 256, 40),
+                                   (64, 128, 33)])
+def test_f32_resident_store_shapes(h, sizes, cfg):
+    rng = np.random.default_rng(7 * sum(sizes) + cfg)
+    F = [np.abs(rng.standard_normal((n, n))) / n + np.eye(n) for n in sizes]
+    N = int(np.prod(sizes))
+    x = rng.standard_normal((3, N))
+    print("fp32 resident store", sizes, "cfg", cfg, flush=True)
+    h.tile_config(3, cfg)
+    try:
+        y = host(h.kron_apply([dev(f) for f in F], dev(x), precision="fp32"))
+    finally:
+        h.tile_config(3, -1)
+    errs = [rel(y[r], X.apply_kron(F, x[r], list(sizes))) for r in range(3)]
+    print(errs, flush=True)
+    assert max(errs) < TOL_KRON["fp32"], errs
+
+
+@pytest.fixture(scope="module")
+def n128():
+    pr = I.problem("advdiff3d", seed=0)
+    return pr, Q.phiquadmv(pr["mats"], pr["t"], pr["v"], 3, eps=1e-14, beta=1.0)
+
+
+@pytest.mark.parametrize("store_cfg,square_cfg", [(1, 1), (2, 2), (3, 1), (0, 0), (-1, -1)])
+def test_f32_resident_phi_action_n128_vs_oracle(h, n128, store_cfg, square_cfg):
+    """3D n = 128 phi-action (phi_0..phi_3) in FP32 with the resident product
+    and squaring kernels forced on every launch they take (the node chains'
+    products with one factor per node, phi_0's chain, the squaring step's p
+    orders per block), against the oracle."""
+    pr, ref = n128
+    h.tile_config(3, store_cfg)
+    h.tile_config(4, square_cfg)
+    try:
+        out, rep = h.action(pr["mats"], pr["t"], 3, dev(pr["v"]), tol=1e-10, precision="fp32", accept_floor=True)
+        o = host(out)
+    finally:
+        h.tile_config(3, -1)
+        h.tile_config(4, -1)
+    errs = [rel(o[k], ref[k]) for k in range(4)]
+    print("fp32 resident", store_cfg, square_cfg, rep["l"], rep["m"], errs, flush=True)
+    assert rep["l"] >= 1
+    assert max(errs) < TOL_PHI["fp32"], errs
