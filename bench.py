@@ -53,15 +53,23 @@ def traffic_key(kernel, precision):
     return kernel if precision == "fp64" else "%s@%s" % (kernel, precision)
 
 
-def load_traffic(kernel, digest, precision="fp64"):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if current."""
+def headline_workload(n, N, seed, rule, precision):
+    """config.workload of the advection-diffusion phi-action lines."""
+    return ("3D advection-diffusion Kronecker sum, n=%d per axis (N=%d), a_d log-U[0.1,10], "
+            "b_d U[0,50], t=1e-3, phi_0..phi_3, v~N(0,1) seed %d, %s, tol 1e-8, %s mode products"
+            % (n, N, seed, "Gauss-Legendre" if rule == "gauss" else "adaptive Clenshaw-Curtis", precision.upper()))
+
+
+def load_traffic(kernel, digest, precision, workload):
+    """HBM bytes per launch from committed rocprofv3 counter runs: only from an entry taken on the same
+    kernel sources and the same workload (sizes, coefficients, rule, precision form)."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
     try:
         d = json.load(open(p))
         ent = d.get(traffic_key(kernel, precision))
-        if not ent or ent.get("kernel_digest") != digest:
+        if not ent or ent.get("kernel_digest") != digest or ent.get("workload") != workload:
             return None
         return float(ent["bytes_per_launch"])
     except Exception:
@@ -267,7 +275,9 @@ def main():
     # its matrix roofline; its bound is the FP32 intermediates' HBM traffic
     bound = "hbm" if args.precision == "bf16x3" else "mfma"
     digest = kernel_source_digest()
-    traffic = load_traffic(dom, digest, args.precision)
+    workload = headline_workload(args.n, N, args.seed, args.rule, args.precision)
+    # the counter runs were taken without the slab products
+    traffic = None if args.slab_products else load_traffic(dom, digest, args.precision, workload)
     ttm_total = {k: v for k, v in all_stats.items() if k.startswith("ttm")}
     ttm_ms = sum(s["ms"] for s in ttm_total.values())
     ttm_tflops = sum(s["flops"] for s in ttm_total.values()) / (ttm_ms * 1e-3) / 1e12
@@ -287,10 +297,7 @@ def main():
         "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3", "int8": "i8"}[args.precision],
         "data": "synthetic",
         "config": {
-            "workload": "3D advection-diffusion Kronecker sum, n=%d per axis (N=%d), a_d log-U[0.1,10], "
-                        "b_d U[0,50], t=1e-3, phi_0..phi_3, v~N(0,1) seed %d, %s, tol 1e-8, %s mode products"
-                        % (args.n, N, args.seed, "Gauss-Legendre" if args.rule == "gauss" else "adaptive Clenshaw-Curtis",
-                           args.precision.upper()),
+            "workload": workload,
             "n": args.n, "N": N, "p": p, "t": pr["t"], "tol": pr["tol"], "rule": args.rule,
             "precision": args.precision, "seed": args.seed, "slab_products": args.slab_products,
             "coefficients": pr["coef"],
@@ -331,7 +338,8 @@ def main():
     if args.precision == "fp64" and not args.no_forms:
         result["forms"] = {}
         for prec in ("fp32", "bf16x3"):
-            f, o = time_form(h, pr, prec, v, out, max(5, args.steps // 2), args.warmup, ms_per_step,
+            wl = None if args.slab_products else headline_workload(args.n, N, args.seed, args.rule, prec)
+            f, o = time_form(h, pr, prec, v, out, max(5, args.steps // 2), args.warmup, ms_per_step, wl,
                              rule=args.rule, slab_products=args.slab_products)
             result["forms"][prec] = f
             form_outs[prec] = o
@@ -362,11 +370,12 @@ def rel_errs(o, ref):
     return [float(np.max(np.abs(o[k] - ref[k])) / np.max(np.abs(ref[k]))) for k in range(ref.shape[0])]
 
 
-def time_form(h, pr, prec, v, out, steps, warmup, ms_fp64, **opts):
+def time_form(h, pr, prec, v, out, steps, warmup, ms_fp64, workload, **opts):
     """One precision form of the mode products on the headline problem: the same tol (so the same
     (l, m) as FP64; the form's rounding floor is accepted, its error is reported), wall time per
     full phi-action over `steps` unprofiled calls, then one call with every launch timed by HIP
-    events for the dominant class's roofline (split bf16: HBM bytes; FP32: the FP32 matrix peak)."""
+    events for the dominant class's roofline (split bf16: HBM bytes; FP32: the FP32 matrix peak).
+    workload names the counter runs the traffic entry must come from (None: no traffic)."""
     import torch
 
     p = pr["p"]
@@ -398,7 +407,7 @@ def time_form(h, pr, prec, v, out, steps, warmup, ms_fp64, **opts):
     else:
         roof = {"kernel": dom, "bound": "mfma", "achieved": tflops, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
                 "frac": tflops / PEAK_TFLOPS[prec], "gbs": gbs}
-    roof["traffic"] = load_traffic(dom, kernel_source_digest(), prec)
+    roof["traffic"] = load_traffic(dom, kernel_source_digest(), prec, workload) if workload else None
     roof.update({"avg_launch_ms": avg_ms, "launches": st["launches"], "fp64_equivalent_tflops": tflops,
                  "algorithmic_bytes_per_launch": st["bytes"] / st["launches"]})
     torch.cuda.synchronize()

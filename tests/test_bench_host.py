@@ -42,3 +42,21 @@ def test_kernel_digest_covers_every_kernel_source():
     for f in kernels:
         assert '"%s"' % f in src, f
     assert len(bench.kernel_source_digest()) == 16
+
+
+def test_traffic_entries_are_current_and_tied_to_their_workload():
+    """The bench line uses a committed counter entry only for the kernel sources and the workload it
+    was measured on: the headline problem at n = 256 (FP64, FP32, split bf16) and the int8 digits at
+    n = 128, not the same form at another size or rule, nor after a kernel source changed."""
+    d = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
+    where = {"ttm_store": (256, "fp64"), "ttm_store@fp32": (256, "fp32"), "ttm_store@bf16x3": (256, "bf16x3"),
+             "ttm_store@int8": (128, "int8")}
+    assert set(d) == set(where)
+    for key, (n, prec) in where.items():
+        digest = d[key]["kernel_digest"]
+        wl = bench.headline_workload(n, n ** 3, 0, "gauss", prec)
+        assert bench.load_traffic("ttm_store", digest, prec, wl) == d[key]["bytes_per_launch"]
+        other = 128 if n == 256 else 256
+        assert bench.load_traffic("ttm_store", digest, prec, bench.headline_workload(other, other ** 3, 0, "gauss", prec)) is None
+        assert bench.load_traffic("ttm_store", digest, prec, bench.headline_workload(n, n ** 3, 0, "cc", prec)) is None
+        assert bench.load_traffic("ttm_store", "0" * 16, prec, wl) is None
