@@ -22,7 +22,10 @@ Bars:
 * FP32 and split-bf16 plans (mode products in that form, node sums and
   squaring in FP64): against the FP64 combination with the same (l, m)
   below 3e-6 and 3e-5, the forms' error floors (8e-7 and 9e-6 per
-  phi-action, measured) with room for the p terms.
+  phi-action, measured) with room for the p terms; FP32 also at 3D n = 128
+  with the resident-factor kernels forced on the plain and the squaring
+  products (the last squaring step with an order offset and an accumulating
+  store), below 3e-6.
 """
 import numpy as np
 import pytest
@@ -314,3 +317,35 @@ def test_combo_fused_matches_separate_launches(h, sizes, p, b0, t):
     print("rel diff", e, "mode-product launches fused / separate", counts, flush=True)
     assert e < 1e-13, e
     assert counts[0] < counts[1], counts
+
+
+@pytest.fixture(scope="module")
+def combo128(h):
+    pr = I.problem("advdiff3d", seed=0, n=128)
+    N = 128 ** 3
+    rng = np.random.default_rng(23)
+    bs = [rng.standard_normal(N) for _ in range(4)]
+    ref, rep = run(h, pr["mats"], pr["t"], bs, tol=1e-8)
+    return pr, bs, ref, rep
+
+
+@pytest.mark.parametrize("store_cfg,square_cfg", [(1, 1), (3, 2), (0, 1), (0, 0), (-1, -1)])
+def test_combo_fp32_n128_resident_vs_fp64(h, combo128, store_cfg, square_cfg):
+    """FP32 linear combination at 3D n = 128 (p = 3, every b_j set) with the
+    FP32 resident-factor kernels forced (kind 3: plain products, kind 4: the
+    squaring steps, including the last one with an order offset and the
+    accumulating store) or the general kernel (cfg 0), against the FP64
+    combination with the same (l, m), below the FP32 bar 3e-6."""
+    pr, bs, ref, rep = combo128
+    h.tile_config(3, store_cfg)
+    h.tile_config(4, square_cfg)
+    try:
+        got, _ = run(h, pr["mats"], pr["t"], bs, tol=1e-8, precision="fp32", accept_floor=True, l=rep["l"],
+                     m=rep["m"])
+    finally:
+        h.tile_config(3, -1)
+        h.tile_config(4, -1)
+    e = rel(got, ref)
+    print("fp32 combo n=128", store_cfg, square_cfg, rep["l"], rep["m"], e, flush=True)
+    assert rep["l"] >= 1
+    assert e < 3e-6, e
