@@ -459,8 +459,8 @@ class Handle:
 
     def tile_config(self, kind, cfg=-1):
         """Force tile shape cfg for every launch of a kind: FP64 0 (store), 1 (node sum), 2 (squaring);
-        split bf16 3 (store) and 4 (squaring), where 0 is the general tile kernel and 1.. keep the
-        1D factor resident in LDS; FP64 with the factor resident in LDS 5 (store), 6 (squaring),
+        split bf16 and FP32 3 (store) and 4 (squaring), where 0 is the general tile kernel and 1.. keep
+        the 1D factor resident in LDS (FP32: n_d in {128, 256}, store 1..3, squaring 1..2); FP64 with the factor resident in LDS 5 (store), 6 (squaring),
         7 (node sum), where 0 declines to the tile kernels.  -1 restores the tuned/default choice.
         Returns the number of shapes of the kind."""
         lib = L.load()
